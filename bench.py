@@ -1,0 +1,200 @@
+"""Benchmark: direct N-body force + Hermite block steps on one MI355X.
+
+Workload (default): an equal-mass Plummer sphere of N = 2^20 particles in N-body units,
+softening 1/256, eta = 0.01, largest step 1/8.  One bench step is the whole hot path once:
+nb_init (full force of all N i-particles against all N j-particles, initial time steps, first
+block selection) followed by 8 block steps (schedule, predict, block force, correct).  The
+initial positions and velocities are restored (a device copy) at the start of every step so that
+every step does the same work.
+
+Output: one JSON line.  `value` is force interactions per second over the timed steps
+(N^2 for the full force plus N times each block's size, the self slot counted as the paper's
+operation count does); `roofline` reports the single-precision force kernel against the
+MI355X FP32 vector peak at 60 flop per interaction; `cpu_baseline` is the FP64 CPU oracle
+timed on a sample of i-particles of the same workload on this host.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_TFLOPS = 157.3      # MI355X dense FP32 vector peak (published)
+PEAK_FP64_TFLOPS = 78.6
+FLOP_PER_INTERACTION = 60     # acc + jerk + potential, the paper's operation count
+METRIC = "interactions/s (acc+jerk) & %FP32 VALU peak at N=2^20; FP32 vs double-single"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rms_rel(got, ref):
+    import numpy as np
+    got, ref = np.asarray(got), np.asarray(ref)
+    if got.ndim == 1:
+        return float(np.sqrt(np.mean(((got - ref) / ref) ** 2)))
+    return float(np.sqrt(np.mean(np.sum((got - ref) ** 2, 1) / np.sum(ref ** 2, 1))))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--block-steps", type=int, default=8)
+    ap.add_argument("--eta", type=float, default=0.01)
+    ap.add_argument("--eps", type=float, default=1.0 / 256)
+    ap.add_argument("--lmin", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "ds", "fp64"])
+    ap.add_argument("--variants", default="ds,fp64",
+                    help="other interaction arithmetics to time once (comma list, or 'none')")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_astro_ph_0702058_amd import nbody
+    from paper_astro_ph_0702058_amd.plummer import plummer, sample_indices
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n = args.n
+    log(f"[bench] generating Plummer N={n} seed={args.seed}")
+    x, v, m = plummer(n, args.seed)
+    st = nbody.DeviceState(x, v, m)
+    x0, v0 = st.x.clone(), st.v.clone()
+    stream = torch.cuda.current_stream()
+
+    ctx = nbody.Context(n, args.eps, lmin=args.lmin, lmax=26, precision=args.precision)
+    ctx.nb_bind(st)
+
+    def step():
+        st.x.copy_(x0)
+        st.v.copy_(v0)
+        ctx.nb_init(args.eta)
+        ctx.nb_step(args.eta, args.block_steps, use_graph=False)
+
+    log(f"[bench] warmup {args.warmup} step(s)")
+    for _ in range(args.warmup):
+        step()
+    ctx.nb_sync()
+
+    interactions = 0
+    ctx.nb_profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    c = ctx.nb_read_control()
+    force_ms, launches = ctx.nb_profile_read()
+    ctx.nb_profile(False)
+    # interactions: per step N^2 (initial full force) + N * (block sizes); the block sizes of
+    # every timed step are identical (same initial state), read from the last one
+    per_step = n * n + n * c.n_active_sum
+    interactions = per_step * args.steps
+    elapsed = t1 - t0
+    value = interactions / elapsed
+    log(f"[bench] {args.steps} steps in {elapsed:.3f} s; block steps sum n_act={c.n_active_sum}"
+        f" ({c.n_active_sum / max(c.n_steps, 1):.0f} per block)")
+
+    achieved = FLOP_PER_INTERACTION * interactions / (force_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": f"force_kernel<{args.precision}>",
+                "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+                "launches": launches, "avg_launch_ms": round(force_ms / max(launches, 1), 4),
+                "flop_per_interaction": FLOP_PER_INTERACTION}
+
+    # accuracy of the timed arithmetic on a sample of i, against the oracle (untimed)
+    st.x.copy_(x0); st.v.copy_(v0)
+    ctx.nb_init(args.eta)
+    ctx.nb_sync()
+    g = st.numpy()
+    ctx.close()
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32", "ds": "f32x2",
+                                                           "fp64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"Plummer N={n} (eps={args.eps:g}, eta={args.eta:g}, "
+                               f"dt_max=2^-{args.lmin}): full force + {args.block_steps} "
+                               "block steps",
+                   "n": n, "eps": args.eps, "eta": args.eta, "block_steps": args.block_steps,
+                   "precision": args.precision, "interactions_per_step": per_step},
+        "roofline": roofline,
+        "context": {"paper_8800gtx_interactions_per_s": 1.23e9,
+                    "paper_grape6af_interactions_per_s": 2.16e9},
+    }
+
+    # other interaction arithmetics: one full force each, timed with the same events
+    variants = {}
+    for prec in [p for p in args.variants.split(",") if p and p != "none"]:
+        if prec == args.precision:
+            continue
+        st.x.copy_(x0); st.v.copy_(v0)
+        cv = nbody.Context(n, args.eps, lmin=args.lmin, precision=prec)
+        cv.nb_bind(st)
+        cv.nb_profile(True)
+        cv.nb_init(args.eta)
+        ms, nl = cv.nb_profile_read()
+        cv.nb_sync()
+        gv = st.numpy()
+        cv.close()
+        rate = n * n / (ms * 1e-3)
+        variants[prec] = {"interactions_per_s": rate, "full_force_ms": ms, "gv": gv}
+        log(f"[bench] {prec}: full force {ms:.1f} ms, {rate:.3e} interactions/s")
+
+    # CPU oracle on a bounded sample of i (all j): timing and the accuracy reference
+    if not args.no_cpu_baseline:
+        import oracle
+        cal = sample_indices(n, 8, 101)
+        t_a = time.perf_counter(); oracle.force(x, v, m, args.eps ** 2, idx=cal); t_b = time.perf_counter()
+        per_i = (t_b - t_a) / 8
+        count = int(max(16, min(16384, args.cpu_seconds / max(per_i, 1e-9))))
+        idx = sample_indices(n, count, 7)
+        log(f"[bench] oracle on {count} sampled i x {n} j")
+        t_a = time.perf_counter()
+        ra, rk, rp = oracle.force(x, v, m, args.eps ** 2, idx=idx)
+        t_b = time.perf_counter()
+        result["cpu_baseline"] = {
+            "value": count * n / (t_b - t_a), "unit": "interactions/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{count} seeded i-particles x all {n} j-particles (FP64, long-double "
+                      f"sums), {t_b - t_a:.1f} s"}
+        errors = {args.precision: {"e_acc": rms_rel(g["a"][idx], ra),
+                                   "e_jerk": rms_rel(g["k"][idx], rk),
+                                   "e_pot": rms_rel(g["pot"][idx], rp), "sample": count}}
+        for prec, d in variants.items():
+            gv = d.pop("gv")
+            errors[prec] = {"e_acc": rms_rel(gv["a"][idx], ra), "e_jerk": rms_rel(gv["k"][idx], rk),
+                            "e_pot": rms_rel(gv["pot"][idx], rp), "sample": count}
+        result["errors_vs_oracle"] = errors
+    else:
+        for d in variants.values():
+            d.pop("gv")
+    # slowdown of each variant: its time per interaction over the timed arithmetic's
+    ns_per_int = force_ms * 1e6 / interactions
+    for prec, d in variants.items():
+        d["slowdown_vs_" + args.precision] = (d["full_force_ms"] * 1e6 / (n * n)) / ns_per_int
+    result["variants"] = variants
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,184 @@
+/*
+ * nbody.h -- C ABI of libnbody, the MI355X (gfx950) direct-summation N-body force and
+ * Hermite block-step library.
+ *
+ * The method is the one of Portegies Zwart, Belleman & Geldof (2007), "High Performance Direct
+ * Gravitational N-body Simulations on Graphics Processing Units": a fourth-order Hermite
+ * predictor-corrector with power-of-two block time steps (Sec. 2), whose cost is the direct
+ * sum of acceleration, jerk and potential on the active block (Sec. 2 Eq. Force, with the
+ * softening of App. A).
+ *
+ * Conventions shared by every call
+ *   - All array pointers are DEVICE pointers on the current HIP device unless a parameter says
+ *     "host".  The caller owns every pointer it passes; the library never frees them and keeps
+ *     them only between nb_bind() and the next nb_bind()/nb_destroy().
+ *   - Per-particle vectors are structure-of-arrays: component c (0 = x, 1 = y, 2 = z) of
+ *     particle i lives at [c * ld + i], where ld is the array's leading dimension (n for the
+ *     particle state, the caller's n_i_max for force outputs).
+ *   - Time is an int64 count of ticks of 2^-lmax (the smallest time step); a particle on level
+ *     l has time step 2^-l = 2^(lmax - l) ticks; lmin <= l <= lmax.
+ *   - Every call is asynchronous on the stream set by nb_set_stream() (default: the null
+ *     stream), except nb_energy(), nb_sync() and nb_read_control(), which synchronise it.
+ *   - Errors: each call returns an nb_status.  Argument errors are detected before anything is
+ *     enqueued.  Conditions the device detects (a non-finite force, a step that wanted to be
+ *     below 2^-lmax) are latched in a device flag word and reported by the next synchronising
+ *     call.  nb_last_error() gives a message for the last failing call on a context.
+ *   - A context is not thread-safe; use one context per host thread.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nb_ctx nb_ctx;
+
+typedef enum {
+    NB_OK = 0,
+    NB_EINVAL = -1,     /* bad argument (NULL pointer, size out of range, unbound state)   */
+    NB_EDEVICE = -2,    /* a HIP runtime call failed; nb_last_error() has its message      */
+    NB_ENOMEM = -3,     /* device allocation failed                                        */
+    NB_ESTATE = -4,     /* call out of order (e.g. nb_correct before any nb_force)          */
+    NB_ENONFINITE = -5, /* a force or corrected state was not finite (device flag)         */
+    NB_EDTMIN = -6      /* the time-step criterion asked for less than 2^-lmax (clamped)   */
+} nb_status;
+
+/* Arithmetic of the pair interaction (the rest of the step is always IEEE double).
+ *  NB_FP32: single-precision VALU arithmetic; separations formed from double positions and
+ *           then rounded once; sums over j-tiles accumulated in float and folded into double.
+ *  NB_DS:   double-single (float-float) arithmetic throughout the interaction and its sums.
+ *  NB_FP64: IEEE double arithmetic throughout. */
+typedef enum { NB_FP32 = 0, NB_DS = 1, NB_FP64 = 2 } nb_precision;
+
+/* FP64 master state of n particles, caller-owned device memory (structure of arrays). */
+typedef struct {
+    double *x;      /* 3*n positions                                                        */
+    double *v;      /* 3*n velocities                                                       */
+    double *a;      /* 3*n accelerations at each particle's own time                        */
+    double *k;      /* 3*n jerks (time derivative of the acceleration)                      */
+    double *m;      /* n masses                                                             */
+    double *pot;    /* n potentials, from the particle's last force evaluation             */
+    int64_t *tick;  /* n particle times (ticks)                                             */
+    int32_t *level; /* n time-step levels                                                   */
+} nb_state;
+
+/* Device-resident scheduler record, readable with nb_read_control(). */
+typedef struct {
+    int64_t t_cur;        /* time of the last completed block step (ticks)                  */
+    int64_t t_next;       /* time of the block currently selected (ticks)                   */
+    int64_t t_end;        /* nb_run() stops selecting blocks beyond this time               */
+    int64_t n_steps;      /* block steps completed since nb_init()                          */
+    int64_t n_active_sum; /* sum of block sizes over those steps                            */
+    int32_t n_act;        /* size of the selected block                                     */
+    int32_t flags;        /* bit 0: non-finite value seen; bit 1: step clamped at 2^-lmax   */
+} nb_control;
+
+/* Create a context for n particles (1 <= n <= 2^28) with Plummer softening eps >= 0, largest
+ * step 2^-lmin and smallest step 2^-lmax (0 <= lmin <= lmax <= 52), interaction arithmetic
+ * `precision`.  Allocates the library's own device work buffers on the current device (about
+ * 200 bytes per particle).  *out is set to NULL on failure. */
+nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t lmax,
+                    int32_t precision);
+
+/* Release the context and its device work buffers (never the caller's).  NULL is a no-op. */
+nb_status nb_destroy(nb_ctx *ctx);
+
+/* Enqueue subsequent work on `hip_stream` (a hipStream_t; NULL = the null stream). */
+nb_status nb_set_stream(nb_ctx *ctx, void *hip_stream);
+
+/* Bind the caller's FP64 state arrays (all fields required, each sized for n particles). */
+nb_status nb_bind(nb_ctx *ctx, const nb_state *state);
+
+/* Sec. 2 start of a run: full force on all n particles from x, v, m at time 0, then the
+ * initial step of each particle, Eq. initTimestep: dt = eta |a| / |k|, rounded down to a power
+ * of two in [2^-lmax, 2^-lmin].  Writes a, k, pot, level; sets every tick to 0.  Resets the
+ * scheduler record and selects the first block. */
+nb_status nb_init(nb_ctx *ctx, double eta);
+
+/* Sec. 2 block selection with Eq. timestep.  First gives each particle of the block corrected
+ * last its new level from dt = (eta (|a1||a2p| + |k1|^2) / (|k1||a3| + |a2p|^2))^(1/2): the
+ * step halves until it is not above dt, or doubles once when dt allows twice the old step, the
+ * particle's time is a multiple of the doubled step and the doubled step is at most 2^-lmin.
+ * Then selects the next block: t_next = min_i (t_i + dt_i) and the block {i : t_i + dt_i =
+ * t_next}, in ascending index order, kept on the device (see nb_active()).  A block beyond
+ * the scheduler's t_end is not selected (its size is 0). */
+nb_status nb_schedule_block(nb_ctx *ctx, double eta);
+
+/* Device pointers to the selected block: index list (int32, capacity n) and its length. */
+nb_status nb_active(nb_ctx *ctx, const int32_t **idx, const int32_t **n_act);
+
+/* Sec. 2 predictor: x_p = x + v D + a D^2/2 + k D^3/6 and v_p = v + a D + k D^2/2 of all n
+ * particles, D = (t - t_i) 2^-lmax, in double precision, stored as the j-particle stream the
+ * force reads (precision-dependent layout, library-owned).  `t` is a device pointer to an
+ * int64 tick count; NULL means the selected block time t_next. */
+nb_status nb_predict(nb_ctx *ctx, const int64_t *t);
+
+/* Sec. 2 Eq. Force with App. A softening, on the predicted stream: for each listed i,
+ *   acc_i  =  sum_{j != i} m_j d s^(-3/2),
+ *   jerk_i =  sum_{j != i} m_j [u s^(-3/2) - 3 (d.u) d s^(-5/2)],
+ *   pot_i  = -sum_{j != i} m_j s^(-1/2),
+ * with d = x_j - x_i, u = v_j - v_i, s = |d|^2 + eps^2, over all n predicted j-particles.
+ * i_idx: device int32 list of particle indices (NULL: 0, 1, ..., n_i - 1).
+ * n_i:   device int32 count (NULL: use n_i_max); must not exceed n_i_max.
+ * acc, jerk: 3 * n_i_max doubles (leading dimension n_i_max); pot: n_i_max doubles.
+ * Rows at and beyond the device count are left untouched.  Requires a prior nb_predict(). */
+nb_status nb_force(nb_ctx *ctx, const int32_t *i_idx, const int32_t *n_i, int32_t n_i_max,
+                   double *acc, double *jerk, double *pot);
+
+/* Sec. 2 corrector of the selected block over its steps, in double precision: from the old
+ * a0, k0 and the new acc/jerk (as written by nb_force on nb_active()'s list, leading dimension
+ * n), a2 = -6 (a0 - a1)/dt^2 - (4 k0 + 2 k1)/dt, a3 = 12 (a0 - a1)/dt^3 + 6 (k0 + k1)/dt^2,
+ * x = x_p + a2 dt^4/24 + a3 dt^5/120, v = v_p + a2 dt^3/6 + a3 dt^4/24, with x_p, v_p
+ * recomputed in double.  Stores a1, k1, pot; sets each block particle's time to t_next; keeps
+ * the time-step criterion inputs for the next nb_schedule_block(). */
+nb_status nb_correct(nb_ctx *ctx, const double *acc, const double *jerk, const double *pot);
+
+/* One whole block step, nsteps times: nb_schedule_block, nb_predict, nb_force on the block
+ * (library-owned outputs), nb_correct.  With use_graph != 0 the step sequence is captured once
+ * into a HIP graph and replayed. */
+nb_status nb_step(nb_ctx *ctx, double eta, int32_t nsteps, int32_t use_graph);
+
+/* Advance block steps until the block time would pass t_end (ticks): the scheduler selects no
+ * block beyond t_end, so the run ends exactly at the last block time <= t_end.  Runs at most
+ * max_steps steps (<= 0: no limit), synchronising once per `chunk` steps (chunk >= 1) to test
+ * for completion.  Returns NB_OK, or a latched device error. */
+nb_status nb_run(nb_ctx *ctx, double eta, int64_t t_end, int64_t max_steps, int32_t chunk,
+                 int32_t use_graph);
+
+/* Sec. 4.2 energy diagnostic, synchronising: kinetic sum m v^2 / 2 and softened potential
+ * energy -1/2 sum_i sum_{j != i} m_i m_j s^(-1/2), in double precision, of the state predicted
+ * to the last completed block time (exact at times where all particles are synchronised).
+ * ekin, epot are HOST pointers. */
+nb_status nb_energy(nb_ctx *ctx, double *ekin, double *epot);
+
+/* Copy the device scheduler record to the HOST struct *out (synchronising), and return the
+ * latched device error, if any. */
+nb_status nb_read_control(nb_ctx *ctx, nb_control *out);
+
+/* Force-kernel timing for measurement: with enable != 0, every force-kernel launch of this
+ * context is bracketed by HIP events recorded on the context's stream (nb_step then launches
+ * eagerly instead of through a graph).  Enabling or disabling discards earlier records;
+ * synchronising. */
+nb_status nb_profile(nb_ctx *ctx, int32_t enable);
+
+/* Total milliseconds between the bracketing events and the number of timed force launches
+ * since profiling was enabled (HOST outputs); synchronising. */
+nb_status nb_profile_read(nb_ctx *ctx, double *ms_total, int64_t *launches);
+
+/* Wait for the context's stream; returns a latched device error, if any. */
+nb_status nb_sync(nb_ctx *ctx);
+
+/* Human-readable message for the last failing call on ctx (never NULL). */
+const char *nb_last_error(const nb_ctx *ctx);
+
+/* Library version string, e.g. "libnbody 0.1 gfx950". */
+const char *nb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NBODY_H */

@@ -50,6 +50,7 @@ def _load():
         "orc_block_step": (_I64, [_I64, _d, _d, _d, _d, _d, _d, _i64, _i32, _D, _D, _I32, _I32,
                                   _i64, _i64, _d, _i64]),
         "orc_shared_step": (None, [_I64, _d, _d, _d, _d, _d, _d, _D, _D]),
+        "orc_num_threads": (ctypes.c_int, []),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -68,6 +69,11 @@ def _f64(a, shape=None):
     if shape is not None:
         a = a.reshape(shape)
     return a
+
+
+def num_threads():
+    """Threads the oracle's parallel loops use (OpenMP)."""
+    return int(_load().orc_num_threads())
 
 
 def force(x, v, m, eps2, idx=None):

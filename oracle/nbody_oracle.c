@@ -32,8 +32,21 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef long double acc_t;
+
+/* Number of threads the parallel loops below use. */
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------------------------
  * Sec. 2 Eq. Force with the softening of App. A.  For each listed i: the acceleration

@@ -1,0 +1,839 @@
+// kernels.hpp -- gfx950 device code of libnbody.
+//
+// Hermite block-step direct N-body integration (Portegies Zwart, Belleman & Geldof 2007):
+//   predict       Sec. 2 predictor, FP64, all particles -> the j-particle stream
+//   force_kernel  Sec. 2 Eq. Force with App. A softening: acceleration, jerk, potential of a
+//                 list of i-particles against all predicted j-particles (FP32 / DS / FP64)
+//   force_reduce  fixed-order sum of the j-split partial sums
+//   correct       Sec. 2 corrector, FP64, on the block
+//   sched_*       Sec. 2 block selection and Eq. timestep, integer time in ticks
+//   energy_*      Sec. 4.2 energy diagnostic, FP64
+// Wave64 throughout; workgroups of 256 work-items (4 waves).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ds_arith.hpp"
+
+namespace nbody {
+
+constexpr int WG = 256;      // work-items per workgroup
+constexpr int TJ = 256;      // j-particles per LDS tile (one staged per work-item)
+
+// Device-side scheduler record.  The first 48 bytes mirror nb_control of the C ABI.
+struct DevControl {
+    int64_t t_cur;
+    int64_t t_next;
+    int64_t t_end;
+    int64_t n_steps;
+    int64_t n_active_sum;
+    int32_t n_act;
+    int32_t flags;          // unused on device; flags live in the words below
+    // internal
+    int64_t t_cand;         // smallest t_i + dt_i found by the last selection
+    int32_t n_pending;      // particles corrected but not yet given a new level
+    int32_t done;           // the last selection found no block at or before t_end
+    int32_t flag_nonfinite; // latched: a force or corrected state was not finite
+    int32_t flag_dtmin;     // latched: the criterion asked for a step below 2^-lmax
+};
+
+// ------------------------------------------------------------------------------------------
+// Work decomposition of one force call, computed identically on host and device from the
+// number of i-particles: i-blocks of WG*IPL particles times K contiguous j-ranges (whole
+// tiles).  K > 1 only when the i-blocks alone cannot fill `target` work items.
+// ------------------------------------------------------------------------------------------
+struct ForcePlan {
+    int32_t n_i, n_iblk, ntiles, tps, K, items;
+    int64_t P;  // padded i rows of one partial plane
+};
+
+__host__ __device__ inline ForcePlan make_plan(int32_t n_i, int32_t n, int32_t ib,
+                                               int32_t target, int32_t kmax) {
+    ForcePlan p;
+    p.n_i = n_i;
+    p.n_iblk = (n_i + ib - 1) / ib;
+    p.ntiles = (n + TJ - 1) / TJ;
+    int32_t K = p.n_iblk > 0 ? target / p.n_iblk : 1;
+    if (K > kmax) K = kmax;
+    if (K > p.ntiles) K = p.ntiles;
+    if (K < 1) K = 1;
+    p.tps = (p.ntiles + K - 1) / K;
+    p.K = (p.ntiles + p.tps - 1) / p.tps;
+    p.items = p.n_iblk * p.K;
+    p.P = (int64_t)p.n_iblk * ib;
+    return p;
+}
+
+struct ForceCommon {
+    int32_t n;               // number of j-particles
+    const int32_t *ilist;    // i-particle indices (NULL: identity)
+    const int32_t *n_i_dev;  // device count (NULL: n_i_max)
+    int32_t n_i_max;
+    int32_t target;          // desired work items
+    int32_t kmax;            // largest j-split
+    double *acc, *jerk, *pot;
+    int32_t ld;              // leading dimension of acc/jerk/pot
+    double *partial;         // K > 1: [K][7][P]
+    DevControl *ctl;         // latched flags (may be NULL)
+};
+
+// Sum record written per i-particle: acc (3), jerk (3), accumulated m/r (1).
+struct Out7 {
+    double v[7];
+};
+
+// ------------------------------------------------------------------------------------------
+// FP32 interaction: separations from FP64 positions (one rounding), float arithmetic, tile
+// sums in float folded into double sums once per tile.
+// ------------------------------------------------------------------------------------------
+struct ModeF32 {
+    struct Args {
+        const double *px, *py, *pz;
+        const float4 *vm;  // vx, vy, vz, m
+        float eps2;
+    };
+    struct I {
+        double x, y, z;
+        float vx, vy, vz, m;
+    };
+    struct Smem {
+        double x[TJ], y[TJ], z[TJ];
+        float4 vm[TJ];
+    };
+    struct Tile {
+        float ax, ay, az, jx, jy, jz, p;
+    };
+    struct Sum {
+        double ax, ay, az, jx, jy, jz, p;
+    };
+
+    __device__ static I load_i(const Args &a, int g) {
+        const float4 q = a.vm[g];
+        return I{a.px[g], a.py[g], a.pz[g], q.x, q.y, q.z, q.w};
+    }
+    __device__ static void stage(const Args &a, Smem &s, int t, int j, int n) {
+        if (j < n) {
+            s.x[t] = a.px[j]; s.y[t] = a.py[j]; s.z[t] = a.pz[j]; s.vm[t] = a.vm[j];
+        } else {  // padding: zero mass contributes nothing
+            s.x[t] = 0.0; s.y[t] = 0.0; s.z[t] = 0.0; s.vm[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+    __device__ static Tile tile_zero() { return Tile{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}; }
+    __device__ static Sum sum_zero() { return Sum{0., 0., 0., 0., 0., 0., 0.}; }
+
+    template <bool SOFT>
+    __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, float eps2,
+                                                    Tile &T) {
+        const float dx = (float)(s.x[jj] - i.x);
+        const float dy = (float)(s.y[jj] - i.y);
+        const float dz = (float)(s.z[jj] - i.z);
+        const float4 q = s.vm[jj];
+        const float ux = q.x - i.vx;
+        const float uy = q.y - i.vy;
+        const float uz = q.z - i.vz;
+        const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+        const float rv = __builtin_fmaf(dz, uz, __builtin_fmaf(dy, uy, dx * ux));
+        float rinv = __builtin_amdgcn_rsqf(r2);
+        if (!SOFT) rinv = r2 > 0.0f ? rinv : 0.0f;
+        const float rinv2 = rinv * rinv;
+        const float mr = q.w * rinv;
+        const float mr3 = mr * rinv2;
+        const float t = -3.0f * (rv * rinv2);
+        T.p += mr;
+        T.ax = __builtin_fmaf(mr3, dx, T.ax);
+        T.ay = __builtin_fmaf(mr3, dy, T.ay);
+        T.az = __builtin_fmaf(mr3, dz, T.az);
+        T.jx = __builtin_fmaf(mr3, __builtin_fmaf(t, dx, ux), T.jx);
+        T.jy = __builtin_fmaf(mr3, __builtin_fmaf(t, dy, uy), T.jy);
+        T.jz = __builtin_fmaf(mr3, __builtin_fmaf(t, dz, uz), T.jz);
+    }
+    __device__ static void fold(Sum &S, const Tile &T) {
+        S.ax += (double)T.ax; S.ay += (double)T.ay; S.az += (double)T.az;
+        S.jx += (double)T.jx; S.jy += (double)T.jy; S.jz += (double)T.jz;
+        S.p += (double)T.p;
+    }
+    // The softened self pair (d = u = 0) adds exactly 0 to acc and jerk and m_i rsq(eps2) to
+    // the potential sum; remove that same float value.
+    __device__ static void remove_self(Sum &S, const I &i, float eps2) {
+        S.p -= (double)(i.m * __builtin_amdgcn_rsqf(eps2));
+    }
+    __device__ static Out7 out(const Sum &S) {
+        return Out7{{S.ax, S.ay, S.az, S.jx, S.jy, S.jz, S.p}};
+    }
+};
+
+// ------------------------------------------------------------------------------------------
+// Double-single interaction: every operation in float-float arithmetic; tile sums folded into
+// outer sums with the accurate addition.
+// ------------------------------------------------------------------------------------------
+struct ModeDS {
+    struct Args {
+        const float4 *q0;  // x_hi, y_hi, z_hi, m_hi
+        const float4 *q1;  // x_lo, y_lo, z_lo, m_lo
+        const float4 *q2;  // vx_hi, vy_hi, vz_hi, 0
+        const float4 *q3;  // vx_lo, vy_lo, vz_lo, 0
+        ds eps2;
+    };
+    struct I {
+        ds x, y, z, vx, vy, vz, m;
+    };
+    struct Smem {
+        float4 q0[TJ], q1[TJ], q2[TJ], q3[TJ];
+    };
+    struct Tile {
+        ds ax, ay, az, jx, jy, jz, p;
+    };
+    using Sum = Tile;
+
+    __device__ static I load_i(const Args &a, int g) {
+        const float4 h = a.q0[g], l = a.q1[g], vh = a.q2[g], vl = a.q3[g];
+        return I{ds{h.x, l.x}, ds{h.y, l.y}, ds{h.z, l.z}, ds{vh.x, vl.x}, ds{vh.y, vl.y},
+                 ds{vh.z, vl.z}, ds{h.w, l.w}};
+    }
+    __device__ static void stage(const Args &a, Smem &s, int t, int j, int n) {
+        if (j < n) {
+            s.q0[t] = a.q0[j]; s.q1[t] = a.q1[j]; s.q2[t] = a.q2[j]; s.q3[t] = a.q3[j];
+        } else {
+            const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+            s.q0[t] = z; s.q1[t] = z; s.q2[t] = z; s.q3[t] = z;
+        }
+    }
+    __device__ static Tile tile_zero() {
+        const ds z{0.f, 0.f};
+        return Tile{z, z, z, z, z, z, z};
+    }
+    __device__ static Sum sum_zero() { return tile_zero(); }
+
+    template <bool SOFT>
+    __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, ds eps2,
+                                                    Tile &T) {
+        const float4 h = s.q0[jj], l = s.q1[jj], vh = s.q2[jj], vl = s.q3[jj];
+        const ds dx = ds_sub(ds{h.x, l.x}, i.x);
+        const ds dy = ds_sub(ds{h.y, l.y}, i.y);
+        const ds dz = ds_sub(ds{h.z, l.z}, i.z);
+        const ds ux = ds_add_sloppy(ds{vh.x, vl.x}, ds_neg(i.vx));
+        const ds uy = ds_add_sloppy(ds{vh.y, vl.y}, ds_neg(i.vy));
+        const ds uz = ds_add_sloppy(ds{vh.z, vl.z}, ds_neg(i.vz));
+        const ds r2 = ds_add_sloppy(ds_add_sloppy(ds_add_sloppy(eps2, ds_sqr(dx)), ds_sqr(dy)),
+                                    ds_sqr(dz));
+        const ds rv = ds_add_sloppy(ds_add_sloppy(ds_mul(dx, ux), ds_mul(dy, uy)), ds_mul(dz, uz));
+        ds rinv = ds_rsqrt(r2);
+        if (!SOFT && !(r2.hi > 0.0f)) rinv = ds{0.f, 0.f};
+        const ds rinv2 = ds_sqr(rinv);
+        const ds mr = ds_mul(ds{h.w, l.w}, rinv);
+        const ds mr3 = ds_mul(mr, rinv2);
+        const ds t = ds_mul_f(ds_mul(rv, rinv2), -3.0f);
+        T.p = ds_add_sloppy(T.p, mr);
+        T.ax = ds_add_sloppy(T.ax, ds_mul(mr3, dx));
+        T.ay = ds_add_sloppy(T.ay, ds_mul(mr3, dy));
+        T.az = ds_add_sloppy(T.az, ds_mul(mr3, dz));
+        T.jx = ds_add_sloppy(T.jx, ds_mul(mr3, ds_add_sloppy(ux, ds_mul(t, dx))));
+        T.jy = ds_add_sloppy(T.jy, ds_mul(mr3, ds_add_sloppy(uy, ds_mul(t, dy))));
+        T.jz = ds_add_sloppy(T.jz, ds_mul(mr3, ds_add_sloppy(uz, ds_mul(t, dz))));
+    }
+    __device__ static void fold(Sum &S, const Tile &T) {
+        S.ax = ds_add(S.ax, T.ax); S.ay = ds_add(S.ay, T.ay); S.az = ds_add(S.az, T.az);
+        S.jx = ds_add(S.jx, T.jx); S.jy = ds_add(S.jy, T.jy); S.jz = ds_add(S.jz, T.jz);
+        S.p = ds_add(S.p, T.p);
+    }
+    __device__ static void remove_self(Sum &S, const I &i, ds eps2) {
+        // the self pair's r2 is eps2 + 0 + 0 + 0, computed as in interact()
+        const ds z{0.f, 0.f};
+        const ds r2 = ds_add_sloppy(ds_add_sloppy(ds_add_sloppy(eps2, ds_sqr(z)), ds_sqr(z)),
+                                    ds_sqr(z));
+        S.p = ds_sub(S.p, ds_mul(i.m, ds_rsqrt(r2)));
+    }
+    __device__ static Out7 out(const Sum &S) {
+        return Out7{{ds_to_double(S.ax), ds_to_double(S.ay), ds_to_double(S.az),
+                     ds_to_double(S.jx), ds_to_double(S.jy), ds_to_double(S.jz),
+                     ds_to_double(S.p)}};
+    }
+};
+
+// ------------------------------------------------------------------------------------------
+// FP64 interaction: IEEE double throughout; s^(-1/2) from the hardware estimate refined by two
+// Newton steps.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ double rsqrt_f64(double s) {
+    double y = __builtin_amdgcn_rsq(s);
+    double h = s * y;
+    double r = __builtin_fma(-h, y, 1.0);
+    y = __builtin_fma(0.5 * y, r, y);
+    h = s * y;
+    r = __builtin_fma(-h, y, 1.0);
+    y = __builtin_fma(0.5 * y, r, y);
+    return y;
+}
+
+struct ModeF64 {
+    struct Args {
+        const double *px, *py, *pz, *pm, *vx, *vy, *vz;
+        double eps2;
+    };
+    struct I {
+        double x, y, z, vx, vy, vz, m;
+    };
+    struct Smem {
+        double x[TJ], y[TJ], z[TJ], m[TJ], vx[TJ], vy[TJ], vz[TJ];
+    };
+    struct Tile {
+        double ax, ay, az, jx, jy, jz, p;
+    };
+    using Sum = Tile;
+
+    __device__ static I load_i(const Args &a, int g) {
+        return I{a.px[g], a.py[g], a.pz[g], a.vx[g], a.vy[g], a.vz[g], a.pm[g]};
+    }
+    __device__ static void stage(const Args &a, Smem &s, int t, int j, int n) {
+        const bool ok = j < n;
+        s.x[t] = ok ? a.px[j] : 0.0; s.y[t] = ok ? a.py[j] : 0.0; s.z[t] = ok ? a.pz[j] : 0.0;
+        s.m[t] = ok ? a.pm[j] : 0.0;
+        s.vx[t] = ok ? a.vx[j] : 0.0; s.vy[t] = ok ? a.vy[j] : 0.0; s.vz[t] = ok ? a.vz[j] : 0.0;
+    }
+    __device__ static Tile tile_zero() { return Tile{0., 0., 0., 0., 0., 0., 0.}; }
+    __device__ static Sum sum_zero() { return tile_zero(); }
+
+    template <bool SOFT>
+    __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, double eps2,
+                                                    Tile &T) {
+        const double dx = s.x[jj] - i.x, dy = s.y[jj] - i.y, dz = s.z[jj] - i.z;
+        const double ux = s.vx[jj] - i.vx, uy = s.vy[jj] - i.vy, uz = s.vz[jj] - i.vz;
+        const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, __builtin_fma(dx, dx, eps2)));
+        const double rv = __builtin_fma(dz, uz, __builtin_fma(dy, uy, dx * ux));
+        double rinv = rsqrt_f64(r2);
+        if (!SOFT) rinv = r2 > 0.0 ? rinv : 0.0;
+        const double rinv2 = rinv * rinv;
+        const double mr = s.m[jj] * rinv;
+        const double mr3 = mr * rinv2;
+        const double t = -3.0 * (rv * rinv2);
+        T.p += mr;
+        T.ax = __builtin_fma(mr3, dx, T.ax);
+        T.ay = __builtin_fma(mr3, dy, T.ay);
+        T.az = __builtin_fma(mr3, dz, T.az);
+        T.jx = __builtin_fma(mr3, __builtin_fma(t, dx, ux), T.jx);
+        T.jy = __builtin_fma(mr3, __builtin_fma(t, dy, uy), T.jy);
+        T.jz = __builtin_fma(mr3, __builtin_fma(t, dz, uz), T.jz);
+    }
+    __device__ static void fold(Sum &S, const Tile &T) {
+        S.ax += T.ax; S.ay += T.ay; S.az += T.az; S.jx += T.jx; S.jy += T.jy; S.jz += T.jz;
+        S.p += T.p;
+    }
+    __device__ static void remove_self(Sum &S, const I &i, double eps2) {
+        S.p -= i.m * rsqrt_f64(__builtin_fma(0.0, 0.0, __builtin_fma(0.0, 0.0, __builtin_fma(0.0, 0.0, eps2))));
+    }
+    __device__ static Out7 out(const Sum &S) {
+        return Out7{{S.ax, S.ay, S.az, S.jx, S.jy, S.jz, S.p}};
+    }
+};
+
+template <class M> struct EpsOf;
+template <> struct EpsOf<ModeF32> { using T = float; };
+template <> struct EpsOf<ModeDS> { using T = ds; };
+template <> struct EpsOf<ModeF64> { using T = double; };
+
+__device__ __forceinline__ bool finite7(const Out7 &o) {
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) ok = ok && __builtin_isfinite(o.v[c]);
+    return ok;
+}
+
+// ------------------------------------------------------------------------------------------
+// The force kernel.  Each workgroup takes work items (i-block, j-range); each work-item holds
+// IPL i-particles in registers; the workgroup stages TJ j-particles at a time in LDS, and
+// every work-item reads each staged j (an LDS broadcast) and interacts it with its i's.
+// K == 1: results go straight to acc/jerk/pot; K > 1: to the partial planes for
+// force_reduce.  The potential sum is negated on output.
+// ------------------------------------------------------------------------------------------
+template <class M, int IPL, bool SOFT>
+__global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCommon fc) {
+    __shared__ typename M::Smem sm;
+    int32_t n_i = fc.n_i_max;
+    if (fc.n_i_dev) {
+        const int32_t d = *fc.n_i_dev;
+        n_i = d < n_i ? d : n_i;
+    }
+    if (n_i <= 0) return;
+    const ForcePlan pl = make_plan(n_i, fc.n, WG * IPL, fc.target, fc.kmax);
+    const auto eps2 = pa.eps2;
+    for (int32_t w = blockIdx.x; w < pl.items; w += gridDim.x) {
+        const int32_t iblk = w / pl.K, ks = w - (w / pl.K) * pl.K;
+        int32_t q[IPL], g[IPL];
+        typename M::I ii[IPL];
+        typename M::Sum S[IPL];
+#pragma unroll
+        for (int p = 0; p < IPL; ++p) {
+            q[p] = iblk * (WG * IPL) + p * WG + (int32_t)threadIdx.x;
+            g[p] = q[p] < n_i ? (fc.ilist ? fc.ilist[q[p]] : q[p]) : 0;
+            ii[p] = M::load_i(pa, g[p]);
+            S[p] = M::sum_zero();
+        }
+        const int32_t t0 = ks * pl.tps;
+        const int32_t t1 = t0 + pl.tps < pl.ntiles ? t0 + pl.tps : pl.ntiles;
+        for (int32_t t = t0; t < t1; ++t) {
+            __syncthreads();
+            M::stage(pa, sm, threadIdx.x, t * TJ + (int32_t)threadIdx.x, fc.n);
+            __syncthreads();
+            typename M::Tile T[IPL];
+#pragma unroll
+            for (int p = 0; p < IPL; ++p) T[p] = M::tile_zero();
+#pragma unroll 4
+            for (int jj = 0; jj < TJ; ++jj) {
+#pragma unroll
+                for (int p = 0; p < IPL; ++p) M::template interact<SOFT>(ii[p], sm, jj, eps2, T[p]);
+            }
+#pragma unroll
+            for (int p = 0; p < IPL; ++p) M::fold(S[p], T[p]);
+        }
+        const int32_t jlo = t0 * TJ, jhi = t1 * TJ;
+#pragma unroll
+        for (int p = 0; p < IPL; ++p) {
+            if (q[p] >= n_i) continue;
+            if (SOFT && g[p] >= jlo && g[p] < jhi) M::remove_self(S[p], ii[p], eps2);
+            Out7 o = M::out(S[p]);
+            o.v[6] = -o.v[6];
+            if (pl.K == 1) {
+                if (fc.ctl && !finite7(o)) fc.ctl->flag_nonfinite = 1;
+                fc.acc[0 * (int64_t)fc.ld + q[p]] = o.v[0];
+                fc.acc[1 * (int64_t)fc.ld + q[p]] = o.v[1];
+                fc.acc[2 * (int64_t)fc.ld + q[p]] = o.v[2];
+                fc.jerk[0 * (int64_t)fc.ld + q[p]] = o.v[3];
+                fc.jerk[1 * (int64_t)fc.ld + q[p]] = o.v[4];
+                fc.jerk[2 * (int64_t)fc.ld + q[p]] = o.v[5];
+                fc.pot[q[p]] = o.v[6];
+            } else {
+                double *base = fc.partial + (int64_t)ks * 7 * pl.P + q[p];
+#pragma unroll
+                for (int c = 0; c < 7; ++c) base[(int64_t)c * pl.P] = o.v[c];
+            }
+        }
+    }
+}
+
+// Fixed-order sum over the K partial planes (deterministic; no atomics).
+__global__ void __launch_bounds__(WG) force_reduce(ForceCommon fc, int32_t ib) {
+    int32_t n_i = fc.n_i_max;
+    if (fc.n_i_dev) {
+        const int32_t d = *fc.n_i_dev;
+        n_i = d < n_i ? d : n_i;
+    }
+    if (n_i <= 0) return;
+    const ForcePlan pl = make_plan(n_i, fc.n, ib, fc.target, fc.kmax);
+    if (pl.K == 1) return;
+    for (int32_t q = blockIdx.x * WG + threadIdx.x; q < n_i; q += gridDim.x * WG) {
+        Out7 o;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) {
+            double s = 0.0;
+            for (int32_t k = 0; k < pl.K; ++k) s += fc.partial[((int64_t)k * 7 + c) * pl.P + q];
+            o.v[c] = s;
+        }
+        if (fc.ctl && !finite7(o)) fc.ctl->flag_nonfinite = 1;
+        for (int c = 0; c < 3; ++c) fc.acc[c * (int64_t)fc.ld + q] = o.v[c];
+        for (int c = 0; c < 3; ++c) fc.jerk[c * (int64_t)fc.ld + q] = o.v[3 + c];
+        fc.pot[q] = o.v[6];
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Sec. 2 predictor (FP64) of all particles to time t, written as the j-particle stream.
+// ------------------------------------------------------------------------------------------
+struct StateView {
+    const double *x, *v, *a, *k, *m;
+    const int64_t *tick;
+    int32_t n;
+    double tick_len;
+};
+
+struct JStreamView {
+    double *px, *py, *pz;  // F32 / F64
+    float4 *vm;            // F32
+    float4 *q0, *q1, *q2, *q3;  // DS
+    double *pm, *vx, *vy, *vz;  // F64
+};
+
+__device__ __forceinline__ void predict_one(double D, double x, double v, double a, double k,
+                                            double &xp, double &vp) {
+    const double h = 0.5 * D;
+    const double t = D * (1.0 / 3.0);
+    // x + D (v + D/2 (a + D/3 k)) and v + D (a + D/2 k)
+    xp = __builtin_fma(D, __builtin_fma(h, __builtin_fma(t, k, a), v), x);
+    vp = __builtin_fma(D, __builtin_fma(h, k, a), v);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(WG) predict_kernel(StateView s, JStreamView js,
+                                                     const int64_t *t_ptr, const DevControl *ctl,
+                                                     int32_t guard) {
+    if (guard && ctl->n_act == 0) return;
+    const int64_t t = t_ptr ? *t_ptr : ctl->t_next;
+    const int32_t n = s.n;
+    for (int32_t i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+        const double D = (double)(t - s.tick[i]) * s.tick_len;
+        double xp[3], vp[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            predict_one(D, s.x[c * (int64_t)n + i], s.v[c * (int64_t)n + i],
+                        s.a[c * (int64_t)n + i], s.k[c * (int64_t)n + i], xp[c], vp[c]);
+        const double m = s.m[i];
+        if (MODE == 0) {
+            js.px[i] = xp[0]; js.py[i] = xp[1]; js.pz[i] = xp[2];
+            js.vm[i] = make_float4((float)vp[0], (float)vp[1], (float)vp[2], (float)m);
+        } else if (MODE == 1) {
+            const ds X = ds_from_double(xp[0]), Y = ds_from_double(xp[1]), Z = ds_from_double(xp[2]);
+            const ds VX = ds_from_double(vp[0]), VY = ds_from_double(vp[1]), VZ = ds_from_double(vp[2]);
+            const ds M = ds_from_double(m);
+            js.q0[i] = make_float4(X.hi, Y.hi, Z.hi, M.hi);
+            js.q1[i] = make_float4(X.lo, Y.lo, Z.lo, M.lo);
+            js.q2[i] = make_float4(VX.hi, VY.hi, VZ.hi, 0.f);
+            js.q3[i] = make_float4(VX.lo, VY.lo, VZ.lo, 0.f);
+        } else {
+            js.px[i] = xp[0]; js.py[i] = xp[1]; js.pz[i] = xp[2]; js.pm[i] = m;
+            js.vx[i] = vp[0]; js.vy[i] = vp[1]; js.vz[i] = vp[2];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Sec. 2 Eq. initTimestep and power-of-two rounding; and the start-of-run state.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ int32_t level_from_dt(double dt, int32_t lmin, int32_t lmax) {
+    int32_t l = lmin;
+    while (l < lmax && __builtin_ldexp(1.0, -l) > dt) ++l;
+    return l;
+}
+
+__global__ void __launch_bounds__(WG) zero_ticks(int64_t *tick, int32_t n) {
+    for (int32_t i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) tick[i] = 0;
+}
+
+__global__ void __launch_bounds__(WG) reset_control(DevControl *ctl) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->t_cur = 0; ctl->t_next = 0; ctl->t_end = INT64_MAX; ctl->n_steps = 0;
+        ctl->n_active_sum = 0; ctl->n_act = 0; ctl->flags = 0; ctl->t_cand = 0;
+        ctl->n_pending = 0; ctl->done = 0; ctl->flag_nonfinite = 0; ctl->flag_dtmin = 0;
+    }
+}
+
+__global__ void __launch_bounds__(WG) set_t_end(DevControl *ctl, int64_t t_end) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->t_end = t_end;
+        ctl->done = 0;
+    }
+}
+
+struct StateRW {
+    double *x, *v, *a, *k, *m, *pot;
+    int64_t *tick;
+    int32_t *level;
+    int32_t n;
+    double tick_len;
+};
+
+__global__ void __launch_bounds__(WG) init_levels(StateRW s, const double *acc, const double *jerk,
+                                                  const double *pot, double eta, int32_t lmin,
+                                                  int32_t lmax, DevControl *ctl) {
+    const int32_t n = s.n;
+    for (int32_t i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+        double na = 0.0, nk = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double a = acc[c * (int64_t)n + i], k = jerk[c * (int64_t)n + i];
+            s.a[c * (int64_t)n + i] = a;
+            s.k[c * (int64_t)n + i] = k;
+            na = __builtin_fma(a, a, na);
+            nk = __builtin_fma(k, k, nk);
+        }
+        s.pot[i] = pot[i];
+        na = __builtin_sqrt(na);
+        nk = __builtin_sqrt(nk);
+        const double dt = nk > 0.0 ? eta * na / nk : __builtin_inf();
+        if (!__builtin_isfinite(na) || !__builtin_isfinite(nk)) ctl->flag_nonfinite = 1;
+        s.level[i] = level_from_dt(dt, lmin, lmax);
+        s.tick[i] = 0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Sec. 2 corrector (FP64) on the selected block.
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(WG) correct_kernel(StateRW s, const int32_t *active,
+                                                     const double *acc, const double *jerk,
+                                                     const double *pot, int32_t ld,
+                                                     double *crit, DevControl *ctl) {
+    const int32_t n_act = ctl->n_act;
+    const int64_t t_next = ctl->t_next;
+    const int32_t n = s.n;
+    for (int32_t q = blockIdx.x * WG + threadIdx.x; q < n_act; q += gridDim.x * WG) {
+        const int32_t i = active[q];
+        const double dt = (double)(t_next - s.tick[i]) * s.tick_len;
+        const double idt = 1.0 / dt;  // a power of two: exact
+        const double dt2 = dt * dt, dt3 = dt2 * dt, dt4 = dt3 * dt, dt5 = dt4 * dt;
+        double na1 = 0.0, nk1 = 0.0, na2p = 0.0, na3 = 0.0;
+        bool ok = true;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t e = c * (int64_t)n + i;
+            const double x = s.x[e], v = s.v[e], a0 = s.a[e], k0 = s.k[e];
+            const double a1 = acc[c * (int64_t)ld + q], k1 = jerk[c * (int64_t)ld + q];
+            double xp, vp;
+            predict_one(dt, x, v, a0, k0, xp, vp);
+            const double da = a0 - a1;
+            const double a2 = (-6.0 * da * idt - (4.0 * k0 + 2.0 * k1)) * idt;
+            const double a3 = (12.0 * da * idt + 6.0 * (k0 + k1)) * idt * idt;
+            const double xn = xp + a2 * (dt4 * (1.0 / 24.0)) + a3 * (dt5 * (1.0 / 120.0));
+            const double vn = vp + a2 * (dt3 * (1.0 / 6.0)) + a3 * (dt4 * (1.0 / 24.0));
+            const double a2p = a2 + a3 * dt;
+            ok = ok && __builtin_isfinite(xn) && __builtin_isfinite(vn) && __builtin_isfinite(a2p);
+            s.x[e] = xn; s.v[e] = vn; s.a[e] = a1; s.k[e] = k1;
+            na1 = __builtin_fma(a1, a1, na1);
+            nk1 = __builtin_fma(k1, k1, nk1);
+            na2p = __builtin_fma(a2p, a2p, na2p);
+            na3 = __builtin_fma(a3, a3, na3);
+        }
+        s.pot[i] = pot[q];
+        na1 = __builtin_sqrt(na1); nk1 = __builtin_sqrt(nk1);
+        na2p = __builtin_sqrt(na2p); na3 = __builtin_sqrt(na3);
+        crit[2 * (int64_t)i] = na1 * na2p + nk1 * nk1;
+        crit[2 * (int64_t)i + 1] = nk1 * na3 + na2p * na2p;
+        s.tick[i] = t_next;
+        if (!ok) ctl->flag_nonfinite = 1;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n_act > 0) {
+        ctl->t_cur = t_next;
+        ctl->n_steps += 1;
+        ctl->n_active_sum += n_act;
+        ctl->n_pending = n_act;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Sec. 2 block scheduling.
+// ------------------------------------------------------------------------------------------
+// New level of each particle corrected last (Eq. timestep, power-of-two rules).
+__global__ void __launch_bounds__(WG) sched_newlevel(StateRW s, const int32_t *active,
+                                                     const double *crit, double eta,
+                                                     int32_t lmin, int32_t lmax,
+                                                     DevControl *ctl) {
+    const int32_t np = ctl->n_pending;
+    for (int32_t q = blockIdx.x * WG + threadIdx.x; q < np; q += gridDim.x * WG) {
+        const int32_t i = active[q];
+        const double num = crit[2 * (int64_t)i], den = crit[2 * (int64_t)i + 1];
+        const double dt = den > 0.0 ? __builtin_sqrt(eta * num / den) : __builtin_inf();
+        if (__builtin_isnan(dt)) ctl->flag_nonfinite = 1;
+        else if (dt < s.tick_len) ctl->flag_dtmin = 1;
+        int32_t l = s.level[i];
+        if (dt < __builtin_ldexp(1.0, -l)) {
+            while (l < lmax && __builtin_ldexp(1.0, -l) > dt) ++l;
+        } else if (l > lmin && dt >= __builtin_ldexp(1.0, -(l - 1))) {
+            const int64_t two_dt = (int64_t)1 << (lmax - l + 1);
+            if (s.tick[i] % two_dt == 0) --l;
+        }
+        s.level[i] = l;
+    }
+}
+
+__device__ __forceinline__ int64_t wg_min_i64(int64_t v, int64_t *red) {
+    // wave minimum by shuffles, then across the 4 waves through LDS
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    int64_t r = red[0];
+    for (int w = 1; w < WG / 64; ++w) r = red[w] < r ? red[w] : r;
+    return r;
+}
+
+__device__ __forceinline__ int64_t wg_sum_i64(int64_t v, int64_t *red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    int64_t r = 0;
+    for (int w = 0; w < WG / 64; ++w) r += red[w];
+    return r;
+}
+
+struct SchedView {
+    const int64_t *tick;
+    const int32_t *level;
+    int32_t n, lmax, chunk, groups;
+    int64_t *wgmin;
+    int32_t *cnt;
+    int32_t *active;
+};
+
+// Pass 1: per-workgroup minimum of t_i + dt_i over its contiguous chunk.
+__global__ void __launch_bounds__(WG) sched_min(SchedView v) {
+    __shared__ int64_t red[WG / 64];
+    const int32_t lo = blockIdx.x * v.chunk;
+    const int32_t hi = lo + v.chunk < v.n ? lo + v.chunk : v.n;
+    int64_t m = INT64_MAX;
+    for (int32_t i = lo + threadIdx.x; i < hi; i += WG) {
+        const int64_t tn = v.tick[i] + ((int64_t)1 << (v.lmax - v.level[i]));
+        m = tn < m ? tn : m;
+    }
+    m = wg_min_i64(m, red);
+    if (threadIdx.x == 0) v.wgmin[blockIdx.x] = m;
+}
+
+__device__ __forceinline__ int64_t global_min(const SchedView &v, int64_t *red) {
+    int64_t m = INT64_MAX;
+    for (int32_t g = threadIdx.x; g < v.groups; g += WG) m = v.wgmin[g] < m ? v.wgmin[g] : m;
+    return wg_min_i64(m, red);
+}
+
+// Pass 2: the block time t_next = min over all, and each chunk's count of block members.
+__global__ void __launch_bounds__(WG) sched_count(SchedView v, DevControl *ctl) {
+    __shared__ int64_t red[WG / 64];
+    const int64_t tc = global_min(v, red);
+    const bool take = tc <= ctl->t_end;
+    const int32_t lo = blockIdx.x * v.chunk;
+    const int32_t hi = lo + v.chunk < v.n ? lo + v.chunk : v.n;
+    int64_t c = 0;
+    if (take)
+        for (int32_t i = lo + threadIdx.x; i < hi; i += WG)
+            c += (v.tick[i] + ((int64_t)1 << (v.lmax - v.level[i]))) == tc;
+    c = wg_sum_i64(c, red);
+    if (threadIdx.x == 0) {
+        v.cnt[blockIdx.x] = (int32_t)c;
+        if (blockIdx.x == 0) {
+            ctl->t_cand = tc;
+            ctl->done = take ? 0 : 1;
+        }
+    }
+}
+
+// Pass 3: ordered compaction of the block members into the active list (ascending index).
+__global__ void __launch_bounds__(WG) sched_scatter(SchedView v, DevControl *ctl) {
+    __shared__ int64_t red[WG / 64];
+    __shared__ int32_t wsum[WG / 64];
+    const int64_t tc = ctl->t_cand;
+    const bool take = ctl->done == 0;
+    // exclusive prefix of the chunk counts, and the total
+    int64_t before = 0, total = 0;
+    for (int32_t g = threadIdx.x; g < v.groups; g += WG) {
+        before += g < (int32_t)blockIdx.x ? v.cnt[g] : 0;
+        total += v.cnt[g];
+    }
+    before = wg_sum_i64(before, red);
+    total = wg_sum_i64(total, red);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t lo = blockIdx.x * v.chunk;
+    const int32_t hi = lo + v.chunk < v.n ? lo + v.chunk : v.n;
+    int32_t base = (int32_t)before;
+    if (take) {
+        for (int32_t i0 = lo; i0 < hi; i0 += WG) {
+            const int32_t i = i0 + threadIdx.x;
+            const bool f = i < hi && (v.tick[i] + ((int64_t)1 << (v.lmax - v.level[i]))) == tc;
+            const uint64_t mask = __ballot(f);
+            const int32_t below = __popcll(mask & ((1ull << lane) - 1ull));
+            __syncthreads();
+            if (lane == 0) wsum[wave] = __popcll(mask);
+            __syncthreads();
+            int32_t off = base;
+            for (int w = 0; w < wave; ++w) off += wsum[w];
+            if (f) v.active[off + below] = i;
+            for (int w = 0; w < WG / 64; ++w) base += wsum[w];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->n_act = take ? (int32_t)total : 0;
+        if (take) ctl->t_next = tc;
+        ctl->n_pending = 0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Sec. 4.2 energy diagnostic (FP64).
+// ------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(WG) energy_predict(StateView s, const DevControl *ctl,
+                                                     double *xp, double *vp) {
+    const int32_t n = s.n;
+    const int64_t t = ctl->t_cur;
+    for (int32_t i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+        const double D = (double)(t - s.tick[i]) * s.tick_len;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t e = c * (int64_t)n + i;
+            predict_one(D, s.x[e], s.v[e], s.a[e], s.k[e], xp[e], vp[e]);
+        }
+    }
+}
+
+// Per particle: m_i sum_{j != i} m_j s^(-1/2) (tile sums folded with Neumaier compensation)
+// and m_i |v_i|^2 / 2.
+__global__ void __launch_bounds__(WG) energy_pairs(const double *xp, const double *vp,
+                                                   const double *m, int32_t n, double eps2,
+                                                   double *w_out, double *k_out) {
+    __shared__ double sx[TJ], sy[TJ], sz[TJ], sm[TJ];
+    const int32_t ntiles = (n + TJ - 1) / TJ;
+    for (int32_t ib = blockIdx.x; ib * WG < n; ib += gridDim.x) {
+        const int32_t i = ib * WG + threadIdx.x;
+        const int32_t ic = i < n ? i : 0;
+        const double xi = xp[ic], yi = xp[(int64_t)n + ic], zi = xp[2 * (int64_t)n + ic];
+        double s = 0.0, comp = 0.0;
+        for (int32_t t = 0; t < ntiles; ++t) {
+            __syncthreads();
+            const int32_t j = t * TJ + threadIdx.x;
+            sx[threadIdx.x] = j < n ? xp[j] : 0.0;
+            sy[threadIdx.x] = j < n ? xp[(int64_t)n + j] : 0.0;
+            sz[threadIdx.x] = j < n ? xp[2 * (int64_t)n + j] : 0.0;
+            sm[threadIdx.x] = j < n ? m[j] : 0.0;
+            __syncthreads();
+            double ts = 0.0;
+            for (int jj = 0; jj < TJ; ++jj) {
+                const double dx = sx[jj] - xi, dy = sy[jj] - yi, dz = sz[jj] - zi;
+                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, __builtin_fma(dx, dx, eps2)));
+                const double term = sm[jj] * rsqrt_f64(r2);
+                ts += (t * TJ + jj == i || !(r2 > 0.0)) ? 0.0 : term;
+            }
+            const double y = s + ts;  // Neumaier step
+            comp += __builtin_fabs(s) >= __builtin_fabs(ts) ? (s - y) + ts : (ts - y) + s;
+            s = y;
+        }
+        if (i < n) {
+            const double mi = m[i];
+            w_out[i] = mi * (s + comp);
+            const double vx = vp[i], vy = vp[(int64_t)n + i], vz = vp[2 * (int64_t)n + i];
+            k_out[i] = 0.5 * mi * __builtin_fma(vz, vz, __builtin_fma(vy, vy, vx * vx));
+        }
+    }
+}
+
+// One workgroup of 1024: fixed-order compensated sums of both arrays.
+__global__ void __launch_bounds__(1024) energy_reduce(const double *w, const double *kin,
+                                                      int32_t n, double *out) {
+    __shared__ double sw[1024], sk[1024];
+    double a = 0.0, ca = 0.0, b = 0.0, cb = 0.0;
+    for (int32_t i = threadIdx.x; i < n; i += 1024) {
+        double y = a + w[i];
+        ca += __builtin_fabs(a) >= __builtin_fabs(w[i]) ? (a - y) + w[i] : (w[i] - y) + a;
+        a = y;
+        y = b + kin[i];
+        cb += __builtin_fabs(b) >= __builtin_fabs(kin[i]) ? (b - y) + kin[i] : (kin[i] - y) + b;
+        b = y;
+    }
+    sw[threadIdx.x] = a + ca;
+    sk[threadIdx.x] = b + cb;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sw[threadIdx.x] += sw[threadIdx.x + s];
+            sk[threadIdx.x] += sk[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sk[0];
+        out[1] = -0.5 * sw[0];
+    }
+}
+
+}  // namespace nbody

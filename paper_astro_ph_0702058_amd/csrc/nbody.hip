@@ -1,0 +1,590 @@
+// nbody.hip -- libnbody: the C ABI declared in include/nbody.h, for gfx950.
+//
+// The host side owns only the context, its device work buffers (j-particle stream, block list,
+// scheduler record, force partial sums, energy scratch) and captured HIP graphs.  All particle
+// state is the caller's.  Every kernel sizes its work from device-resident counts, so a block
+// step needs no host round trip and can be captured and replayed as a graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/nbody.h"
+#include "kernels.hpp"
+
+using namespace nbody;
+
+namespace {
+
+struct Variant {
+    int ipl;        // i-particles per work-item
+    int target;     // desired work items per force call
+    int kmax;       // largest j-split
+};
+
+}  // namespace
+
+struct nb_ctx {
+    int32_t n = 0;
+    double eps = 0.0;
+    int32_t lmin = 0, lmax = 0, prec = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+    nb_state st{};
+    bool bound = false;
+    bool predicted = false;
+    bool forced = false;
+    int device = 0;
+    int num_cu = 256;
+
+    // library-owned device buffers
+    void *jbuf = nullptr;
+    JStreamView js{};
+    double *acc1 = nullptr, *jerk1 = nullptr, *pot1 = nullptr;  // block force outputs, ld = n
+    double *partial = nullptr;
+    int64_t partial_rows = 0;
+    int32_t *active = nullptr;
+    double *crit = nullptr;
+    int64_t *wgmin = nullptr;
+    int32_t *cnt = nullptr;
+    DevControl *ctl = nullptr;
+    double *exp_ = nullptr, *evp = nullptr, *ew = nullptr, *ek = nullptr, *eout = nullptr;
+    int64_t *t_zero = nullptr;
+
+    int32_t sched_groups = 1, sched_chunk = 1;
+    Variant var{2, 4096, 64};
+
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    double graph_eta = -1.0;
+    int32_t graph_steps = 0;
+
+    // force-kernel timing (HIP events on the context stream), off by default
+    bool profile = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+
+    std::string err;
+};
+
+namespace {
+
+nb_status fail(nb_ctx *c, nb_status s, const char *fmt, ...) {
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define HIP_OK(ctx, call)                                                                    \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), NB_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+#define LAUNCH_OK(ctx)                                                                       \
+    do {                                                                                     \
+        hipError_t e_ = hipGetLastError();                                                   \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), NB_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+int32_t grid_for(int64_t n, int32_t cap) {
+    int64_t g = (n + WG - 1) / WG;
+    if (g < 1) g = 1;
+    return (int32_t)std::min<int64_t>(g, cap);
+}
+
+StateView state_view(const nb_ctx *c) {
+    return StateView{c->st.x, c->st.v, c->st.a, c->st.k, c->st.m, c->st.tick, c->n,
+                     std::ldexp(1.0, -c->lmax)};
+}
+
+StateRW state_rw(const nb_ctx *c) {
+    return StateRW{c->st.x, c->st.v, c->st.a, c->st.k, c->st.m, c->st.pot, c->st.tick,
+                   c->st.level, c->n, std::ldexp(1.0, -c->lmax)};
+}
+
+SchedView sched_view(const nb_ctx *c) {
+    return SchedView{c->st.tick, c->st.level, c->n, c->lmax, c->sched_chunk, c->sched_groups,
+                     c->wgmin, c->cnt, c->active};
+}
+
+// Heuristic variant table per size class (the tuner may overwrite it).
+Variant default_variant(int32_t n, int prec, int num_cu) {
+    Variant v;
+    v.ipl = (prec == NB_FP32 && n >= 16384) ? 2 : 1;
+    // enough equal work items for several rounds over all compute units
+    v.target = num_cu * 16;
+    v.kmax = 256;
+    return v;
+}
+
+nb_status alloc(nb_ctx *c, void **p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes > 0 ? bytes : 16);
+    if (e != hipSuccess) return fail(c, NB_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    return NB_OK;
+}
+
+nb_status enqueue_predict(nb_ctx *c, const int64_t *t, int guard, hipStream_t s) {
+    const StateView sv = state_view(c);
+    const int32_t grid = grid_for(c->n, 8192);
+    switch (c->prec) {
+        case NB_FP32: predict_kernel<0><<<grid, WG, 0, s>>>(sv, c->js, t, c->ctl, guard); break;
+        case NB_DS: predict_kernel<1><<<grid, WG, 0, s>>>(sv, c->js, t, c->ctl, guard); break;
+        default: predict_kernel<2><<<grid, WG, 0, s>>>(sv, c->js, t, c->ctl, guard); break;
+    }
+    LAUNCH_OK(c);
+    return NB_OK;
+}
+
+template <class M>
+void launch_force_mode(const typename M::Args &pa, const ForceCommon &fc, int ipl, bool soft,
+                       int32_t grid, hipStream_t s) {
+    if (ipl == 2) {
+        if (soft) force_kernel<M, 2, true><<<grid, WG, 0, s>>>(pa, fc);
+        else force_kernel<M, 2, false><<<grid, WG, 0, s>>>(pa, fc);
+    } else {
+        if (soft) force_kernel<M, 1, true><<<grid, WG, 0, s>>>(pa, fc);
+        else force_kernel<M, 1, false><<<grid, WG, 0, s>>>(pa, fc);
+    }
+}
+
+nb_status enqueue_force(nb_ctx *c, const int32_t *ilist, const int32_t *n_i_dev, int32_t n_i_max,
+                        double *acc, double *jerk, double *pot, int32_t ld, hipStream_t s) {
+    const Variant v = c->var;
+    const int ipl = (c->prec == NB_FP32) ? v.ipl : 1;
+    const int32_t ib = WG * ipl;
+    ForceCommon fc{c->n, ilist, n_i_dev, n_i_max, v.target, v.kmax, acc, jerk, pot, ld,
+                   c->partial, c->ctl};
+    // nb_create sized the partial planes for every count up to n under this variant
+    const int32_t kmax = v.kmax;
+    int32_t grid;
+    if (n_i_dev) {
+        grid = std::max(1, v.target);
+        const ForcePlan full = make_plan(n_i_max, c->n, ib, v.target, kmax);
+        grid = std::max(grid, std::min(full.items, 65535));
+    } else {
+        const ForcePlan p = make_plan(n_i_max, c->n, ib, v.target, kmax);
+        grid = std::min(p.items, 1 << 20);
+    }
+    const bool soft = c->eps > 0.0;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->profile) {
+        HIP_OK(c, hipEventCreate(&e0));
+        HIP_OK(c, hipEventCreate(&e1));
+        HIP_OK(c, hipEventRecord(e0, s));
+    }
+    switch (c->prec) {
+        case NB_FP32: {
+            ModeF32::Args pa{c->js.px, c->js.py, c->js.pz, c->js.vm, (float)(c->eps * c->eps)};
+            launch_force_mode<ModeF32>(pa, fc, ipl, soft, grid, s);
+            break;
+        }
+        case NB_DS: {
+            const double e2 = c->eps * c->eps;
+            const float h = (float)e2;
+            ModeDS::Args pa{c->js.q0, c->js.q1, c->js.q2, c->js.q3, ds{h, (float)(e2 - (double)h)}};
+            launch_force_mode<ModeDS>(pa, fc, 1, soft, grid, s);
+            break;
+        }
+        default: {
+            ModeF64::Args pa{c->js.px, c->js.py, c->js.pz, c->js.pm, c->js.vx, c->js.vy, c->js.vz,
+                             c->eps * c->eps};
+            launch_force_mode<ModeF64>(pa, fc, 1, soft, grid, s);
+            break;
+        }
+    }
+    LAUNCH_OK(c);
+    if (c->profile) {
+        HIP_OK(c, hipEventRecord(e1, s));
+        c->ev.emplace_back(e0, e1);
+    }
+    // second pass: a no-op when the plan has K == 1
+    const int32_t rgrid = grid_for(n_i_max, 4096);
+    force_reduce<<<rgrid, WG, 0, s>>>(fc, ib);
+    LAUNCH_OK(c);
+    return NB_OK;
+}
+
+nb_status enqueue_schedule(nb_ctx *c, double eta, hipStream_t s) {
+    const StateRW rw = state_rw(c);
+    sched_newlevel<<<grid_for(c->n, 2048), WG, 0, s>>>(rw, c->active, c->crit, eta, c->lmin,
+                                                        c->lmax, c->ctl);
+    LAUNCH_OK(c);
+    const SchedView sv = sched_view(c);
+    sched_min<<<c->sched_groups, WG, 0, s>>>(sv);
+    LAUNCH_OK(c);
+    sched_count<<<c->sched_groups, WG, 0, s>>>(sv, c->ctl);
+    LAUNCH_OK(c);
+    sched_scatter<<<c->sched_groups, WG, 0, s>>>(sv, c->ctl);
+    LAUNCH_OK(c);
+    return NB_OK;
+}
+
+nb_status enqueue_correct(nb_ctx *c, const double *acc, const double *jerk, const double *pot,
+                          hipStream_t s) {
+    correct_kernel<<<grid_for(c->n, 2048), WG, 0, s>>>(state_rw(c), c->active, acc, jerk, pot,
+                                                        c->n, c->crit, c->ctl);
+    LAUNCH_OK(c);
+    return NB_OK;
+}
+
+nb_status enqueue_step(nb_ctx *c, double eta, hipStream_t s) {
+    nb_status r;
+    if ((r = enqueue_schedule(c, eta, s)) != NB_OK) return r;
+    if ((r = enqueue_predict(c, nullptr, 1, s)) != NB_OK) return r;
+    if ((r = enqueue_force(c, c->active, &c->ctl->n_act, c->n, c->acc1, c->jerk1, c->pot1, c->n,
+                           s)) != NB_OK)
+        return r;
+    return enqueue_correct(c, c->acc1, c->jerk1, c->pot1, s);
+}
+
+nb_status latched(nb_ctx *c) {
+    DevControl h;
+    HIP_OK(c, hipMemcpyAsync(&h, c->ctl, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    if (h.flag_nonfinite) return fail(c, NB_ENONFINITE, "non-finite force or state on device");
+    if (h.flag_dtmin) return fail(c, NB_EDTMIN, "time step below 2^-%d requested (clamped)", c->lmax);
+    return NB_OK;
+}
+
+void drop_graph(nb_ctx *c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+    c->graph_steps = 0;
+}
+
+nb_status need(nb_ctx *c, bool bound_required = true) {
+    if (!c) return NB_EINVAL;
+    if (bound_required && !c->bound) return fail(c, NB_ESTATE, "state not bound (call nb_bind)");
+    HIP_OK(c, hipSetDevice(c->device));
+    return NB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nb_version(void) { return "libnbody 0.1 gfx950"; }
+
+const char *nb_last_error(const nb_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t lmax,
+                    int32_t precision) {
+    if (!out) return NB_EINVAL;
+    *out = nullptr;
+    if (n < 1 || n > (1 << 28) || !(eps >= 0.0) || !std::isfinite(eps) || lmin < 0 ||
+        lmax < lmin || lmax > 52 || precision < NB_FP32 || precision > NB_FP64)
+        return NB_EINVAL;
+    nb_ctx *c = new nb_ctx();
+    c->n = n; c->eps = eps; c->lmin = lmin; c->lmax = lmax; c->prec = precision;
+    nb_status r;
+    if (hipGetDevice(&c->device) != hipSuccess) { delete c; return NB_EDEVICE; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cu = prop.multiProcessorCount;
+    c->var = default_variant(n, precision, c->num_cu);
+    const size_t N = (size_t)n;
+    // j-stream: up to 64 bytes per particle
+    if ((r = alloc(c, &c->jbuf, 64 * N)) != NB_OK) { nb_destroy(c); return r; }
+    {
+        char *b = (char *)c->jbuf;
+        if (precision == NB_FP32) {
+            c->js.px = (double *)b; c->js.py = c->js.px + N; c->js.pz = c->js.py + N;
+            c->js.vm = (float4 *)(c->js.pz + N);
+        } else if (precision == NB_DS) {
+            c->js.q0 = (float4 *)b; c->js.q1 = c->js.q0 + N; c->js.q2 = c->js.q1 + N;
+            c->js.q3 = c->js.q2 + N;
+        } else {
+            c->js.px = (double *)b; c->js.py = c->js.px + N; c->js.pz = c->js.py + N;
+            c->js.pm = c->js.pz + N; c->js.vx = c->js.pm + N; c->js.vy = c->js.vx + N;
+            c->js.vz = c->js.vy + N;
+        }
+    }
+    void *p;
+    if ((r = alloc(c, &p, 7 * N * sizeof(double))) != NB_OK) { nb_destroy(c); return r; }
+    c->acc1 = (double *)p; c->jerk1 = c->acc1 + 3 * N; c->pot1 = c->jerk1 + 3 * N;
+    // partial planes: K * P rows for the largest plan any count up to n can produce
+    {
+        int64_t rows = 0;
+        for (int ipl = 1; ipl <= 2; ++ipl) {
+            const int32_t ib = WG * ipl;
+            for (int32_t nb = 1; nb <= (n + ib - 1) / ib; ++nb) {
+                const ForcePlan pl = make_plan(std::min<int64_t>((int64_t)nb * ib, n), n, ib,
+                                               c->var.target, c->var.kmax);
+                if (pl.K > 1) rows = std::max<int64_t>(rows, (int64_t)pl.K * pl.P);
+            }
+        }
+        c->partial_rows = rows;
+        if ((r = alloc(c, &p, (size_t)std::max<int64_t>(rows, 1) * 7 * sizeof(double))) != NB_OK) {
+            nb_destroy(c); return r;
+        }
+        c->partial = (double *)p;
+    }
+    if ((r = alloc(c, &p, N * sizeof(int32_t))) != NB_OK) { nb_destroy(c); return r; }
+    c->active = (int32_t *)p;
+    if ((r = alloc(c, &p, 2 * N * sizeof(double))) != NB_OK) { nb_destroy(c); return r; }
+    c->crit = (double *)p;
+    c->sched_groups = (int32_t)std::min<int64_t>(std::max<int64_t>((N + 4095) / 4096, 1), 1024);
+    c->sched_chunk = (int32_t)((N + c->sched_groups - 1) / c->sched_groups);
+    if ((r = alloc(c, &p, c->sched_groups * sizeof(int64_t))) != NB_OK) { nb_destroy(c); return r; }
+    c->wgmin = (int64_t *)p;
+    if ((r = alloc(c, &p, c->sched_groups * sizeof(int32_t))) != NB_OK) { nb_destroy(c); return r; }
+    c->cnt = (int32_t *)p;
+    if ((r = alloc(c, &p, sizeof(DevControl))) != NB_OK) { nb_destroy(c); return r; }
+    c->ctl = (DevControl *)p;
+    if ((r = alloc(c, &p, (8 * N + 2) * sizeof(double))) != NB_OK) { nb_destroy(c); return r; }
+    c->exp_ = (double *)p; c->evp = c->exp_ + 3 * N; c->ew = c->evp + 3 * N; c->ek = c->ew + N;
+    c->eout = c->ek + N;
+    if ((r = alloc(c, &p, sizeof(int64_t))) != NB_OK) { nb_destroy(c); return r; }
+    c->t_zero = (int64_t *)p;
+    if (hipMemset(c->t_zero, 0, sizeof(int64_t)) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        nb_destroy(c);
+        return NB_EDEVICE;
+    }
+    reset_control<<<1, WG>>>(c->ctl);
+    if (hipDeviceSynchronize() != hipSuccess) { nb_destroy(c); return NB_EDEVICE; }
+    *out = c;
+    return NB_OK;
+}
+
+nb_status nb_destroy(nb_ctx *c) {
+    if (!c) return NB_OK;
+    (void)hipSetDevice(c->device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    (void)hipDeviceSynchronize();
+    drop_graph(c);
+    for (auto &p : c->ev) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    void *bufs[] = {c->jbuf, c->acc1, c->partial, c->active, c->crit, c->wgmin, c->cnt, c->ctl,
+                    c->exp_, c->t_zero};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    delete c;
+    return NB_OK;
+}
+
+nb_status nb_set_stream(nb_ctx *c, void *stream) {
+    if (!c) return NB_EINVAL;
+    c->stream = (hipStream_t)stream;
+    return NB_OK;
+}
+
+nb_status nb_bind(nb_ctx *c, const nb_state *s) {
+    if (!c || !s) return NB_EINVAL;
+    if (!s->x || !s->v || !s->a || !s->k || !s->m || !s->pot || !s->tick || !s->level)
+        return fail(c, NB_EINVAL, "nb_bind: every state array is required");
+    c->st = *s;
+    c->bound = true;
+    c->predicted = false;
+    c->forced = false;
+    drop_graph(c);
+    return NB_OK;
+}
+
+nb_status nb_init(nb_ctx *c, double eta) {
+    nb_status r;
+    if ((r = need(c)) != NB_OK) return r;
+    if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, NB_EINVAL, "eta must be > 0");
+    hipStream_t s = c->stream;
+    reset_control<<<1, WG, 0, s>>>(c->ctl);
+    LAUNCH_OK(c);
+    zero_ticks<<<grid_for(c->n, 4096), WG, 0, s>>>(c->st.tick, c->n);
+    LAUNCH_OK(c);
+    if ((r = enqueue_predict(c, c->t_zero, 0, s)) != NB_OK) return r;
+    if ((r = enqueue_force(c, nullptr, nullptr, c->n, c->acc1, c->jerk1, c->pot1, c->n, s)) != NB_OK)
+        return r;
+    init_levels<<<grid_for(c->n, 4096), WG, 0, s>>>(state_rw(c), c->acc1, c->jerk1, c->pot1, eta,
+                                                      c->lmin, c->lmax, c->ctl);
+    LAUNCH_OK(c);
+    c->predicted = true;
+    c->forced = false;
+    return enqueue_schedule(c, eta, s);
+}
+
+nb_status nb_schedule_block(nb_ctx *c, double eta) {
+    nb_status r;
+    if ((r = need(c)) != NB_OK) return r;
+    if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, NB_EINVAL, "eta must be > 0");
+    return enqueue_schedule(c, eta, c->stream);
+}
+
+nb_status nb_active(nb_ctx *c, const int32_t **idx, const int32_t **n_act) {
+    if (!c || !idx || !n_act) return NB_EINVAL;
+    *idx = c->active;
+    *n_act = &c->ctl->n_act;
+    return NB_OK;
+}
+
+nb_status nb_predict(nb_ctx *c, const int64_t *t) {
+    nb_status r;
+    if ((r = need(c)) != NB_OK) return r;
+    if ((r = enqueue_predict(c, t, 0, c->stream)) != NB_OK) return r;
+    c->predicted = true;
+    return NB_OK;
+}
+
+nb_status nb_force(nb_ctx *c, const int32_t *i_idx, const int32_t *n_i, int32_t n_i_max,
+                   double *acc, double *jerk, double *pot) {
+    nb_status r;
+    if ((r = need(c)) != NB_OK) return r;
+    if (!c->predicted) return fail(c, NB_ESTATE, "nb_force before nb_predict");
+    if (!acc || !jerk || !pot) return fail(c, NB_EINVAL, "nb_force: output pointers required");
+    if (n_i_max < 0 || n_i_max > c->n)
+        return fail(c, NB_EINVAL, "nb_force: n_i_max %d outside [0, %d]", n_i_max, c->n);
+    if (!i_idx && !n_i && n_i_max == 0) return NB_OK;
+    if ((r = enqueue_force(c, i_idx, n_i, n_i_max, acc, jerk, pot, n_i_max, c->stream)) != NB_OK)
+        return r;
+    c->forced = true;
+    return NB_OK;
+}
+
+nb_status nb_correct(nb_ctx *c, const double *acc, const double *jerk, const double *pot) {
+    nb_status r;
+    if ((r = need(c)) != NB_OK) return r;
+    if (!acc || !jerk || !pot) return fail(c, NB_EINVAL, "nb_correct: force arrays required");
+    return enqueue_correct(c, acc, jerk, pot, c->stream);
+}
+
+nb_status nb_step(nb_ctx *c, double eta, int32_t nsteps, int32_t use_graph) {
+    nb_status r;
+    if ((r = need(c)) != NB_OK) return r;
+    if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, NB_EINVAL, "eta must be > 0");
+    if (nsteps < 0) return fail(c, NB_EINVAL, "nsteps < 0");
+    if (!use_graph || c->profile) {  // timing events are recorded on eager launches only
+        for (int32_t i = 0; i < nsteps; ++i)
+            if ((r = enqueue_step(c, eta, c->stream)) != NB_OK) return r;
+        c->predicted = true;
+        return NB_OK;
+    }
+    // One captured step, replayed nsteps times (kernel arguments bake in eta).
+    if (!c->gexec || c->graph_eta != eta) {
+        drop_graph(c);
+        HIP_OK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        nb_status rs = enqueue_step(c, eta, c->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (rs != NB_OK) { if (g) (void)hipGraphDestroy(g); return rs; }
+        if (e != hipSuccess) return fail(c, NB_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+        c->graph = g;
+        HIP_OK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+        c->graph_eta = eta;
+        c->graph_steps = 1;
+    }
+    for (int32_t i = 0; i < nsteps; ++i) HIP_OK(c, hipGraphLaunch(c->gexec, c->stream));
+    c->predicted = true;
+    return NB_OK;
+}
+
+nb_status nb_run(nb_ctx *c, double eta, int64_t t_end, int64_t max_steps, int32_t chunk,
+                 int32_t use_graph) {
+    nb_status r;
+    if ((r = need(c)) != NB_OK) return r;
+    if (chunk < 1) return fail(c, NB_EINVAL, "chunk must be >= 1");
+    set_t_end<<<1, WG, 0, c->stream>>>(c->ctl, t_end);
+    LAUNCH_OK(c);
+    int64_t done_steps = 0;
+    for (;;) {
+        int32_t k = chunk;
+        if (max_steps > 0) k = (int32_t)std::min<int64_t>(k, max_steps - done_steps);
+        if (k <= 0) break;
+        if ((r = nb_step(c, eta, k, use_graph)) != NB_OK) return r;
+        done_steps += k;
+        DevControl h;
+        HIP_OK(c, hipMemcpyAsync(&h, c->ctl, sizeof h, hipMemcpyDeviceToHost, c->stream));
+        HIP_OK(c, hipStreamSynchronize(c->stream));
+        if (h.flag_nonfinite) return fail(c, NB_ENONFINITE, "non-finite force or state on device");
+        if (h.done) break;
+    }
+    // leave the scheduler open-ended again
+    set_t_end<<<1, WG, 0, c->stream>>>(c->ctl, INT64_MAX);
+    LAUNCH_OK(c);
+    return latched(c);
+}
+
+nb_status nb_energy(nb_ctx *c, double *ekin, double *epot) {
+    nb_status r;
+    if ((r = need(c)) != NB_OK) return r;
+    if (!ekin || !epot) return fail(c, NB_EINVAL, "nb_energy: host outputs required");
+    hipStream_t s = c->stream;
+    energy_predict<<<grid_for(c->n, 8192), WG, 0, s>>>(state_view(c), c->ctl, c->exp_, c->evp);
+    LAUNCH_OK(c);
+    energy_pairs<<<grid_for(c->n, 1 << 20), WG, 0, s>>>(c->exp_, c->evp, c->st.m, c->n,
+                                                         c->eps * c->eps, c->ew, c->ek);
+    LAUNCH_OK(c);
+    energy_reduce<<<1, 1024, 0, s>>>(c->ew, c->ek, c->n, c->eout);
+    LAUNCH_OK(c);
+    double h[2];
+    HIP_OK(c, hipMemcpyAsync(h, c->eout, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_OK(c, hipStreamSynchronize(s));
+    *ekin = h[0];
+    *epot = h[1];
+    return latched(c);
+}
+
+nb_status nb_read_control(nb_ctx *c, nb_control *out) {
+    if (!c || !out) return NB_EINVAL;
+    HIP_OK(c, hipSetDevice(c->device));
+    DevControl h;
+    HIP_OK(c, hipMemcpyAsync(&h, c->ctl, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    out->t_cur = h.t_cur; out->t_next = h.t_next; out->t_end = h.t_end;
+    out->n_steps = h.n_steps; out->n_active_sum = h.n_active_sum; out->n_act = h.n_act;
+    out->flags = (h.flag_nonfinite ? 1 : 0) | (h.flag_dtmin ? 2 : 0);
+    if (h.flag_nonfinite) return fail(c, NB_ENONFINITE, "non-finite force or state on device");
+    if (h.flag_dtmin) return fail(c, NB_EDTMIN, "time step below 2^-%d requested (clamped)", c->lmax);
+    return NB_OK;
+}
+
+nb_status nb_profile(nb_ctx *c, int32_t enable) {
+    if (!c) return NB_EINVAL;
+    HIP_OK(c, hipSetDevice(c->device));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    for (auto &p : c->ev) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    c->ev.clear();
+    c->profile = enable != 0;
+    return NB_OK;
+}
+
+nb_status nb_profile_read(nb_ctx *c, double *ms_total, int64_t *launches) {
+    if (!c || !ms_total || !launches) return NB_EINVAL;
+    HIP_OK(c, hipSetDevice(c->device));
+    HIP_OK(c, hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    for (auto &p : c->ev) {
+        float ms = 0.f;
+        HIP_OK(c, hipEventElapsedTime(&ms, p.first, p.second));
+        tot += ms;
+    }
+    *ms_total = tot;
+    *launches = (int64_t)c->ev.size();
+    return NB_OK;
+}
+
+nb_status nb_sync(nb_ctx *c) {
+    if (!c) return NB_EINVAL;
+    HIP_OK(c, hipSetDevice(c->device));
+    return latched(c);
+}
+
+}  // extern "C"

@@ -1,0 +1,301 @@
+"""Python binding of libnbody (include/nbody.h): argument marshalling only.
+
+Device memory and streams come from PyTorch (ROCm build); every step of the computation runs in
+the library's HIP kernels.  The functions and methods carry the C ABI's names.  If the shared
+library has not been built this module raises on first use: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "lib", "libnbody.so")
+
+NB_OK, NB_EINVAL, NB_EDEVICE, NB_ENOMEM, NB_ESTATE, NB_ENONFINITE, NB_EDTMIN = 0, -1, -2, -3, -4, -5, -6
+PRECISIONS = {"fp32": 0, "ds": 1, "fp64": 2}
+_STATUS_NAMES = {0: "NB_OK", -1: "NB_EINVAL", -2: "NB_EDEVICE", -3: "NB_ENOMEM", -4: "NB_ESTATE",
+                 -5: "NB_ENONFINITE", -6: "NB_EDTMIN"}
+
+
+class NBodyError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class nb_state(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_void_p), ("v", ctypes.c_void_p), ("a", ctypes.c_void_p),
+                ("k", ctypes.c_void_p), ("m", ctypes.c_void_p), ("pot", ctypes.c_void_p),
+                ("tick", ctypes.c_void_p), ("level", ctypes.c_void_p)]
+
+
+class nb_control(ctypes.Structure):
+    _fields_ = [("t_cur", ctypes.c_int64), ("t_next", ctypes.c_int64), ("t_end", ctypes.c_int64),
+                ("n_steps", ctypes.c_int64), ("n_active_sum", ctypes.c_int64),
+                ("n_act", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+EXPORTS = ["nb_create", "nb_destroy", "nb_set_stream", "nb_bind", "nb_init",
+           "nb_schedule_block", "nb_active", "nb_predict", "nb_force", "nb_correct", "nb_step",
+           "nb_run", "nb_energy", "nb_read_control", "nb_profile", "nb_profile_read", "nb_sync",
+           "nb_last_error", "nb_version"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libnbody.so and declare its signatures.  Raises if it is not built."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it first "
+                           "(python -m paper_astro_ph_0702058_amd.build)")
+    # torch brings its own HIP runtime (same soname); loading it first makes the library bind
+    # to that one, so that one runtime owns every device pointer in the process.
+    _torch()
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "nb_create": [ctypes.POINTER(P), I32, D, I32, I32, I32],
+        "nb_destroy": [P],
+        "nb_set_stream": [P, P],
+        "nb_bind": [P, ctypes.POINTER(nb_state)],
+        "nb_init": [P, D],
+        "nb_schedule_block": [P, D],
+        "nb_active": [P, ctypes.POINTER(P), ctypes.POINTER(P)],
+        "nb_predict": [P, P],
+        "nb_force": [P, P, P, I32, P, P, P],
+        "nb_correct": [P, P, P, P],
+        "nb_step": [P, D, I32, I32],
+        "nb_run": [P, D, I64, I64, I32, I32],
+        "nb_energy": [P, ctypes.POINTER(D), ctypes.POINTER(D)],
+        "nb_read_control": [P, ctypes.POINTER(nb_control)],
+        "nb_profile": [P, I32],
+        "nb_profile_read": [P, ctypes.POINTER(D), ctypes.POINTER(I64)],
+        "nb_sync": [P],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.nb_last_error.argtypes = [P]
+    lib.nb_last_error.restype = ctypes.c_char_p
+    lib.nb_version.argtypes = []
+    lib.nb_version.restype = ctypes.c_char_p
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def read_device_int32(addr: int, count: int) -> np.ndarray:
+    """Copy `count` int32 values at device address `addr` to a new host array (synchronising),
+    with the HIP runtime the library is bound to."""
+    lib = load_library()
+    out = np.empty(int(count), np.int32)
+    if count > 0:
+        _torch().cuda.synchronize()
+        f = lib.hipMemcpy
+        f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        f.restype = ctypes.c_int
+        rc = f(out.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p(addr), 4 * int(count), 2)
+        if rc != 0:
+            raise NBodyError(NB_EDEVICE, f"hipMemcpy failed ({rc})")
+    return out
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class DeviceState:
+    """FP64 master state on the GPU as torch tensors, structure-of-arrays:
+    x, v, a, k: (3, n) float64; m, pot: (n,) float64; tick: (n,) int64; level: (n,) int32."""
+
+    def __init__(self, x, v, m, device="cuda"):
+        torch = _torch()
+        x = np.asarray(x, np.float64).reshape(-1, 3)
+        v = np.asarray(v, np.float64).reshape(-1, 3)
+        self.n = x.shape[0]
+        dev = torch.device(device)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.x = torch.tensor(np.ascontiguousarray(x.T), **f64)
+        self.v = torch.tensor(np.ascontiguousarray(v.T), **f64)
+        self.m = torch.tensor(np.asarray(m, np.float64), **f64)
+        self.a = torch.zeros((3, self.n), **f64)
+        self.k = torch.zeros((3, self.n), **f64)
+        self.pot = torch.zeros(self.n, **f64)
+        self.tick = torch.zeros(self.n, dtype=torch.int64, device=dev)
+        self.level = torch.zeros(self.n, dtype=torch.int32, device=dev)
+
+    def as_struct(self):
+        return nb_state(*(t.data_ptr() for t in
+                          (self.x, self.v, self.a, self.k, self.m, self.pot, self.tick, self.level)))
+
+    def numpy(self):
+        """(x, v, a, k) as (n, 3) numpy arrays plus m, pot, tick, level."""
+        g = lambda t: t.detach().cpu().numpy()
+        return dict(x=g(self.x).T.copy(), v=g(self.v).T.copy(), a=g(self.a).T.copy(),
+                    k=g(self.k).T.copy(), m=g(self.m), pot=g(self.pot), tick=g(self.tick),
+                    level=g(self.level))
+
+
+@dataclass
+class Control:
+    t_cur: int
+    t_next: int
+    t_end: int
+    n_steps: int
+    n_active_sum: int
+    n_act: int
+    flags: int
+
+
+class Context:
+    """One libnbody context: n particles, softening eps, steps in [2^-lmax, 2^-lmin]."""
+
+    def __init__(self, n, eps, lmin=3, lmax=26, precision="fp32", stream=None):
+        self.lib = load_library()
+        self.n = int(n)
+        self.eps = float(eps)
+        self.lmin, self.lmax = int(lmin), int(lmax)
+        self.precision = precision
+        h = ctypes.c_void_p()
+        self._check(self.lib.nb_create(ctypes.byref(h), self.n, self.eps, self.lmin, self.lmax,
+                                       PRECISIONS[precision]), ctx=None)
+        self.h = h
+        self.state = None
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.nb_set_stream(s)
+
+    # -- plumbing
+    def _check(self, status, ctx="self"):
+        if status != NB_OK:
+            msg = ""
+            if ctx is not None and getattr(self, "h", None):
+                msg = self.lib.nb_last_error(self.h).decode()
+            raise NBodyError(status, msg)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- C ABI
+    def nb_set_stream(self, stream):
+        self.stream = stream
+        self._check(self.lib.nb_set_stream(self.h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def nb_bind(self, state: DeviceState):
+        assert state.n == self.n
+        self.state = state
+        self._struct = state.as_struct()
+        self._check(self.lib.nb_bind(self.h, ctypes.byref(self._struct)))
+
+    def nb_init(self, eta):
+        self._check(self.lib.nb_init(self.h, float(eta)))
+
+    def nb_schedule_block(self, eta):
+        self._check(self.lib.nb_schedule_block(self.h, float(eta)))
+
+    def nb_active(self):
+        """(device address of the int32 block list, device address of its int32 count)."""
+        idx, cnt = ctypes.c_void_p(), ctypes.c_void_p()
+        self._check(self.lib.nb_active(self.h, ctypes.byref(idx), ctypes.byref(cnt)))
+        return idx.value, cnt.value
+
+    def nb_predict(self, t=None):
+        """Predict all particles to the device int64 tensor t (ticks), or to the block time."""
+        self._check(self.lib.nb_predict(self.h, _ptr(t)))
+
+    def nb_force(self, acc, jerk, pot, i_idx=None, n_i=None, n_i_max=None):
+        """acc, jerk: (3, n_i_max) float64 tensors; pot: (n_i_max,).  i_idx: int32 tensor or a
+        device address; n_i: int32 device tensor/address (or None = n_i_max)."""
+        n_i_max = acc.shape[1] if n_i_max is None else int(n_i_max)
+        assert acc.shape == (3, n_i_max) and jerk.shape == (3, n_i_max) and pot.shape == (n_i_max,)
+        for t in (acc, jerk, pot):
+            assert t.dtype == _torch().float64 and t.is_contiguous()
+        ii = ctypes.c_void_p(i_idx) if isinstance(i_idx, int) else _ptr(i_idx)
+        nn = ctypes.c_void_p(n_i) if isinstance(n_i, int) else _ptr(n_i)
+        self._check(self.lib.nb_force(self.h, ii, nn, n_i_max, _ptr(acc), _ptr(jerk), _ptr(pot)))
+
+    def nb_correct(self, acc, jerk, pot):
+        self._check(self.lib.nb_correct(self.h, _ptr(acc), _ptr(jerk), _ptr(pot)))
+
+    def nb_step(self, eta, nsteps=1, use_graph=True):
+        self._check(self.lib.nb_step(self.h, float(eta), int(nsteps), int(bool(use_graph))))
+
+    def nb_run(self, eta, t_end, max_steps=0, chunk=64, use_graph=True):
+        """Advance to time t_end (time units, converted to ticks)."""
+        t_ticks = int(round(float(t_end) * 2.0 ** self.lmax))
+        self._check(self.lib.nb_run(self.h, float(eta), t_ticks, int(max_steps), int(chunk),
+                                    int(bool(use_graph))))
+
+    def nb_energy(self):
+        ek, ep = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.nb_energy(self.h, ctypes.byref(ek), ctypes.byref(ep)))
+        return ek.value, ep.value
+
+    def nb_read_control(self) -> Control:
+        c = nb_control()
+        self._check(self.lib.nb_read_control(self.h, ctypes.byref(c)))
+        return Control(c.t_cur, c.t_next, c.t_end, c.n_steps, c.n_active_sum, c.n_act, c.flags)
+
+    def nb_profile(self, enable=True):
+        self._check(self.lib.nb_profile(self.h, int(bool(enable))))
+
+    def nb_profile_read(self):
+        """(total force-kernel milliseconds, number of timed launches)."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(self.lib.nb_profile_read(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def nb_sync(self):
+        self._check(self.lib.nb_sync(self.h))
+
+
+def force_on_state(x, v, m, eps, precision="fp32", idx=None, device="cuda"):
+    """Acceleration, jerk and potential of particles ``idx`` (all if None) of the state
+    (x, v, m) at its own time, through nb_predict (zero time offset) and nb_force.
+    Returns numpy (acc (n_i,3), jerk (n_i,3), pot (n_i,))."""
+    torch = _torch()
+    st = DeviceState(x, v, m, device=device)
+    with Context(st.n, eps, precision=precision) as ctx:
+        ctx.nb_bind(st)
+        t0 = torch.zeros(1, dtype=torch.int64, device=device)
+        ctx.nb_predict(t0)
+        if idx is None:
+            n_i = st.n
+            ii = None
+        else:
+            ii = torch.as_tensor(np.asarray(idx, np.int32), device=device)
+            n_i = ii.numel()
+        acc = torch.zeros((3, n_i), dtype=torch.float64, device=device)
+        jerk = torch.zeros_like(acc)
+        pot = torch.zeros(n_i, dtype=torch.float64, device=device)
+        if n_i > 0:
+            ctx.nb_force(acc, jerk, pot, i_idx=ii)
+        ctx.nb_sync()
+        return acc.cpu().numpy().T.copy(), jerk.cpu().numpy().T.copy(), pot.cpu().numpy()

@@ -1,0 +1,153 @@
+"""GPU parity of the force path (nb_predict + nb_force through the C ABI) against the FP64 oracle.
+
+Error measure (rms relative, over the listed i):  e_a = sqrt(mean_i |a_i - a_i^ref|^2 / |a_i^ref|^2),
+likewise for the jerk and the potential.  Tolerances:
+  fp32: acc 2e-6 (the target for single-precision arithmetic), jerk 1e-5, pot 2e-6;
+  ds:   acc 1e-11 (the target for double-single arithmetic), jerk 1e-10, pot 1e-11;
+  fp64: 1e-13 for all three (a few ulp per term; tile sums keep growth well below that).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_astro_ph_0702058_amd import nbody
+from paper_astro_ph_0702058_amd.plummer import plummer, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": (2e-6, 1e-5, 2e-6), "ds": (1e-11, 1e-10, 1e-11), "fp64": (1e-13, 1e-13, 1e-13)}
+
+
+def rms_rel(got, ref):
+    got = np.asarray(got); ref = np.asarray(ref)
+    if got.ndim == 1:
+        return float(np.sqrt(np.mean(((got - ref) / ref) ** 2)))
+    num = np.sum((got - ref) ** 2, axis=1)
+    den = np.sum(ref ** 2, axis=1)
+    return float(np.sqrt(np.mean(num / den)))
+
+
+def check(prec, got, ref, label=""):
+    ta, tk, tp = TOL[prec]
+    ea, ek, ep = rms_rel(got[0], ref[0]), rms_rel(got[1], ref[1]), rms_rel(got[2], ref[2])
+    print(f"{label} {prec}: e_acc={ea:.3e} e_jerk={ek:.3e} e_pot={ep:.3e}", flush=True)
+    assert ea <= ta and ek <= tk and ep <= tp, (ea, ek, ep)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "ds", "fp64"])
+def test_force_all_i_ragged(prec):
+    """N = 1000 (three full tiles plus a ragged tail), all i against all j."""
+    x, v, m = plummer(1000, 11)
+    eps = 1 / 256
+    got = nbody.force_on_state(x, v, m, eps, prec)
+    ref = oracle.force(x, v, m, eps * eps)
+    check(prec, got, ref, "N=1000")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "ds", "fp64"])
+def test_force_subset_uses_j_split(prec):
+    """Few i against many j: the work is split over j-ranges and summed in a second pass."""
+    n = 20000
+    x, v, m = plummer(n, 12)
+    eps = 1e-3
+    idx = sample_indices(n, 300, 5)
+    got = nbody.force_on_state(x, v, m, eps, prec, idx=idx)
+    ref = oracle.force(x, v, m, eps * eps, idx=idx)
+    check(prec, got, ref, "N=20000 j-split")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "ds", "fp64"])
+def test_force_unsoftened(prec):
+    """eps = 0: the self pair is masked out instead of subtracted."""
+    x, v, m = plummer(700, 13)
+    got = nbody.force_on_state(x, v, m, 0.0, prec)
+    ref = oracle.force(x, v, m, 0.0)
+    check(prec, got, ref, "eps=0")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "ds", "fp64"])
+def test_force_degenerate_sizes(prec):
+    # a single particle feels nothing
+    a, k, p = nbody.force_on_state(np.array([[0.3, -0.2, 0.1]]), np.array([[1.0, 0, 0]]),
+                                   np.array([1.0]), 0.01, prec)
+    assert np.all(a == 0) and np.all(k == 0) and np.all(p == 0)
+    # the two-body closed form: d = (1,2,2), eps^2 = 16, m_j = 1, u = (0,0,1)
+    x = np.array([[0.0, 0, 0], [1.0, 2, 2]]); v = np.array([[0.0, 0, 0], [0.0, 0, 1]])
+    m = np.array([1.0, 1.0])
+    a, k, p = nbody.force_on_state(x, v, m, 4.0, prec)
+    tol = 1e-6 if prec == "fp32" else 1e-14
+    np.testing.assert_allclose(a[0], [0.008, 0.016, 0.016], rtol=tol, atol=0)
+    np.testing.assert_allclose(k[0], [-0.00192, -0.00384, 0.00416], rtol=tol, atol=1e-20)
+    np.testing.assert_allclose(p, [-0.2, -0.2], rtol=tol)
+    np.testing.assert_allclose(a[1], -a[0], rtol=tol)
+    # an empty i-list is a no-op
+    a, k, p = nbody.force_on_state(x, v, m, 4.0, prec, idx=np.zeros(0, np.int32))
+    assert a.shape == (0, 3)
+
+
+def test_force_is_deterministic():
+    x, v, m = plummer(5000, 14)
+    r1 = nbody.force_on_state(x, v, m, 1 / 256, "fp32")
+    r2 = nbody.force_on_state(x, v, m, 1 / 256, "fp32")
+    for a, b in zip(r1, r2):
+        assert np.array_equal(a, b)
+
+
+def test_force_full_size_sampled():
+    """N = 2^20 Plummer sphere, eps = 1/256: the full all-i force in single precision (the
+    launch the benchmark times), checked on 128 sampled rows; double-single on 48 sampled i."""
+    import torch
+    n = 1 << 20
+    x, v, m = plummer(n, 3)
+    eps = 1 / 256
+    idx = sample_indices(n, 128, 21)
+    st = nbody.DeviceState(x, v, m)
+    with nbody.Context(n, eps, precision="fp32") as ctx:
+        ctx.nb_bind(st)
+        t0 = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ctx.nb_predict(t0)
+        acc = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        jerk = torch.zeros_like(acc)
+        pot = torch.zeros(n, dtype=torch.float64, device="cuda")
+        ctx.nb_force(acc, jerk, pot)
+        ctx.nb_sync()
+        ii = torch.as_tensor(idx, device="cuda")
+        got = (acc[:, ii].cpu().numpy().T, jerk[:, ii].cpu().numpy().T, pot[ii].cpu().numpy())
+    ref = oracle.force(x, v, m, eps * eps, idx=idx)
+    check("fp32", got, ref, "N=2^20 sampled")
+    idx2 = idx[:48]
+    got = nbody.force_on_state(x, v, m, eps, "ds", idx=idx2)
+    check("ds", got, tuple(r[:48] for r in ref), "N=2^20 sampled")
+
+
+def test_nonfinite_input_is_reported():
+    """A NaN position makes forces non-finite: the device latches the flag and the next
+    synchronising call reports NB_ENONFINITE (the kernels themselves finish normally)."""
+    import torch
+    x, v, m = plummer(300, 15)
+    x[7, 0] = np.nan
+    st = nbody.DeviceState(x, v, m)
+    with nbody.Context(300, 0.01, precision="fp32") as ctx:
+        ctx.nb_bind(st)
+        ctx.nb_predict(torch.zeros(1, dtype=torch.int64, device="cuda"))
+        acc = torch.zeros((3, 300), dtype=torch.float64, device="cuda")
+        jerk = torch.zeros_like(acc); pot = torch.zeros(300, dtype=torch.float64, device="cuda")
+        ctx.nb_force(acc, jerk, pot)
+        with pytest.raises(nbody.NBodyError) as e:
+            ctx.nb_sync()
+        assert e.value.status == nbody.NB_ENONFINITE
+
+
+def test_argument_errors_on_device():
+    import torch
+    x, v, m = plummer(64, 16)
+    st = nbody.DeviceState(x, v, m)
+    with nbody.Context(64, 0.01) as ctx:
+        acc = torch.zeros((3, 64), dtype=torch.float64, device="cuda")
+        with pytest.raises(nbody.NBodyError) as e:
+            ctx.nb_force(acc, acc, acc[0])          # nothing bound yet
+        assert e.value.status == nbody.NB_ESTATE
+        ctx.nb_bind(st)
+        with pytest.raises(nbody.NBodyError) as e:
+            ctx.nb_force(acc, acc, acc[0])          # not predicted yet
+        assert e.value.status == nbody.NB_ESTATE

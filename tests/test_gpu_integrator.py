@@ -1,0 +1,208 @@
+"""GPU parity of the Hermite block-step path (nb_init, nb_schedule_block, nb_predict, nb_force,
+nb_correct, nb_step, nb_run, nb_energy) against the FP64 oracle, through the C ABI.
+
+Integer results (levels, block lists, block times) must be identical, except that a level may
+differ where the criterion's value lies within the force arithmetic's rounding of a power of
+two (both sides decide in double precision, from forces that differ by that rounding).
+FP64 state after a step: 1e-12 relative (the same formulas in another rounding order, fed by
+forces that agree to ~1e-15).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_astro_ph_0702058_amd import nbody
+from paper_astro_ph_0702058_amd.plummer import plummer
+
+pytestmark = pytest.mark.gpu
+
+LMAX = 26
+BAND = {"fp64": 1e-11, "ds": 1e-9, "fp32": 1e-4}   # relative distance to a power of two
+
+
+def near_power_of_two(dt, band):
+    with np.errstate(divide="ignore", invalid="ignore"):
+        l2 = np.log2(dt)
+    return np.isfinite(l2) & (np.abs(l2 - np.round(l2)) < band / math.log(2))
+
+
+def make(n, seed, eps, prec, lmin):
+    x, v, m = plummer(n, seed)
+    st = nbody.DeviceState(x, v, m)
+    ctx = nbody.Context(n, eps, lmin=lmin, lmax=LMAX, precision=prec)
+    ctx.nb_bind(st)
+    return x, v, m, st, ctx
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_init_levels_and_first_block(prec):
+    n, eps, nu, lmin = 1500, 1 / 256, 0.01, 3
+    x, v, m, st, ctx = make(n, 21, eps, prec, lmin)
+    ctx.nb_init(nu)
+    g = st.numpy()
+    ref = oracle.BlockIntegrator(x, v, m, eps=eps, nu=nu, lmin=lmin)
+    tol = 1e-13 if prec == "fp64" else 2e-5
+    assert np.sqrt(np.mean(np.sum((g["a"] - ref.a) ** 2, 1) / np.sum(ref.a ** 2, 1))) < tol
+    assert np.sqrt(np.mean(np.sum((g["k"] - ref.k) ** 2, 1) / np.sum(ref.k ** 2, 1))) < 10 * tol
+    assert np.all(g["tick"] == 0)
+    dt0 = np.array([oracle.initial_dt(nu, ref.a[i], ref.k[i]) for i in range(n)])
+    diff = g["level"] != ref.level
+    assert not np.any(diff & ~near_power_of_two(dt0, BAND[prec])), np.flatnonzero(diff)
+    # the first block, selected on the device from the device's own levels
+    t_next, blk = oracle.select_block(g["tick"], g["level"], LMAX)
+    c = ctx.nb_read_control()
+    assert c.t_next == t_next and c.n_act == blk.size
+    idx_addr, _ = ctx.nb_active()
+    assert np.array_equal(nbody.read_device_int32(idx_addr, c.n_act), blk)
+    ctx.close()
+
+
+def test_predict_then_force_on_staggered_state():
+    """Particles at different times (ticks that are multiples of their steps) predicted to a
+    common block time, then the force, all in FP64: matches the oracle's predictor + force."""
+    import torch
+    n, eps = 900, 1 / 128
+    x, v, m = plummer(n, 22)
+    rng = np.random.default_rng(3)
+    a = rng.normal(size=(n, 3)); k = rng.normal(size=(n, 3)) * 10
+    level = rng.integers(4, 9, n).astype(np.int32)
+    t_target = 1 << (LMAX - 3)
+    dt_ticks = np.int64(1) << (LMAX - level.astype(np.int64))
+    tick = t_target - dt_ticks * rng.integers(1, 3, n)
+    st = nbody.DeviceState(x, v, m)
+    st.a.copy_(torch.tensor(a.T.copy())); st.k.copy_(torch.tensor(k.T.copy()))
+    st.tick.copy_(torch.tensor(tick)); st.level.copy_(torch.tensor(level))
+    with nbody.Context(n, eps, precision="fp64") as ctx:
+        ctx.nb_bind(st)
+        ctx.nb_predict(torch.tensor([t_target], dtype=torch.int64, device="cuda"))
+        acc = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        jerk = torch.zeros_like(acc); pot = torch.zeros(n, dtype=torch.float64, device="cuda")
+        ctx.nb_force(acc, jerk, pot)
+        ctx.nb_sync()
+    xp, vp = oracle.predict(x, v, a, k, tick, t_target, LMAX)
+    ra, rk, rp = oracle.force(xp, vp, m, eps * eps)
+    ga = acc.cpu().numpy().T
+    assert np.max(np.linalg.norm(ga - ra, axis=1) / np.linalg.norm(ra, axis=1)) < 1e-12
+    gk = jerk.cpu().numpy().T
+    assert np.max(np.linalg.norm(gk - rk, axis=1) / np.linalg.norm(rk, axis=1)) < 1e-11
+    assert np.max(np.abs(pot.cpu().numpy() - rp) / np.abs(rp)) < 1e-13
+
+
+def test_correct_and_new_levels_match_oracle():
+    """One block step with the oracle's own forces fed to nb_correct: the corrected FP64 state
+    and the new levels from nb_schedule_block match the oracle's corrector and rules."""
+    import torch
+    n, eps, nu, lmin = 1200, 1 / 256, 0.01, 3
+    x, v, m, st, ctx = make(n, 23, eps, "fp64", lmin)
+    ctx.nb_init(nu)
+    # run a few device steps so that particles sit at different times
+    ctx.nb_step(nu, 5, use_graph=False)
+    ctx.nb_schedule_block(nu)
+    c = ctx.nb_read_control()
+    g = st.numpy()
+    t_next, blk = oracle.select_block(g["tick"], g["level"], LMAX)
+    assert c.t_next == t_next and c.n_act == blk.size
+    xp, vp = oracle.predict(g["x"], g["v"], g["a"], g["k"], g["tick"], t_next, LMAX)
+    a1, k1, p1 = oracle.force(xp, vp, g["m"], eps * eps, idx=blk)
+    # device: feed the same forces (rows in block order, leading dimension n)
+    A = torch.zeros((3, n), dtype=torch.float64, device="cuda"); A[:, :blk.size] = torch.tensor(a1.T.copy())
+    K = torch.zeros((3, n), dtype=torch.float64, device="cuda"); K[:, :blk.size] = torch.tensor(k1.T.copy())
+    Pt = torch.zeros(n, dtype=torch.float64, device="cuda"); Pt[:blk.size] = torch.tensor(p1)
+    ctx.nb_correct(A, K, Pt)
+    ctx.nb_schedule_block(nu)
+    ctx.nb_sync()
+    h = st.numpy()
+    # oracle corrector on the same inputs
+    X, V, Aa, Kk, Pp = (g[k].copy() for k in ("x", "v", "a", "k", "pot"))
+    crit = oracle.correct(blk, g["level"], xp, vp, a1, k1, p1, X, V, Aa, Kk, Pp)
+    scale_x = np.linalg.norm(X[blk], axis=1)[:, None] + 1e-300
+    assert np.max(np.abs(h["x"][blk] - X[blk]) / scale_x) < 1e-13
+    assert np.max(np.abs(h["v"][blk] - V[blk]) / (np.linalg.norm(V[blk], axis=1)[:, None])) < 1e-12
+    assert np.array_equal(h["a"][blk], a1) and np.array_equal(h["k"][blk], k1)
+    assert np.all(h["tick"][blk] == t_next)
+    dt_raw = np.array([oracle.aarseth_dt(nu, cn, cd) for cn, cd in crit])
+    want = np.array([oracle.next_level(d, l, t_next, lmin, LMAX)
+                     for d, l in zip(dt_raw, g["level"][blk])])
+    diff = h["level"][blk] != want
+    assert not np.any(diff & ~near_power_of_two(dt_raw, 1e-10)), (h["level"][blk][diff], want[diff])
+    others = np.setdiff1d(np.arange(n), blk)
+    assert np.array_equal(h["level"][others], g["level"][others])
+    ctx.close()
+
+
+def test_block_steps_follow_oracle_in_fp64():
+    """30 whole block steps on device (FP64 interaction) follow the oracle step for step."""
+    n, eps, nu, lmin = 256, 1 / 64, 0.01, 4
+    x, v, m, st, ctx = make(n, 24, eps, "fp64", lmin)
+    ctx.nb_init(nu)
+    ref = oracle.BlockIntegrator(x, v, m, eps=eps, nu=nu, lmin=lmin)
+    for s in range(30):
+        ctx.nb_step(nu, 1, use_graph=False)
+        t, blk = ref.step()
+        c = ctx.nb_read_control()
+        assert c.t_cur == t and c.n_steps == s + 1, (s, c, t)
+    g = st.numpy()
+    assert np.array_equal(g["tick"], ref.tick) and np.array_equal(g["level"], ref.level)
+    assert np.max(np.abs(g["x"] - ref.x)) < 1e-11
+    assert np.max(np.abs(g["v"] - ref.v)) < 1e-10
+    ctx.close()
+
+
+def test_graph_replay_equals_eager():
+    """The captured step replayed as a graph gives bitwise the same state as eager launches
+    (40 steps, with synchronisations between replays)."""
+    n, eps, nu = 2000, 1 / 256, 0.01
+    outs = []
+    for graph in (False, True):
+        x, v, m, st, ctx = make(n, 25, eps, "fp32", 3)
+        ctx.nb_init(nu)
+        for _ in range(4):
+            ctx.nb_step(nu, 10, use_graph=graph)
+            ctx.nb_sync()
+        outs.append(st.numpy())
+        ctx.close()
+    for key in ("x", "v", "a", "k", "tick", "level", "pot"):
+        assert np.array_equal(outs[0][key], outs[1][key]), key
+
+
+def test_energy_matches_oracle():
+    n, eps = 3000, 1 / 256
+    x, v, m, st, ctx = make(n, 26, eps, "fp32", 3)
+    ctx.nb_init(0.01)
+    ek, ep = ctx.nb_energy()
+    rk, rp = oracle.energy(x, v, m, eps * eps)
+    assert abs(ek - rk) <= 1e-14 * abs(rk)
+    assert abs(ep - rp) <= 1e-13 * abs(rp)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "ds", "fp32"])
+def test_plummer_1024_to_one_eighth(prec):
+    """N = 1024 Plummer, eps = 1/256, nu = 0.01, dt <= 1/64, integrated to t = 1/8 (graph
+    replay): energy conservation, block statistics and positions against the oracle run."""
+    n, eps, nu, lmin = 1024, 1 / 256, 0.01, 6
+    x, v, m, st, ctx = make(n, 1, eps, prec, lmin)
+    ctx.nb_init(nu)
+    ek0, ep0 = ctx.nb_energy()
+    ctx.nb_run(nu, 0.125, chunk=64, use_graph=True)
+    c = ctx.nb_read_control()
+    ek1, ep1 = ctx.nb_energy()
+    g = st.numpy()
+    ref = oracle.BlockIntegrator(x, v, m, eps=eps, nu=nu, lmin=lmin)
+    e0 = ref.energy()
+    ref.run_until(0.125)
+    de_ref = abs((ref.energy() - e0) / e0)
+    de = abs((ek1 + ep1 - (ek0 + ep0)) / (ek0 + ep0))
+    print(f"{prec}: steps {c.n_steps} vs {ref.n_steps}; mean block {c.n_active_sum / c.n_steps:.2f}"
+          f" vs {ref.n_active_total / ref.n_steps:.2f}; dE/E {de:.3e} vs {de_ref:.3e}", flush=True)
+    assert c.t_cur == 1 << (LMAX - 3) and np.all(g["tick"] == c.t_cur)
+    assert abs(c.n_steps - ref.n_steps) <= 0.05 * ref.n_steps
+    if prec == "fp32":
+        assert de < 1e-6
+    else:
+        assert de < 10 * de_ref + 1e-12
+        assert c.n_steps == ref.n_steps
+        assert np.sqrt(np.mean(np.sum((g["x"] - ref.x) ** 2, 1))) < 1e-8
+    ctx.close()

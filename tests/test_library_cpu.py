@@ -1,0 +1,80 @@
+"""Host-side checks that need no GPU: the C-ABI library loads, exports every entry point the
+header declares, and the product package never reaches the oracle."""
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nbody.h")
+PKG = os.path.join(ROOT, "paper_astro_ph_0702058_amd")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nb_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_astro_ph_0702058_amd import nbody
+    if not os.path.exists(nbody.LIB_PATH):
+        from paper_astro_ph_0702058_amd import build
+        build.build()
+    return nbody.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_astro_ph_0702058_amd import nbody
+    declared = _declared()
+    assert len(declared) >= 19
+    out = subprocess.run(["nm", "-D", "--defined-only", nbody.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (nb_\w+)", out))
+    missing = [d for d in declared if d not in exported]
+    assert not missing, missing
+    assert sorted(nbody.EXPORTS) == declared
+
+
+def test_version_and_argument_errors(lib):
+    import ctypes
+    from paper_astro_ph_0702058_amd import nbody
+    assert b"gfx950" in lib.nb_version()
+    # argument checks happen before any device work
+    assert lib.nb_create(None, 10, 0.1, 3, 26, 0) == nbody.NB_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.nb_create(ctypes.byref(h), 0, 0.1, 3, 26, 0) == nbody.NB_EINVAL
+    assert lib.nb_create(ctypes.byref(h), 10, -1.0, 3, 26, 0) == nbody.NB_EINVAL
+    assert lib.nb_create(ctypes.byref(h), 10, 0.1, 5, 4, 0) == nbody.NB_EINVAL
+    assert lib.nb_create(ctypes.byref(h), 10, 0.1, 3, 26, 7) == nbody.NB_EINVAL
+    assert lib.nb_destroy(None) == nbody.NB_OK
+    assert lib.nb_init(None, 0.01) == nbody.NB_EINVAL
+    assert lib.nb_force(None, None, None, 1, None, None, None) == nbody.NB_EINVAL
+
+
+def test_library_is_gfx950_code_object():
+    from paper_astro_ph_0702058_amd import nbody
+    data = open(nbody.LIB_PATH, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_product_never_imports_oracle():
+    """The product path has no CPU fallback: nothing under the package names the oracle."""
+    for dirpath, _, files in os.walk(PKG):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(from|import)\s+oracle", text, re.M), f
+                assert "nbody_oracle" not in text, f
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_astro_ph_0702058_amd import nbody\n"
+            "try:\n    nbody.load_library(%r)\nexcept RuntimeError as e:\n    print('raised', e)\n"
+            % (ROOT, str(tmp_path / "nope.so")))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
+    assert "raised" in r.stdout
