@@ -57,6 +57,8 @@ def main():
                     help="other interaction arithmetics to time once (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="skip the (untimed) autotuning of the force-kernel variants")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -79,6 +81,15 @@ def main():
 
     ctx = nbody.Context(n, args.eps, lmin=args.lmin, lmax=26, precision=args.precision)
     ctx.nb_bind(st)
+
+    if args.tune:
+        import torch as _t
+        ctx.nb_predict(_t.zeros(1, dtype=_t.int64, device="cuda"))
+        from paper_astro_ph_0702058_amd.tuning import autotune
+        t_tune = time.perf_counter()
+        chosen = autotune(ctx, cache_path=None, reps=1)
+        log(f"[bench] tuned in {time.perf_counter() - t_tune:.1f} s: {chosen}")
+    variant_full, variant_block = ctx.nb_get_variant(0), ctx.nb_get_variant(1)
 
     def step():
         st.x.copy_(x0)
@@ -136,7 +147,8 @@ def main():
                                f"dt_max=2^-{args.lmin}): full force + {args.block_steps} "
                                "block steps",
                    "n": n, "eps": args.eps, "eta": args.eta, "block_steps": args.block_steps,
-                   "precision": args.precision, "interactions_per_step": per_step},
+                   "precision": args.precision, "interactions_per_step": per_step,
+                   "variant_full_force": variant_full, "variant_block_steps": variant_block},
         "roofline": roofline,
         "context": {"paper_8800gtx_interactions_per_s": 1.23e9,
                     "paper_grape6af_interactions_per_s": 2.16e9},

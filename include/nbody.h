@@ -169,6 +169,34 @@ nb_status nb_profile(nb_ctx *ctx, int32_t enable);
  * since profiling was enabled (HOST outputs); synchronising. */
 nb_status nb_profile_read(nb_ctx *ctx, double *ms_total, int64_t *launches);
 
+/* Force-kernel launch variant: i-particles held per work-item (ipl), unroll of the j-loop,
+ * desired number of equal work items per launch (target; the j-range is split K ways when the
+ * i-blocks alone are fewer) and the largest split (kmax).  Compiled: fp32 ipl in {1, 2} and
+ * unroll in {1, 2, 4}; ds and fp64 ipl = 1 and unroll in {1, 2}.  Any choice computes the same
+ * sums up to rounding order. */
+typedef struct {
+    int32_t ipl, unroll, target, kmax;
+} nb_variant;
+
+/* The variant used for force calls on (nearly) all particles (which = 0: nb_init, nb_force
+ * without a device count on more than n/8 particles) or for block-step and other calls
+ * (which = 1). */
+nb_status nb_get_variant(nb_ctx *ctx, int32_t which, nb_variant *out);
+
+/* Replace that variant (HOST struct).  NB_EINVAL if it is not compiled, or if its j-split
+ * would need more partial-sum storage than the context holds (targets up to 16 per compute
+ * unit, kmax <= 256). */
+nb_status nb_set_variant(nb_ctx *ctx, int32_t which, const nb_variant *v);
+
+/* Autotuner: launch every available variant on the first n_i particles against the
+ * predicted stream (which = 0: count passed from the host; which = 1: count read from device
+ * memory, as block steps do), `reps` timed launches each after one untimed, keep the fastest
+ * for `which`, and return it in *best with its mean time in milliseconds (HOST outputs, either
+ * may be NULL).  Overwrites the library's own force outputs only.  Synchronising; requires a
+ * prior nb_predict(). */
+nb_status nb_tune(nb_ctx *ctx, int32_t which, int32_t n_i, int32_t reps, nb_variant *best,
+                  double *best_ms);
+
 /* Wait for the context's stream; returns a latched device error, if any. */
 nb_status nb_sync(nb_ctx *ctx);
 

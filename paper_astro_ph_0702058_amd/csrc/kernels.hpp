@@ -342,11 +342,12 @@ __device__ __forceinline__ bool finite7(const Out7 &o) {
 // ------------------------------------------------------------------------------------------
 // The force kernel.  Each workgroup takes work items (i-block, j-range); each work-item holds
 // IPL i-particles in registers; the workgroup stages TJ j-particles at a time in LDS, and
-// every work-item reads each staged j (an LDS broadcast) and interacts it with its i's.
+// every work-item reads each staged j (an LDS broadcast) and interacts it with its i's; the
+// j-loop is unrolled UNR times.
 // K == 1: results go straight to acc/jerk/pot; K > 1: to the partial planes for
 // force_reduce.  The potential sum is negated on output.
 // ------------------------------------------------------------------------------------------
-template <class M, int IPL, bool SOFT>
+template <class M, int IPL, int UNR, bool SOFT>
 __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCommon fc) {
     __shared__ typename M::Smem sm;
     int32_t n_i = fc.n_i_max;
@@ -378,7 +379,7 @@ __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCom
             typename M::Tile T[IPL];
 #pragma unroll
             for (int p = 0; p < IPL; ++p) T[p] = M::tile_zero();
-#pragma unroll 4
+#pragma unroll UNR
             for (int jj = 0; jj < TJ; ++jj) {
 #pragma unroll
                 for (int p = 0; p < IPL; ++p) M::template interact<SOFT>(ii[p], sm, jj, eps2, T[p]);

@@ -21,11 +21,14 @@ using namespace nbody;
 
 namespace {
 
-struct Variant {
-    int ipl;        // i-particles per work-item
-    int target;     // desired work items per force call
-    int kmax;       // largest j-split
-};
+using Variant = nb_variant;
+
+// Compiled force-kernel variants: i-particles per work-item x j-loop unroll.
+bool variant_compiled(int prec, const Variant &v) {
+    const bool unr_ok = v.unroll == 1 || v.unroll == 2 || v.unroll == 4;
+    if (prec == NB_FP32) return unr_ok && (v.ipl == 1 || v.ipl == 2);
+    return v.ipl == 1 && (v.unroll == 1 || v.unroll == 2);
+}
 
 }  // namespace
 
@@ -57,7 +60,10 @@ struct nb_ctx {
     int64_t *t_zero = nullptr;
 
     int32_t sched_groups = 1, sched_chunk = 1;
-    Variant var{2, 4096, 64};
+    Variant var_full{2, 2, 4096, 256};   // calls on (nearly) all particles
+    Variant var_block{2, 2, 4096, 256};  // block-step calls (device-resident count)
+    int32_t max_target = 4096;           // partial planes are sized for targets up to this
+    int32_t *tune_n = nullptr;           // device count used while tuning
 
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -120,12 +126,13 @@ SchedView sched_view(const nb_ctx *c) {
                      c->wgmin, c->cnt, c->active};
 }
 
-// Heuristic variant table per size class (the tuner may overwrite it).
-Variant default_variant(int32_t n, int prec, int num_cu) {
+// Heuristic defaults per size class; nb_tune() replaces them with measured choices.
+Variant default_variant(int32_t n, int prec, int num_cu, bool block) {
     Variant v;
-    v.ipl = (prec == NB_FP32 && n >= 16384) ? 2 : 1;
-    // enough equal work items for several rounds over all compute units
-    v.target = num_cu * 16;
+    v.ipl = (prec == NB_FP32 && n >= 16384 && !block) ? 2 : 1;
+    if (prec == NB_FP32 && block && n >= (1 << 18)) v.ipl = 2;
+    v.unroll = 2;
+    v.target = num_cu * 16;  // equal work items for several rounds over all compute units
     v.kmax = 256;
     return v;
 }
@@ -148,34 +155,59 @@ nb_status enqueue_predict(nb_ctx *c, const int64_t *t, int guard, hipStream_t s)
     return NB_OK;
 }
 
+template <class M, int IPL, int UNR>
+void launch_soft(const typename M::Args &pa, const ForceCommon &fc, bool soft, int32_t grid,
+                 hipStream_t s) {
+    if (soft) force_kernel<M, IPL, UNR, true><<<grid, WG, 0, s>>>(pa, fc);
+    else force_kernel<M, IPL, UNR, false><<<grid, WG, 0, s>>>(pa, fc);
+}
+
 template <class M>
-void launch_force_mode(const typename M::Args &pa, const ForceCommon &fc, int ipl, bool soft,
-                       int32_t grid, hipStream_t s) {
-    if (ipl == 2) {
-        if (soft) force_kernel<M, 2, true><<<grid, WG, 0, s>>>(pa, fc);
-        else force_kernel<M, 2, false><<<grid, WG, 0, s>>>(pa, fc);
+void launch_ipl1(const typename M::Args &pa, const ForceCommon &fc, const Variant &v, bool soft,
+                 int32_t grid, hipStream_t s) {
+    if (v.unroll == 1) launch_soft<M, 1, 1>(pa, fc, soft, grid, s);
+    else launch_soft<M, 1, 2>(pa, fc, soft, grid, s);
+}
+
+void launch_f32(const ModeF32::Args &pa, const ForceCommon &fc, const Variant &v, bool soft,
+                int32_t grid, hipStream_t s) {
+    if (v.ipl == 2) {
+        if (v.unroll == 1) launch_soft<ModeF32, 2, 1>(pa, fc, soft, grid, s);
+        else if (v.unroll == 2) launch_soft<ModeF32, 2, 2>(pa, fc, soft, grid, s);
+        else launch_soft<ModeF32, 2, 4>(pa, fc, soft, grid, s);
     } else {
-        if (soft) force_kernel<M, 1, true><<<grid, WG, 0, s>>>(pa, fc);
-        else force_kernel<M, 1, false><<<grid, WG, 0, s>>>(pa, fc);
+        if (v.unroll == 1) launch_soft<ModeF32, 1, 1>(pa, fc, soft, grid, s);
+        else if (v.unroll == 2) launch_soft<ModeF32, 1, 2>(pa, fc, soft, grid, s);
+        else launch_soft<ModeF32, 1, 4>(pa, fc, soft, grid, s);
     }
 }
 
-nb_status enqueue_force(nb_ctx *c, const int32_t *ilist, const int32_t *n_i_dev, int32_t n_i_max,
-                        double *acc, double *jerk, double *pot, int32_t ld, hipStream_t s) {
-    const Variant v = c->var;
-    const int ipl = (c->prec == NB_FP32) ? v.ipl : 1;
-    const int32_t ib = WG * ipl;
+// Largest K * P over every i-count up to n, for one variant.
+int64_t partial_rows_for(int32_t n, const Variant &v) {
+    const int32_t ib = WG * v.ipl;
+    int64_t rows = 0;
+    for (int32_t nb = 1; nb <= (n + ib - 1) / ib; ++nb) {
+        const ForcePlan pl = make_plan((int32_t)std::min<int64_t>((int64_t)nb * ib, n), n, ib,
+                                       v.target, v.kmax);
+        if (pl.K > 1) rows = std::max<int64_t>(rows, (int64_t)pl.K * pl.P);
+        if (pl.K == 1) break;  // K only falls as the number of i-blocks grows
+    }
+    return rows;
+}
+
+nb_status enqueue_force(nb_ctx *c, const Variant &v, const int32_t *ilist,
+                        const int32_t *n_i_dev, int32_t n_i_max, double *acc, double *jerk,
+                        double *pot, int32_t ld, hipStream_t s) {
+    const int32_t ib = WG * v.ipl;
     ForceCommon fc{c->n, ilist, n_i_dev, n_i_max, v.target, v.kmax, acc, jerk, pot, ld,
                    c->partial, c->ctl};
-    // nb_create sized the partial planes for every count up to n under this variant
-    const int32_t kmax = v.kmax;
     int32_t grid;
     if (n_i_dev) {
-        grid = std::max(1, v.target);
-        const ForcePlan full = make_plan(n_i_max, c->n, ib, v.target, kmax);
-        grid = std::max(grid, std::min(full.items, 65535));
+        // the count is known only on the device: enough workgroups for any count up to n_i_max
+        const ForcePlan full = make_plan(n_i_max, c->n, ib, v.target, v.kmax);
+        grid = std::max(std::max(1, v.target), std::min(full.items, 65535));
     } else {
-        const ForcePlan p = make_plan(n_i_max, c->n, ib, v.target, kmax);
+        const ForcePlan p = make_plan(n_i_max, c->n, ib, v.target, v.kmax);
         grid = std::min(p.items, 1 << 20);
     }
     const bool soft = c->eps > 0.0;
@@ -188,20 +220,20 @@ nb_status enqueue_force(nb_ctx *c, const int32_t *ilist, const int32_t *n_i_dev,
     switch (c->prec) {
         case NB_FP32: {
             ModeF32::Args pa{c->js.px, c->js.py, c->js.pz, c->js.vm, (float)(c->eps * c->eps)};
-            launch_force_mode<ModeF32>(pa, fc, ipl, soft, grid, s);
+            launch_f32(pa, fc, v, soft, grid, s);
             break;
         }
         case NB_DS: {
             const double e2 = c->eps * c->eps;
             const float h = (float)e2;
             ModeDS::Args pa{c->js.q0, c->js.q1, c->js.q2, c->js.q3, ds{h, (float)(e2 - (double)h)}};
-            launch_force_mode<ModeDS>(pa, fc, 1, soft, grid, s);
+            launch_ipl1<ModeDS>(pa, fc, v, soft, grid, s);
             break;
         }
         default: {
             ModeF64::Args pa{c->js.px, c->js.py, c->js.pz, c->js.pm, c->js.vx, c->js.vy, c->js.vz,
                              c->eps * c->eps};
-            launch_force_mode<ModeF64>(pa, fc, 1, soft, grid, s);
+            launch_ipl1<ModeF64>(pa, fc, v, soft, grid, s);
             break;
         }
     }
@@ -244,8 +276,8 @@ nb_status enqueue_step(nb_ctx *c, double eta, hipStream_t s) {
     nb_status r;
     if ((r = enqueue_schedule(c, eta, s)) != NB_OK) return r;
     if ((r = enqueue_predict(c, nullptr, 1, s)) != NB_OK) return r;
-    if ((r = enqueue_force(c, c->active, &c->ctl->n_act, c->n, c->acc1, c->jerk1, c->pot1, c->n,
-                           s)) != NB_OK)
+    if ((r = enqueue_force(c, c->var_block, c->active, &c->ctl->n_act, c->n, c->acc1, c->jerk1,
+                           c->pot1, c->n, s)) != NB_OK)
         return r;
     return enqueue_correct(c, c->acc1, c->jerk1, c->pot1, s);
 }
@@ -296,7 +328,9 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
         c->num_cu = prop.multiProcessorCount;
-    c->var = default_variant(n, precision, c->num_cu);
+    c->var_full = default_variant(n, precision, c->num_cu, false);
+    c->var_block = default_variant(n, precision, c->num_cu, true);
+    c->max_target = c->num_cu * 16;
     const size_t N = (size_t)n;
     // j-stream: up to 64 bytes per particle
     if ((r = alloc(c, &c->jbuf, 64 * N)) != NB_OK) { nb_destroy(c); return r; }
@@ -317,17 +351,12 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
     void *p;
     if ((r = alloc(c, &p, 7 * N * sizeof(double))) != NB_OK) { nb_destroy(c); return r; }
     c->acc1 = (double *)p; c->jerk1 = c->acc1 + 3 * N; c->pot1 = c->jerk1 + 3 * N;
-    // partial planes: K * P rows for the largest plan any count up to n can produce
+    // partial planes: K * P rows for the largest plan that any variant the tuner may pick
+    // (targets up to max_target, kmax up to 256) can produce for any count up to n
     {
         int64_t rows = 0;
-        for (int ipl = 1; ipl <= 2; ++ipl) {
-            const int32_t ib = WG * ipl;
-            for (int32_t nb = 1; nb <= (n + ib - 1) / ib; ++nb) {
-                const ForcePlan pl = make_plan(std::min<int64_t>((int64_t)nb * ib, n), n, ib,
-                                               c->var.target, c->var.kmax);
-                if (pl.K > 1) rows = std::max<int64_t>(rows, (int64_t)pl.K * pl.P);
-            }
-        }
+        for (int ipl = 1; ipl <= 2; ++ipl)
+            rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->max_target, 256}));
         c->partial_rows = rows;
         if ((r = alloc(c, &p, (size_t)std::max<int64_t>(rows, 1) * 7 * sizeof(double))) != NB_OK) {
             nb_destroy(c); return r;
@@ -349,9 +378,10 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
     if ((r = alloc(c, &p, (8 * N + 2) * sizeof(double))) != NB_OK) { nb_destroy(c); return r; }
     c->exp_ = (double *)p; c->evp = c->exp_ + 3 * N; c->ew = c->evp + 3 * N; c->ek = c->ew + N;
     c->eout = c->ek + N;
-    if ((r = alloc(c, &p, sizeof(int64_t))) != NB_OK) { nb_destroy(c); return r; }
+    if ((r = alloc(c, &p, 2 * sizeof(int64_t))) != NB_OK) { nb_destroy(c); return r; }
     c->t_zero = (int64_t *)p;
-    if (hipMemset(c->t_zero, 0, sizeof(int64_t)) != hipSuccess ||
+    c->tune_n = (int32_t *)(c->t_zero + 1);
+    if (hipMemset(c->t_zero, 0, 2 * sizeof(int64_t)) != hipSuccess ||
         hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         nb_destroy(c);
         return NB_EDEVICE;
@@ -409,7 +439,8 @@ nb_status nb_init(nb_ctx *c, double eta) {
     zero_ticks<<<grid_for(c->n, 4096), WG, 0, s>>>(c->st.tick, c->n);
     LAUNCH_OK(c);
     if ((r = enqueue_predict(c, c->t_zero, 0, s)) != NB_OK) return r;
-    if ((r = enqueue_force(c, nullptr, nullptr, c->n, c->acc1, c->jerk1, c->pot1, c->n, s)) != NB_OK)
+    if ((r = enqueue_force(c, c->var_full, nullptr, nullptr, c->n, c->acc1, c->jerk1, c->pot1,
+                           c->n, s)) != NB_OK)
         return r;
     init_levels<<<grid_for(c->n, 4096), WG, 0, s>>>(state_rw(c), c->acc1, c->jerk1, c->pot1, eta,
                                                       c->lmin, c->lmax, c->ctl);
@@ -450,7 +481,8 @@ nb_status nb_force(nb_ctx *c, const int32_t *i_idx, const int32_t *n_i, int32_t 
     if (n_i_max < 0 || n_i_max > c->n)
         return fail(c, NB_EINVAL, "nb_force: n_i_max %d outside [0, %d]", n_i_max, c->n);
     if (!i_idx && !n_i && n_i_max == 0) return NB_OK;
-    if ((r = enqueue_force(c, i_idx, n_i, n_i_max, acc, jerk, pot, n_i_max, c->stream)) != NB_OK)
+    const Variant &v = (n_i == nullptr && n_i_max > c->n / 8) ? c->var_full : c->var_block;
+    if ((r = enqueue_force(c, v, i_idx, n_i, n_i_max, acc, jerk, pot, n_i_max, c->stream)) != NB_OK)
         return r;
     c->forced = true;
     return NB_OK;
@@ -550,6 +582,80 @@ nb_status nb_read_control(nb_ctx *c, nb_control *out) {
     out->flags = (h.flag_nonfinite ? 1 : 0) | (h.flag_dtmin ? 2 : 0);
     if (h.flag_nonfinite) return fail(c, NB_ENONFINITE, "non-finite force or state on device");
     if (h.flag_dtmin) return fail(c, NB_EDTMIN, "time step below 2^-%d requested (clamped)", c->lmax);
+    return NB_OK;
+}
+
+static bool variant_valid(const nb_ctx *c, const nb_variant &v) {
+    if (!variant_compiled(c->prec, v)) return false;
+    if (v.target < 1 || v.target > c->max_target || v.kmax < 1 || v.kmax > 256) return false;
+    return partial_rows_for(c->n, v) <= c->partial_rows;
+}
+
+nb_status nb_get_variant(nb_ctx *c, int32_t which, nb_variant *out) {
+    if (!c || !out || which < 0 || which > 1) return NB_EINVAL;
+    *out = which == 0 ? c->var_full : c->var_block;
+    return NB_OK;
+}
+
+nb_status nb_set_variant(nb_ctx *c, int32_t which, const nb_variant *v) {
+    if (!c || !v || which < 0 || which > 1) return NB_EINVAL;
+    if (!variant_valid(c, *v))
+        return fail(c, NB_EINVAL, "variant ipl=%d unroll=%d target=%d kmax=%d not available",
+                    v->ipl, v->unroll, v->target, v->kmax);
+    (which == 0 ? c->var_full : c->var_block) = *v;
+    drop_graph(c);
+    return NB_OK;
+}
+
+nb_status nb_tune(nb_ctx *c, int32_t which, int32_t n_i, int32_t reps, nb_variant *best,
+                  double *best_ms) {
+    nb_status r;
+    if ((r = need(c)) != NB_OK) return r;
+    if (which < 0 || which > 1 || n_i < 1 || n_i > c->n || reps < 1)
+        return fail(c, NB_EINVAL, "nb_tune: bad arguments");
+    if (!c->predicted) return fail(c, NB_ESTATE, "nb_tune before nb_predict");
+    hipStream_t s = c->stream;
+    HIP_OK(c, hipMemcpyAsync(c->tune_n, &n_i, sizeof n_i, hipMemcpyHostToDevice, s));
+    const bool was_profiling = c->profile;
+    c->profile = false;
+    hipEvent_t e0, e1;
+    HIP_OK(c, hipEventCreate(&e0));
+    HIP_OK(c, hipEventCreate(&e1));
+    nb_variant bestv = which == 0 ? c->var_full : c->var_block;
+    double bms = 1e300;
+    const int ipls[] = {1, 2}, unrs[] = {1, 2, 4};
+    const int32_t targets[] = {c->num_cu * 4, c->num_cu * 8, c->num_cu * 16};
+    for (int ipl : ipls)
+        for (int unr : unrs)
+            for (int32_t tg : targets) {
+                const nb_variant v{ipl, unr, tg, 256};
+                if (!variant_valid(c, v)) continue;
+                float tot = 0.f;
+                for (int rep = 0; rep <= reps; ++rep) {  // the first launch is not timed
+                    HIP_OK(c, hipEventRecord(e0, s));
+                    if (which == 0)
+                        r = enqueue_force(c, v, nullptr, nullptr, n_i, c->acc1, c->jerk1, c->pot1,
+                                          c->n, s);
+                    else
+                        r = enqueue_force(c, v, nullptr, c->tune_n, c->n, c->acc1, c->jerk1,
+                                          c->pot1, c->n, s);
+                    if (r != NB_OK) { c->profile = was_profiling; return r; }
+                    HIP_OK(c, hipEventRecord(e1, s));
+                    HIP_OK(c, hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIP_OK(c, hipEventElapsedTime(&ms, e0, e1));
+                    if (rep > 0) tot += ms;
+                }
+                const double avg = tot / reps;
+                if (avg < bms) { bms = avg; bestv = v; }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->profile = was_profiling;
+    (which == 0 ? c->var_full : c->var_block) = bestv;
+    drop_graph(c);
+    if (best) *best = bestv;
+    if (best_ms) *best_ms = bms;
     return NB_OK;
 }
 

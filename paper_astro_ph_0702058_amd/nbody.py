@@ -39,10 +39,15 @@ class nb_control(ctypes.Structure):
                 ("n_act", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
+class nb_variant(ctypes.Structure):
+    _fields_ = [("ipl", ctypes.c_int32), ("unroll", ctypes.c_int32), ("target", ctypes.c_int32),
+                ("kmax", ctypes.c_int32)]
+
+
 EXPORTS = ["nb_create", "nb_destroy", "nb_set_stream", "nb_bind", "nb_init",
            "nb_schedule_block", "nb_active", "nb_predict", "nb_force", "nb_correct", "nb_step",
-           "nb_run", "nb_energy", "nb_read_control", "nb_profile", "nb_profile_read", "nb_sync",
-           "nb_last_error", "nb_version"]
+           "nb_run", "nb_energy", "nb_read_control", "nb_get_variant", "nb_set_variant",
+           "nb_tune", "nb_profile", "nb_profile_read", "nb_sync", "nb_last_error", "nb_version"]
 
 _lib = None
 
@@ -75,6 +80,9 @@ def load_library(path: str = LIB_PATH):
         "nb_run": [P, D, I64, I64, I32, I32],
         "nb_energy": [P, ctypes.POINTER(D), ctypes.POINTER(D)],
         "nb_read_control": [P, ctypes.POINTER(nb_control)],
+        "nb_get_variant": [P, I32, ctypes.POINTER(nb_variant)],
+        "nb_set_variant": [P, I32, ctypes.POINTER(nb_variant)],
+        "nb_tune": [P, I32, I32, I32, ctypes.POINTER(nb_variant), ctypes.POINTER(D)],
         "nb_profile": [P, I32],
         "nb_profile_read": [P, ctypes.POINTER(D), ctypes.POINTER(I64)],
         "nb_sync": [P],
@@ -262,6 +270,24 @@ class Context:
         c = nb_control()
         self._check(self.lib.nb_read_control(self.h, ctypes.byref(c)))
         return Control(c.t_cur, c.t_next, c.t_end, c.n_steps, c.n_active_sum, c.n_act, c.flags)
+
+    def nb_get_variant(self, which):
+        v = nb_variant()
+        self._check(self.lib.nb_get_variant(self.h, int(which), ctypes.byref(v)))
+        return dict(ipl=v.ipl, unroll=v.unroll, target=v.target, kmax=v.kmax)
+
+    def nb_set_variant(self, which, variant):
+        v = nb_variant(int(variant["ipl"]), int(variant["unroll"]), int(variant["target"]),
+                       int(variant["kmax"]))
+        self._check(self.lib.nb_set_variant(self.h, int(which), ctypes.byref(v)))
+
+    def nb_tune(self, which, n_i, reps=2):
+        """Time every force-kernel variant and keep the fastest for `which` (0: full-force
+        calls, 1: block-step calls).  Returns (variant dict, mean milliseconds)."""
+        v, ms = nb_variant(), ctypes.c_double()
+        self._check(self.lib.nb_tune(self.h, int(which), int(n_i), int(reps), ctypes.byref(v),
+                                     ctypes.byref(ms)))
+        return dict(ipl=v.ipl, unroll=v.unroll, target=v.target, kmax=v.kmax), ms.value
 
     def nb_profile(self, enable=True):
         self._check(self.lib.nb_profile(self.h, int(bool(enable))))

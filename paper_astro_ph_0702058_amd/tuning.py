@@ -1,0 +1,54 @@
+"""Autotuning of force-kernel launch variants with an on-disk cache.
+
+The library's nb_tune() times every compiled variant (i-particles per work-item, j-loop unroll,
+work items per launch, which fixes the j-split) on the live device.  This module runs it for the
+two call classes of a context -- full-force calls and block-step calls, the latter at the block
+size the paper's fit predicts (0.20 N^0.81) -- and remembers the winners per device name,
+precision and N in a JSON file, so that later contexts of the same shape reuse them.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "libnbody_tune.json")
+
+
+def expected_block_size(n: int) -> int:
+    """Mean block size of the block time-step scheme, 0.20 N^0.81 (the paper's fit, Sec. 5)."""
+    return max(1, min(n, int(round(0.20 * n ** 0.81))))
+
+
+def _key(ctx, which, n_i):
+    import torch
+    name = torch.cuda.get_device_name(torch.cuda.current_device())
+    return f"{name}|{ctx.precision}|eps>0={ctx.eps > 0}|n={ctx.n}|which={which}|n_i={n_i}"
+
+
+def autotune(ctx, cache_path: str | None = DEFAULT_CACHE, reps: int = 2, retune: bool = False):
+    """Tune (or load) both variants of a bound, predicted context.  Returns {which: variant}."""
+    cache = {}
+    if cache_path and os.path.exists(cache_path) and not retune:
+        try:
+            with open(cache_path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    chosen = {}
+    for which, n_i in ((0, ctx.n), (1, expected_block_size(ctx.n))):
+        key = _key(ctx, which, n_i)
+        if key in cache:
+            ctx.nb_set_variant(which, cache[key]["variant"])
+            chosen[which] = cache[key]["variant"]
+            continue
+        v, ms = ctx.nb_tune(which, n_i, reps)
+        cache[key] = {"variant": v, "ms": ms}
+        chosen[which] = v
+    if cache_path:
+        try:
+            os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+            with open(cache_path, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+        except OSError:
+            pass
+    return chosen
