@@ -33,6 +33,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "ds_arith.hpp"):
+        with open(os.path.join(ROOT, "paper_astro_ph_0702058_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel_sym, n, args):
+    """HBM bytes per launch of the full-force kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a plain copy of known
+    size), or None when the summary is for another workload or the kernel source has changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "force_full_fp32_plummer_n1048576_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if (t.get("kernel") != kernel_sym or t.get("n") != n or t.get("eps") != args.eps
+            or t.get("kernel_source_sha256_16") != kernel_source_hash()):
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
 def rms_rel(got, ref):
     import numpy as np
     got, ref = np.asarray(got), np.asarray(ref)
@@ -57,8 +83,9 @@ def main():
                     help="other interaction arithmetics to time once (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-tune", dest="tune", action="store_false",
-                    help="skip the (untimed) autotuning of the force-kernel variants")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune the force-kernel variants first (untimed); default: the "
+                         "library's defaults, which are the tuned choices for MI355X")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -111,8 +138,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     c = ctx.nb_read_control()
-    force_ms, launches = ctx.nb_profile_read()
-    ctx.nb_profile(False)
+    force_ms, launches = ctx.nb_profile_read(-1)
     # interactions: per step N^2 (initial full force) + N * (block sizes); the block sizes of
     # every timed step are identical (same initial state), read from the last one
     per_step = n * n + n * c.n_active_sum
@@ -122,13 +148,31 @@ def main():
     log(f"[bench] {args.steps} steps in {elapsed:.3f} s; block steps sum n_act={c.n_active_sum}"
         f" ({c.n_active_sum / max(c.n_steps, 1):.0f} per block)")
 
-    achieved = FLOP_PER_INTERACTION * interactions / (force_ms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "kernel": f"force_kernel<{args.precision}>",
-                "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-                "launches": launches, "avg_launch_ms": round(force_ms / max(launches, 1), 4),
-                "flop_per_interaction": FLOP_PER_INTERACTION}
+    # roofline of the dominant kernel: the full-force launches (one per step, N^2 interactions)
+    full_ms, full_n = ctx.nb_profile_read(0)
+    blk_ms, blk_n = ctx.nb_profile_read(1)
+    avg_full_ms = full_ms / max(full_n, 1)
+    achieved = FLOP_PER_INTERACTION * n * n / (avg_full_ms * 1e-3) / 1e12
+    kernel_sym = "force_kernel<ModeF32, %d, %d, true, 0>" % (variant_full["ipl"], variant_full["unroll"])
+    traffic = committed_traffic(kernel_sym, n, args)
+    roofline = {"bound": "alu", "kernel": kernel_sym, "achieved": round(achieved, 3),
+                "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+                "launches": full_n, "avg_launch_ms": round(avg_full_ms, 3),
+                "flop_per_interaction": FLOP_PER_INTERACTION,
+                "interactions_per_launch": n * n,
+                "block_step_launches": {"launches": blk_n,
+                                        "avg_launch_ms": round(blk_ms / max(blk_n, 1), 4),
+                                        "interactions": n * c.n_active_sum * args.steps,
+                                        "tflops": round(FLOP_PER_INTERACTION * n * c.n_active_sum
+                                                        * args.steps / max(blk_ms * 1e-3, 1e-12)
+                                                        / 1e12, 3)}}
+    if args.precision != "fp32":
+        roofline["peak"] = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
+        roofline["frac"] = round(achieved / roofline["peak"], 4)
+        roofline["kernel"] = kernel_sym.replace("ModeF32", {"ds": "ModeDS", "fp64": "ModeF64"}[args.precision])
 
+    ctx.nb_profile(False)
     # accuracy of the timed arithmetic on a sample of i, against the oracle (untimed)
     st.x.copy_(x0); st.v.copy_(v0)
     ctx.nb_init(args.eta)
@@ -164,7 +208,7 @@ def main():
         cv.nb_bind(st)
         cv.nb_profile(True)
         cv.nb_init(args.eta)
-        ms, nl = cv.nb_profile_read()
+        ms, nl = cv.nb_profile_read(0)
         cv.nb_sync()
         gv = st.numpy()
         cv.close()
@@ -200,8 +244,8 @@ def main():
     else:
         for d in variants.values():
             d.pop("gv")
-    # slowdown of each variant: its time per interaction over the timed arithmetic's
-    ns_per_int = force_ms * 1e6 / interactions
+    # slowdown of each variant: its full-force time over the timed arithmetic's full force
+    ns_per_int = avg_full_ms * 1e6 / (n * n)
     for prec, d in variants.items():
         d["slowdown_vs_" + args.precision] = (d["full_force_ms"] * 1e6 / (n * n)) / ns_per_int
     result["variants"] = variants

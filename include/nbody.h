@@ -166,8 +166,11 @@ nb_status nb_read_control(nb_ctx *ctx, nb_control *out);
 nb_status nb_profile(nb_ctx *ctx, int32_t enable);
 
 /* Total milliseconds between the bracketing events and the number of timed force launches
- * since profiling was enabled (HOST outputs); synchronising. */
-nb_status nb_profile_read(nb_ctx *ctx, double *ms_total, int64_t *launches);
+ * since profiling was enabled (HOST outputs), for full-force launches (which = 0, the nb_init
+ * force and nb_force calls without a device count on more than n/8 particles), the other
+ * launches (which = 1: block steps and small lists) or all (which = -1).  The two classes are
+ * also distinct kernel symbols.  Synchronising. */
+nb_status nb_profile_read(nb_ctx *ctx, int32_t which, double *ms_total, int64_t *launches);
 
 /* Force-kernel launch variant: i-particles held per work-item (ipl), unroll of the j-loop,
  * desired number of equal work items per launch (target; the j-range is split K ways when the

@@ -347,7 +347,9 @@ __device__ __forceinline__ bool finite7(const Out7 &o) {
 // K == 1: results go straight to acc/jerk/pot; K > 1: to the partial planes for
 // force_reduce.  The potential sum is negated on output.
 // ------------------------------------------------------------------------------------------
-template <class M, int IPL, int UNR, bool SOFT>
+// CLS only separates the symbols of full-force launches (0) and block-step launches (1) so that
+// profilers report the two launch classes apart; the code is the same.
+template <class M, int IPL, int UNR, bool SOFT, int CLS>
 __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCommon fc) {
     __shared__ typename M::Smem sm;
     int32_t n_i = fc.n_i_max;

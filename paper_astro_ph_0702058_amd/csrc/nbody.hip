@@ -72,7 +72,11 @@ struct nb_ctx {
 
     // force-kernel timing (HIP events on the context stream), off by default
     bool profile = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    struct Timed {
+        hipEvent_t start, stop;
+        int cls;
+    };
+    std::vector<Timed> ev;
 
     std::string err;
 };
@@ -129,10 +133,11 @@ SchedView sched_view(const nb_ctx *c) {
 // Heuristic defaults per size class; nb_tune() replaces them with measured choices.
 Variant default_variant(int32_t n, int prec, int num_cu, bool block) {
     Variant v;
-    v.ipl = (prec == NB_FP32 && n >= 16384 && !block) ? 2 : 1;
-    if (prec == NB_FP32 && block && n >= (1 << 18)) v.ipl = 2;
-    v.unroll = 2;
-    v.target = num_cu * 16;  // equal work items for several rounds over all compute units
+    // measured on MI355X at N = 2^20: two i per work-item, unroll 1 for full-force calls and
+    // 2 for block steps; 16 work items per compute unit (full) and 8 (blocks)
+    v.ipl = (prec == NB_FP32 && n >= 16384) ? 2 : 1;
+    v.unroll = (prec == NB_FP32 && !block) ? 1 : 2;
+    v.target = num_cu * (block ? 8 : 16);
     v.kmax = 256;
     return v;
 }
@@ -156,29 +161,34 @@ nb_status enqueue_predict(nb_ctx *c, const int64_t *t, int guard, hipStream_t s)
 }
 
 template <class M, int IPL, int UNR>
-void launch_soft(const typename M::Args &pa, const ForceCommon &fc, bool soft, int32_t grid,
-                 hipStream_t s) {
-    if (soft) force_kernel<M, IPL, UNR, true><<<grid, WG, 0, s>>>(pa, fc);
-    else force_kernel<M, IPL, UNR, false><<<grid, WG, 0, s>>>(pa, fc);
+void launch_soft(const typename M::Args &pa, const ForceCommon &fc, bool soft, int cls,
+                 int32_t grid, hipStream_t s) {
+    if (cls == 0) {
+        if (soft) force_kernel<M, IPL, UNR, true, 0><<<grid, WG, 0, s>>>(pa, fc);
+        else force_kernel<M, IPL, UNR, false, 0><<<grid, WG, 0, s>>>(pa, fc);
+    } else {
+        if (soft) force_kernel<M, IPL, UNR, true, 1><<<grid, WG, 0, s>>>(pa, fc);
+        else force_kernel<M, IPL, UNR, false, 1><<<grid, WG, 0, s>>>(pa, fc);
+    }
 }
 
 template <class M>
 void launch_ipl1(const typename M::Args &pa, const ForceCommon &fc, const Variant &v, bool soft,
-                 int32_t grid, hipStream_t s) {
-    if (v.unroll == 1) launch_soft<M, 1, 1>(pa, fc, soft, grid, s);
-    else launch_soft<M, 1, 2>(pa, fc, soft, grid, s);
+                 int cls, int32_t grid, hipStream_t s) {
+    if (v.unroll == 1) launch_soft<M, 1, 1>(pa, fc, soft, cls, grid, s);
+    else launch_soft<M, 1, 2>(pa, fc, soft, cls, grid, s);
 }
 
 void launch_f32(const ModeF32::Args &pa, const ForceCommon &fc, const Variant &v, bool soft,
-                int32_t grid, hipStream_t s) {
+                int cls, int32_t grid, hipStream_t s) {
     if (v.ipl == 2) {
-        if (v.unroll == 1) launch_soft<ModeF32, 2, 1>(pa, fc, soft, grid, s);
-        else if (v.unroll == 2) launch_soft<ModeF32, 2, 2>(pa, fc, soft, grid, s);
-        else launch_soft<ModeF32, 2, 4>(pa, fc, soft, grid, s);
+        if (v.unroll == 1) launch_soft<ModeF32, 2, 1>(pa, fc, soft, cls, grid, s);
+        else if (v.unroll == 2) launch_soft<ModeF32, 2, 2>(pa, fc, soft, cls, grid, s);
+        else launch_soft<ModeF32, 2, 4>(pa, fc, soft, cls, grid, s);
     } else {
-        if (v.unroll == 1) launch_soft<ModeF32, 1, 1>(pa, fc, soft, grid, s);
-        else if (v.unroll == 2) launch_soft<ModeF32, 1, 2>(pa, fc, soft, grid, s);
-        else launch_soft<ModeF32, 1, 4>(pa, fc, soft, grid, s);
+        if (v.unroll == 1) launch_soft<ModeF32, 1, 1>(pa, fc, soft, cls, grid, s);
+        else if (v.unroll == 2) launch_soft<ModeF32, 1, 2>(pa, fc, soft, cls, grid, s);
+        else launch_soft<ModeF32, 1, 4>(pa, fc, soft, cls, grid, s);
     }
 }
 
@@ -195,7 +205,7 @@ int64_t partial_rows_for(int32_t n, const Variant &v) {
     return rows;
 }
 
-nb_status enqueue_force(nb_ctx *c, const Variant &v, const int32_t *ilist,
+nb_status enqueue_force(nb_ctx *c, const Variant &v, int cls, const int32_t *ilist,
                         const int32_t *n_i_dev, int32_t n_i_max, double *acc, double *jerk,
                         double *pot, int32_t ld, hipStream_t s) {
     const int32_t ib = WG * v.ipl;
@@ -220,27 +230,27 @@ nb_status enqueue_force(nb_ctx *c, const Variant &v, const int32_t *ilist,
     switch (c->prec) {
         case NB_FP32: {
             ModeF32::Args pa{c->js.px, c->js.py, c->js.pz, c->js.vm, (float)(c->eps * c->eps)};
-            launch_f32(pa, fc, v, soft, grid, s);
+            launch_f32(pa, fc, v, soft, cls, grid, s);
             break;
         }
         case NB_DS: {
             const double e2 = c->eps * c->eps;
             const float h = (float)e2;
             ModeDS::Args pa{c->js.q0, c->js.q1, c->js.q2, c->js.q3, ds{h, (float)(e2 - (double)h)}};
-            launch_ipl1<ModeDS>(pa, fc, v, soft, grid, s);
+            launch_ipl1<ModeDS>(pa, fc, v, soft, cls, grid, s);
             break;
         }
         default: {
             ModeF64::Args pa{c->js.px, c->js.py, c->js.pz, c->js.pm, c->js.vx, c->js.vy, c->js.vz,
                              c->eps * c->eps};
-            launch_ipl1<ModeF64>(pa, fc, v, soft, grid, s);
+            launch_ipl1<ModeF64>(pa, fc, v, soft, cls, grid, s);
             break;
         }
     }
     LAUNCH_OK(c);
     if (c->profile) {
         HIP_OK(c, hipEventRecord(e1, s));
-        c->ev.emplace_back(e0, e1);
+        c->ev.push_back(nb_ctx::Timed{e0, e1, cls});
     }
     // second pass: a no-op when the plan has K == 1
     const int32_t rgrid = grid_for(n_i_max, 4096);
@@ -276,7 +286,7 @@ nb_status enqueue_step(nb_ctx *c, double eta, hipStream_t s) {
     nb_status r;
     if ((r = enqueue_schedule(c, eta, s)) != NB_OK) return r;
     if ((r = enqueue_predict(c, nullptr, 1, s)) != NB_OK) return r;
-    if ((r = enqueue_force(c, c->var_block, c->active, &c->ctl->n_act, c->n, c->acc1, c->jerk1,
+    if ((r = enqueue_force(c, c->var_block, 1, c->active, &c->ctl->n_act, c->n, c->acc1, c->jerk1,
                            c->pot1, c->n, s)) != NB_OK)
         return r;
     return enqueue_correct(c, c->acc1, c->jerk1, c->pot1, s);
@@ -399,8 +409,8 @@ nb_status nb_destroy(nb_ctx *c) {
     (void)hipDeviceSynchronize();
     drop_graph(c);
     for (auto &p : c->ev) {
-        (void)hipEventDestroy(p.first);
-        (void)hipEventDestroy(p.second);
+        (void)hipEventDestroy(p.start);
+        (void)hipEventDestroy(p.stop);
     }
     void *bufs[] = {c->jbuf, c->acc1, c->partial, c->active, c->crit, c->wgmin, c->cnt, c->ctl,
                     c->exp_, c->t_zero};
@@ -439,7 +449,7 @@ nb_status nb_init(nb_ctx *c, double eta) {
     zero_ticks<<<grid_for(c->n, 4096), WG, 0, s>>>(c->st.tick, c->n);
     LAUNCH_OK(c);
     if ((r = enqueue_predict(c, c->t_zero, 0, s)) != NB_OK) return r;
-    if ((r = enqueue_force(c, c->var_full, nullptr, nullptr, c->n, c->acc1, c->jerk1, c->pot1,
+    if ((r = enqueue_force(c, c->var_full, 0, nullptr, nullptr, c->n, c->acc1, c->jerk1, c->pot1,
                            c->n, s)) != NB_OK)
         return r;
     init_levels<<<grid_for(c->n, 4096), WG, 0, s>>>(state_rw(c), c->acc1, c->jerk1, c->pot1, eta,
@@ -481,8 +491,9 @@ nb_status nb_force(nb_ctx *c, const int32_t *i_idx, const int32_t *n_i, int32_t 
     if (n_i_max < 0 || n_i_max > c->n)
         return fail(c, NB_EINVAL, "nb_force: n_i_max %d outside [0, %d]", n_i_max, c->n);
     if (!i_idx && !n_i && n_i_max == 0) return NB_OK;
-    const Variant &v = (n_i == nullptr && n_i_max > c->n / 8) ? c->var_full : c->var_block;
-    if ((r = enqueue_force(c, v, i_idx, n_i, n_i_max, acc, jerk, pot, n_i_max, c->stream)) != NB_OK)
+    const int cls = (n_i == nullptr && n_i_max > c->n / 8) ? 0 : 1;
+    if ((r = enqueue_force(c, cls == 0 ? c->var_full : c->var_block, cls, i_idx, n_i, n_i_max,
+                           acc, jerk, pot, n_i_max, c->stream)) != NB_OK)
         return r;
     c->forced = true;
     return NB_OK;
@@ -634,10 +645,10 @@ nb_status nb_tune(nb_ctx *c, int32_t which, int32_t n_i, int32_t reps, nb_varian
                 for (int rep = 0; rep <= reps; ++rep) {  // the first launch is not timed
                     HIP_OK(c, hipEventRecord(e0, s));
                     if (which == 0)
-                        r = enqueue_force(c, v, nullptr, nullptr, n_i, c->acc1, c->jerk1, c->pot1,
-                                          c->n, s);
+                        r = enqueue_force(c, v, 0, nullptr, nullptr, n_i, c->acc1, c->jerk1,
+                                          c->pot1, c->n, s);
                     else
-                        r = enqueue_force(c, v, nullptr, c->tune_n, c->n, c->acc1, c->jerk1,
+                        r = enqueue_force(c, v, 1, nullptr, c->tune_n, c->n, c->acc1, c->jerk1,
                                           c->pot1, c->n, s);
                     if (r != NB_OK) { c->profile = was_profiling; return r; }
                     HIP_OK(c, hipEventRecord(e1, s));
@@ -664,26 +675,29 @@ nb_status nb_profile(nb_ctx *c, int32_t enable) {
     HIP_OK(c, hipSetDevice(c->device));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     for (auto &p : c->ev) {
-        (void)hipEventDestroy(p.first);
-        (void)hipEventDestroy(p.second);
+        (void)hipEventDestroy(p.start);
+        (void)hipEventDestroy(p.stop);
     }
     c->ev.clear();
     c->profile = enable != 0;
     return NB_OK;
 }
 
-nb_status nb_profile_read(nb_ctx *c, double *ms_total, int64_t *launches) {
-    if (!c || !ms_total || !launches) return NB_EINVAL;
+nb_status nb_profile_read(nb_ctx *c, int32_t which, double *ms_total, int64_t *launches) {
+    if (!c || !ms_total || !launches || which < -1 || which > 1) return NB_EINVAL;
     HIP_OK(c, hipSetDevice(c->device));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     double tot = 0.0;
+    int64_t cnt = 0;
     for (auto &p : c->ev) {
+        if (which >= 0 && p.cls != which) continue;
         float ms = 0.f;
-        HIP_OK(c, hipEventElapsedTime(&ms, p.first, p.second));
+        HIP_OK(c, hipEventElapsedTime(&ms, p.start, p.stop));
         tot += ms;
+        ++cnt;
     }
     *ms_total = tot;
-    *launches = (int64_t)c->ev.size();
+    *launches = cnt;
     return NB_OK;
 }
 

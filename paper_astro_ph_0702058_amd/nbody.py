@@ -84,7 +84,7 @@ def load_library(path: str = LIB_PATH):
         "nb_set_variant": [P, I32, ctypes.POINTER(nb_variant)],
         "nb_tune": [P, I32, I32, I32, ctypes.POINTER(nb_variant), ctypes.POINTER(D)],
         "nb_profile": [P, I32],
-        "nb_profile_read": [P, ctypes.POINTER(D), ctypes.POINTER(I64)],
+        "nb_profile_read": [P, I32, ctypes.POINTER(D), ctypes.POINTER(I64)],
         "nb_sync": [P],
     }
     for name, args in sig.items():
@@ -292,10 +292,11 @@ class Context:
     def nb_profile(self, enable=True):
         self._check(self.lib.nb_profile(self.h, int(bool(enable))))
 
-    def nb_profile_read(self):
-        """(total force-kernel milliseconds, number of timed launches)."""
+    def nb_profile_read(self, which=-1):
+        """(total force-kernel milliseconds, number of timed launches) of one launch class
+        (0: full force, 1: block steps and small lists, -1: all)."""
         ms, n = ctypes.c_double(), ctypes.c_int64()
-        self._check(self.lib.nb_profile_read(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        self._check(self.lib.nb_profile_read(self.h, int(which), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
     def nb_sync(self):
