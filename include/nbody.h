@@ -188,7 +188,7 @@ nb_status nb_get_variant(nb_ctx *ctx, int32_t which, nb_variant *out);
 
 /* Replace that variant (HOST struct).  NB_EINVAL if it is not compiled, or if its j-split
  * would need more partial-sum storage than the context holds (targets up to 16 per compute
- * unit, kmax <= 256). */
+ * unit, kmax <= 65536). */
 nb_status nb_set_variant(nb_ctx *ctx, int32_t which, const nb_variant *v);
 
 /* Autotuner: launch every available variant on the first n_i particles against the

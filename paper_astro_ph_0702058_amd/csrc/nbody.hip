@@ -138,7 +138,7 @@ Variant default_variant(int32_t n, int prec, int num_cu, bool block) {
     v.ipl = (prec == NB_FP32 && n >= 16384) ? 2 : 1;
     v.unroll = (prec == NB_FP32 && !block) ? 1 : 2;
     v.target = num_cu * (block ? 8 : 16);
-    v.kmax = 256;
+    v.kmax = 1 << 16;  // K is bounded by the tile count and by target / i-blocks anyway
     return v;
 }
 
@@ -366,7 +366,7 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
     {
         int64_t rows = 0;
         for (int ipl = 1; ipl <= 2; ++ipl)
-            rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->max_target, 256}));
+            rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->max_target, 1 << 16}));
         c->partial_rows = rows;
         if ((r = alloc(c, &p, (size_t)std::max<int64_t>(rows, 1) * 7 * sizeof(double))) != NB_OK) {
             nb_destroy(c); return r;
@@ -598,7 +598,7 @@ nb_status nb_read_control(nb_ctx *c, nb_control *out) {
 
 static bool variant_valid(const nb_ctx *c, const nb_variant &v) {
     if (!variant_compiled(c->prec, v)) return false;
-    if (v.target < 1 || v.target > c->max_target || v.kmax < 1 || v.kmax > 256) return false;
+    if (v.target < 1 || v.target > c->max_target || v.kmax < 1 || v.kmax > (1 << 16)) return false;
     return partial_rows_for(c->n, v) <= c->partial_rows;
 }
 
@@ -639,7 +639,7 @@ nb_status nb_tune(nb_ctx *c, int32_t which, int32_t n_i, int32_t reps, nb_varian
     for (int ipl : ipls)
         for (int unr : unrs)
             for (int32_t tg : targets) {
-                const nb_variant v{ipl, unr, tg, 256};
+                const nb_variant v{ipl, unr, tg, 1 << 16};
                 if (!variant_valid(c, v)) continue;
                 float tot = 0.f;
                 for (int rep = 0; rep <= reps; ++rep) {  // the first launch is not timed

@@ -31,7 +31,7 @@ def test_variant_parity(prec, ipl, unr, target):
     with nbody.Context(n, eps, precision=prec) as ctx:
         ctx.nb_bind(st)
         ctx.nb_predict(torch.zeros(1, dtype=torch.int64, device="cuda"))
-        var = dict(ipl=ipl, unroll=unr, target=target, kmax=256)
+        var = dict(ipl=ipl, unroll=unr, target=target, kmax=65536)
         ctx.nb_set_variant(1, var)
         assert ctx.nb_get_variant(1) == var
         ii = torch.as_tensor(idx, device="cuda")
@@ -56,6 +56,8 @@ def test_set_variant_rejects_unavailable():
             ctx.nb_set_variant(0, dict(ipl=1, unroll=3, target=64, kmax=256))
         with pytest.raises(nbody.NBodyError):
             ctx.nb_set_variant(0, dict(ipl=1, unroll=2, target=10 ** 7, kmax=256))
+        with pytest.raises(nbody.NBodyError):
+            ctx.nb_set_variant(0, dict(ipl=1, unroll=2, target=64, kmax=10 ** 6))
 
 
 def test_tuner_picks_a_working_variant():
