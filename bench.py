@@ -67,6 +67,75 @@ def rms_rel(got, ref):
     return float(np.sqrt(np.mean(np.sum((got - ref) ** 2, 1) / np.sum(ref ** 2, 1))))
 
 
+def bench_ensemble(args):
+    """Ensemble workload: every cluster integrated by its own block steps to t_end; one step of
+    the bench = the whole run from the initial conditions (nb_ens_init + nb_ens_run)."""
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_astro_ph_0702058_amd import nbody
+    from paper_astro_ph_0702058_amd.plummer import ensemble_sizes, plummer
+    sizes = ensemble_sizes(args.clusters, 4)
+    eps = 1.0 / sizes
+    parts = [plummer(int(nc), 1000 + c) for c, nc in enumerate(sizes)]
+    x = np.concatenate([p[0] for p in parts]); v = np.concatenate([p[1] for p in parts])
+    m = np.concatenate([p[2] for p in parts])
+    st = nbody.DeviceState(x, v, m)
+    x0, v0 = st.x.clone(), st.v.clone()
+    ens = nbody.Ensemble(sizes, eps, lmin=3, precision=args.precision)
+    ens.nb_ens_bind(st)
+    eta = 0.02
+    layout = None
+    if args.tune:
+        from paper_astro_ph_0702058_amd.tuning import ensemble_autotune
+        layout = ensemble_autotune(ens, st, x0, v0, eta)
+        log(f"[bench] ensemble layout {layout}")
+
+    def step():
+        st.x.copy_(x0); st.v.copy_(v0)
+        ens.nb_ens_init(eta)
+        ens.nb_ens_run(eta, args.t_end, steps_per_launch=32)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctl = ens.nb_ens_control()
+    ek, ep = ens.nb_ens_energy()
+    st.x.copy_(x0); st.v.copy_(v0)
+    ens.nb_ens_init(eta)
+    ek0, ep0 = ens.nb_ens_energy()
+    ens.close()
+    inter = sum(int(nc) * int(nc) + int(nc) * c.n_active_sum for nc, c in zip(sizes, ctl))
+    elapsed = (t1 - t0) / args.steps
+    de = np.abs((ek + ep) - (ek0 + ep0)) / np.abs(ek0 + ep0)
+    result = {
+        "metric": "interactions/s, batched ensemble", "value": inter / elapsed,
+        "unit": "interactions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {"fp32": "f32", "ds": "f32x2", "fp64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"{args.clusters} Plummer clusters, N_c log-uniform [64, 4096] "
+                               f"(total {int(sizes.sum())}), eps=1/N_c, eta=0.02, t -> {args.t_end}",
+                   "clusters": args.clusters, "particles": int(sizes.sum()),
+                   "interactions_per_run": inter, "layout": layout,
+                   "max_block_steps": max(c.n_steps for c in ctl),
+                   "mean_block_steps": float(np.mean([c.n_steps for c in ctl])),
+                   "dE_over_E_max": float(de.max()), "dE_over_E_median": float(np.median(de))},
+        "roofline": {"bound": "alu", "achieved": round(60 * inter / elapsed / 1e12, 3),
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(60 * inter / elapsed / 1e12 / PEAK_FP32_TFLOPS, 4),
+                     "traffic": None},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,11 +152,19 @@ def main():
                     help="other interaction arithmetics to time once (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="full", choices=["full", "ensemble"],
+                    help="full: N-body force + block steps at N (default); ensemble: 512 "
+                         "Plummer clusters, N_c log-uniform in [64, 4096], eps = 1/N_c, "
+                         "eta = 0.02, to t = 1")
+    ap.add_argument("--clusters", type=int, default=512)
+    ap.add_argument("--t-end", type=float, default=1.0)
     ap.add_argument("--tune", action="store_true",
                     help="autotune the force-kernel variants first (untimed); default: the "
                          "library's defaults, which are the tuned choices for MI355X")
     args = ap.parse_args()
 
+    if args.workload == "ensemble":
+        return bench_ensemble(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)

@@ -203,6 +203,64 @@ nb_status nb_tune(nb_ctx *ctx, int32_t which, int32_t n_i, int32_t reps, nb_vari
 /* Wait for the context's stream; returns a latched device error, if any. */
 nb_status nb_sync(nb_ctx *ctx);
 
+/* ------------------------------------------------------------------------------------------
+ * Ensembles: many independent clusters, each integrated by its own Sec. 2 block-step scheme
+ * (own particle times, levels and blocks), advanced together.  One global step gives every
+ * cluster that has not reached t_end one of its own block steps: the force work items of all
+ * clusters' blocks spread over the whole GPU (j- and i-particles predicted as they are
+ * loaded), then one workgroup per cluster for the corrector, the new levels and the next
+ * block.  A run replays a HIP
+ * graph of steps_per_launch global steps until every cluster is done.
+ * The state is one nb_state over all particles, clusters stored contiguously.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct nb_ens nb_ens;
+
+/* Create an ensemble of n_clusters clusters: cluster c holds particles [offsets[c],
+ * offsets[c+1]) (HOST array of n_clusters + 1, offsets[0] = 0, strictly increasing, total
+ * <= 2^28, n_clusters <= 8192) with softening eps[c] > 0 (HOST array); steps in
+ * [2^-lmax, 2^-lmin]; interaction
+ * arithmetic `precision`.  Allocates the ensemble's device work buffers. */
+nb_status nb_ens_create(nb_ens **out, int32_t n_clusters, const int32_t *offsets,
+                        const double *eps, int32_t lmin, int32_t lmax, int32_t precision);
+
+/* Release the ensemble's own buffers (never the caller's).  NULL is a no-op. */
+nb_status nb_ens_destroy(nb_ens *ens);
+
+/* Enqueue subsequent work on `hip_stream` (NULL: the null stream). */
+nb_status nb_ens_set_stream(nb_ens *ens, void *hip_stream);
+
+/* Bind the caller's FP64 state over all particles (as nb_bind). */
+nb_status nb_ens_bind(nb_ens *ens, const nb_state *state);
+
+/* Force work layout (the autotuner's knobs): whole 256-particle j-tiles per work item for
+ * each cluster (HOST array of n_clusters values >= 1, or NULL to keep), i-particles per
+ * work-item (must be 1: small blocks instead share each i among several lanes) and j-loop
+ * unroll (1 or 2).  Synchronising. */
+nb_status nb_ens_set_layout(nb_ens *ens, const int32_t *tiles_per_item, int32_t ipl,
+                            int32_t unroll);
+
+/* Sec. 2 start of run for every cluster: full force at time 0, initial steps from
+ * Eq. initTimestep with this eta, times 0. */
+nb_status nb_ens_init(nb_ens *ens, double eta);
+
+/* Advance every cluster by its own block steps until its next block would pass t_end
+ * (ticks), steps_per_launch global steps per graph launch (use_graph != 0) or eager launch
+ * batch, synchronising after each to test for completion; at most max_steps global steps
+ * (<= 0: no limit).  Returns NB_OK or a latched device error. */
+nb_status nb_ens_run(nb_ens *ens, double eta, int64_t t_end, int32_t steps_per_launch,
+                     int64_t max_steps, int32_t use_graph);
+
+/* Per-cluster scheduler records into the HOST array out[n_clusters] (flags = 1 once the
+ * cluster has reached t_end).  Synchronising. */
+nb_status nb_ens_control(nb_ens *ens, nb_control *out);
+
+/* Sec. 4.2 energy of every cluster at its current time, FP64 (HOST arrays of n_clusters).
+ * Synchronising. */
+nb_status nb_ens_energy(nb_ens *ens, double *ekin, double *epot);
+
+/* Message for the last failing call on an ensemble (never NULL). */
+const char *nb_ens_last_error(const nb_ens *ens);
+
 /* Human-readable message for the last failing call on ctx (never NULL). */
 const char *nb_last_error(const nb_ctx *ctx);
 

@@ -1,0 +1,389 @@
+// ensemble.hpp -- gfx950 device code for many independent clusters integrated together.
+//
+// Every cluster runs its own Sec. 2 block-step scheme (own times, levels and blocks).  One
+// global step advances every unfinished cluster by one of its own block steps, in three kernels:
+//   ens_plan   one workgroup: the prefix over clusters of their force work items
+//              (cluster, i-block, j-range)
+//   ens_force  all workgroups take items.  An item is an
+//              i-block of the cluster's block against a range of whole j-tiles of the same
+//              cluster; i- and j-particles are predicted to the cluster's block time as they
+//              are loaded (Sec. 2 predictor, FP64); small blocks share each i among several
+//              lanes (wave-shuffle reduction); partial sums go to the cluster's partial planes
+//   ens_local  one workgroup of 1024 per cluster: fixed-order sum of the partials, the
+//              corrector and the new step of each block particle (Eq. timestep), then the
+//              cluster's next block (smallest t_i + dt_i)
+// No workgroup ever waits for another: the cluster-local work needs only its own workgroup's
+// barriers, and the phases are separate kernels.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace nbody {
+
+struct EnsCluster {  // device-resident per-cluster record
+    int64_t t_cur, t_next, n_steps, n_active_sum;
+    int32_t n_act, n_pending, done, pad;
+};
+
+struct EnsView {
+    int32_t C;                  // number of clusters
+    const int32_t *off;         // C + 1 particle offsets
+    const int32_t *K;           // j-ranges per i-block of each cluster
+    const int32_t *tpi;         // whole tiles per j-range
+    const int64_t *part_off;    // start of each cluster's partial planes
+    const int32_t *prow;        // rows of one partial plane of each cluster
+    const double *eps2;         // softening^2 of each cluster (> 0)
+    EnsCluster *cl;
+    int32_t *active;            // global indices, cluster c's block at active[off[c]...]
+    int32_t *item_start;        // C + 1 exclusive prefix of force work items (ens_plan)
+    double *partial;
+    double *crit;
+    int32_t *flags;             // [0]: non-finite seen, [1]: step clamped at 2^-lmax
+    int32_t lmin, lmax;
+    double tick_len;
+    int64_t t_end;
+};
+
+// Ordered compaction of the particles of [lo, hi) that satisfy `pred` into out[base ...],
+// by one workgroup; returns the count.
+template <int BS, class Pred>
+__device__ int32_t wg_compact(int32_t lo, int32_t hi, Pred pred, int32_t *out, int32_t *wsum) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t base = 0;
+    for (int32_t i0 = lo; i0 < hi; i0 += BS) {
+        const int32_t i = i0 + threadIdx.x;
+        const bool f = i < hi && pred(i);
+        const uint64_t mask = __ballot(f);
+        const int32_t below = __popcll(mask & ((1ull << lane) - 1ull));
+        __syncthreads();
+        if (lane == 0) wsum[wave] = __popcll(mask);
+        __syncthreads();
+        int32_t o = base;
+        for (int w = 0; w < wave; ++w) o += wsum[w];
+        if (f) out[o + below] = i;
+        for (int w = 0; w < BS / 64; ++w) base += wsum[w];
+    }
+    return base;
+}
+
+template <int BS>
+__device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t *red) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t o = __shfl_xor(v, off, 64);
+        v = o < v ? o : v;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    int64_t r = red[0];
+    for (int w = 1; w < BS / 64; ++w) r = red[w] < r ? red[w] : r;
+    return r;
+}
+
+constexpr int WGL = 1024;  // workgroup of the cluster-local kernel
+
+// One workgroup of WGL per cluster.
+//   phase 0: start of run -- block = every particle, times 0, block time 0
+//   phase 1: after the start-of-run force -- store a, k, pot and the initial levels
+//            (Eq. initTimestep), then select the first block
+//   phase 2: after a block force -- correct the block, give it new levels (Eq. timestep),
+//            then select the next block
+// Each thread takes whole block particles: the fixed-order sum of its K partial planes, the
+// corrector and the new level, with the criterion kept in registers.
+__global__ void __launch_bounds__(WGL) ens_local(EnsView e, StateRW s, double eta,
+                                                 int32_t phase) {
+    __shared__ int64_t red[WGL / 64];
+    __shared__ int32_t wsum[WGL / 64];
+    const int32_t c = blockIdx.x;
+    if (c >= e.C) return;
+    const int32_t lo = e.off[c], hi = e.off[c + 1];
+    EnsCluster *cl = e.cl + c;
+    if (phase == 0) {
+        const int32_t na = wg_compact<WGL>(lo, hi, [](int32_t) { return true; }, e.active + lo, wsum);
+        for (int32_t i = lo + threadIdx.x; i < hi; i += WGL) s.tick[i] = 0;
+        if (threadIdx.x == 0) {
+            cl->t_cur = 0; cl->t_next = 0; cl->n_steps = 0; cl->n_active_sum = 0;
+            cl->n_act = na; cl->n_pending = 0; cl->done = 0;
+        }
+        return;
+    }
+    if (cl->done) return;  // n_act is already 0
+    const int32_t n_act = cl->n_act;
+    const int64_t t_next = cl->t_next;
+    const int32_t K = e.K[c], P = e.prow[c];
+    const double *pbase = e.partial + e.part_off[c];
+    const int64_t stride = (int64_t)7 * P;
+    bool bad = false, clamp = false;
+    for (int32_t q = threadIdx.x; q < n_act; q += WGL) {
+        // the 7 sums of this block particle over the K partial planes, in plane order
+        double o[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        const double *src = pbase + q;
+        int32_t j = 0;
+        for (; j + 2 <= K; j += 2) {
+            double v0[7], v1[7];
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+                v0[k] = src[j * stride + (int64_t)k * P];
+                v1[k] = src[(j + 1) * stride + (int64_t)k * P];
+            }
+#pragma unroll
+            for (int k = 0; k < 7; ++k) o[k] = (o[k] + v0[k]) + v1[k];
+        }
+        for (; j < K; ++j) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) o[k] += src[j * stride + (int64_t)k * P];
+        }
+        const int32_t i = e.active[lo + q];
+        const double a1[3] = {o[0], o[1], o[2]}, k1[3] = {o[3], o[4], o[5]};
+        if (phase == 1) {
+            double na = 0.0, nk = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                s.a[k * (int64_t)s.n + i] = a1[k];
+                s.k[k * (int64_t)s.n + i] = k1[k];
+                na = __builtin_fma(a1[k], a1[k], na);
+                nk = __builtin_fma(k1[k], k1[k], nk);
+            }
+            s.pot[i] = -o[6];
+            na = __builtin_sqrt(na); nk = __builtin_sqrt(nk);
+            const double dt = nk > 0.0 ? eta * na / nk : __builtin_inf();
+            bad = bad || !__builtin_isfinite(na) || !__builtin_isfinite(nk);
+            s.level[i] = level_from_dt(dt, e.lmin, e.lmax);
+        } else {
+            const double dt_old = (double)(t_next - s.tick[i]) * s.tick_len;
+            double num = 0.0, den = 0.0;
+            const bool ok = correct_particle(s, i, dt_old, a1, k1, -o[6], t_next, nullptr, &num, &den);
+            bad = bad || !ok;
+            const double dt = den > 0.0 ? __builtin_sqrt(eta * num / den) : __builtin_inf();
+            bad = bad || __builtin_isnan(dt);
+            clamp = clamp || dt < e.tick_len;
+            s.level[i] = next_level(dt, s.level[i], t_next, e.lmin, e.lmax);
+        }
+    }
+    __syncthreads();
+    if (bad) e.flags[0] = 1;
+    if (clamp) e.flags[1] = 1;
+    if (phase == 2 && threadIdx.x == 0 && n_act > 0) {
+        cl->t_cur = t_next;
+        cl->n_steps += 1;
+        cl->n_active_sum += n_act;
+    }
+    // next block of this cluster
+    int64_t m = INT64_MAX;
+    for (int32_t i = lo + threadIdx.x; i < hi; i += WGL) {
+        const int64_t tn = s.tick[i] + ((int64_t)1 << (e.lmax - s.level[i]));
+        m = tn < m ? tn : m;
+    }
+    const int64_t tn_min = block_min_i64<WGL>(m, red);
+    if (tn_min > e.t_end) {
+        if (threadIdx.x == 0) { cl->done = 1; cl->n_act = 0; }
+        return;
+    }
+    const int32_t lmax = e.lmax;
+    const int32_t na = wg_compact<WGL>(
+        lo, hi,
+        [&](int32_t i) { return s.tick[i] + ((int64_t)1 << (lmax - s.level[i])) == tn_min; },
+        e.active + lo, wsum);
+    if (threadIdx.x == 0) {
+        cl->t_next = tn_min;
+        cl->n_act = na;
+    }
+}
+
+// Exclusive prefix over clusters of their force work items (one workgroup of WGL).
+__global__ void __launch_bounds__(WGL) ens_plan(EnsView e) {
+    __shared__ int32_t buf[WGL];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int32_t c0 = 0; c0 < e.C; c0 += WGL) {
+        const int32_t c = c0 + threadIdx.x;
+        int32_t items = 0;
+        if (c < e.C) {
+            const int32_t na = e.cl[c].n_act;
+            const int32_t ibc = WG / lane_split(na, true);
+            items = na > 0 ? ((na + ibc - 1) / ibc) * e.K[c] : 0;
+        }
+        buf[threadIdx.x] = items;
+        __syncthreads();
+        for (int o = 1; o < WGL; o <<= 1) {  // inclusive scan (Hillis-Steele)
+            const int32_t v = (int)threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += v;
+            __syncthreads();
+        }
+        if (c < e.C) e.item_start[c] = carry + buf[threadIdx.x] - items;
+        __syncthreads();
+        if (threadIdx.x == WGL - 1) carry += buf[WGL - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) e.item_start[e.C] = carry;
+}
+
+template <class M> __device__ __forceinline__ typename EpsOf<M>::T eps_as(double e2);
+template <> __device__ __forceinline__ float eps_as<ModeF32>(double e2) { return (float)e2; }
+template <> __device__ __forceinline__ ds eps_as<ModeDS>(double e2) { return ds_from_double(e2); }
+template <> __device__ __forceinline__ double eps_as<ModeF64>(double e2) { return e2; }
+
+// Work items of all clusters; softened (eps > 0) interactions only.
+// Predicted FP64 position and velocity of particle i at tick t (Sec. 2 predictor).
+__device__ __forceinline__ void predicted(const StateRW &s, int32_t i, int64_t t, double xp[3],
+                                          double vp[3]) {
+    const double D = (double)(t - s.tick[i]) * s.tick_len;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int64_t ix = k * (int64_t)s.n + i;
+        predict_one(D, s.x[ix], s.v[ix], s.a[ix], s.k[ix], xp[k], vp[k]);
+    }
+}
+
+// Softened (eps > 0) interactions only; one i per work-item, S lanes per i when the
+// cluster's block is small.
+// Dynamic LDS: the C + 1 item starts, copied once per workgroup.
+template <class M, int UNR>
+__global__ void __launch_bounds__(WG) ens_force(EnsView e, StateRW st) {
+    __shared__ typename M::Smem sm;
+    extern __shared__ int32_t start[];
+    for (int32_t c = threadIdx.x; c <= e.C; c += WG) start[c] = e.item_start[c];
+    __syncthreads();
+    const int32_t total = start[e.C];
+    for (int32_t w = blockIdx.x; w < total; w += gridDim.x) {
+        // cluster of item w: the last c with start[c] <= w
+        int32_t lo = 0, hi = e.C - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (start[mid] <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        const int32_t c = lo;
+        const int32_t K = e.K[c], tpi = e.tpi[c];
+        const int32_t local = w - start[c];
+        const int32_t iblk = local / K, ks = local - (local / K) * K;
+        const int32_t p0 = e.off[c], n_c = e.off[c + 1] - p0;
+        const int32_t n_act = e.cl[c].n_act;
+        const int64_t tb = e.cl[c].t_next;
+        const int32_t Sl = lane_split(n_act, true);
+        const int32_t slice = (int32_t)threadIdx.x % Sl;
+        const int32_t ntiles = (n_c + TJ - 1) / TJ;
+        const auto eps2 = eps_as<M>(e.eps2[c]);
+        const int32_t q = iblk * (WG / Sl) + (int32_t)threadIdx.x / Sl;
+        const int32_t g = q < n_act ? e.active[p0 + q] : p0;
+        double xp[3], vp[3];
+        predicted(st, g, tb, xp, vp);
+        const typename M::I ii = M::make_i(xp, vp, st.m[g]);
+        typename M::Sum S = M::sum_zero();
+        const int32_t t0 = ks * tpi;
+        const int32_t t1 = t0 + tpi < ntiles ? t0 + tpi : ntiles;
+        for (int32_t t = t0; t < t1; ++t) {
+            __syncthreads();
+            const int32_t jl = t * TJ + (int32_t)threadIdx.x;
+            if (jl < n_c) {
+                double xj[3], vj[3];
+                predicted(st, p0 + jl, tb, xj, vj);
+                M::put(sm, threadIdx.x, xj, vj, st.m[p0 + jl]);
+            } else {  // padding: zero mass contributes nothing
+                const double z[3] = {0.0, 0.0, 0.0};
+                M::put(sm, threadIdx.x, z, z, 0.0);
+            }
+            __syncthreads();
+            typename M::Tile T = M::tile_zero();
+#pragma unroll UNR
+            for (int jj = slice; jj < TJ; jj += Sl) M::template interact<true>(ii, sm, jj, eps2, T);
+            M::fold(S, T);
+        }
+        for (int off = Sl >> 1; off > 0; off >>= 1) M::shfl_add(S, off);
+        const int32_t jlo = p0 + t0 * TJ, jhi = p0 + t1 * TJ;
+        if (slice == 0 && q < n_act) {
+            if (g >= jlo && g < jhi) M::remove_self(S, ii, eps2);
+            const Out7 o = M::out(S);
+            const int32_t P = e.prow[c];
+            double *base = e.partial + e.part_off[c] + (int64_t)ks * 7 * P + q;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) base[(int64_t)k * P] = o.v[k];
+        }
+    }
+}
+
+// Energy of every cluster at its current time (FP64): one workgroup per cluster, pair sums
+// with Neumaier compensation; cluster particles predicted to the cluster's t_cur.
+__global__ void __launch_bounds__(WG) ens_energy(EnsView e, StateRW s, double *ekin,
+                                                 double *epot) {
+    __shared__ double sx[TJ], sy[TJ], sz[TJ], smm[TJ];
+    __shared__ double rk[WG], rp[WG];
+    const int32_t c = blockIdx.x;
+    if (c >= e.C) return;
+    const int32_t p0 = e.off[c], n_c = e.off[c + 1] - p0;
+    const int64_t t = e.cl[c].t_cur;
+    const double eps2 = e.eps2[c];
+    double kin = 0.0, kc = 0.0, pot = 0.0, pc = 0.0;
+    for (int32_t i0 = 0; i0 < n_c; i0 += WG) {
+        const int32_t il = i0 + threadIdx.x;
+        const int32_t i = p0 + (il < n_c ? il : 0);
+        const double D = (double)(t - s.tick[i]) * s.tick_len;
+        double xi[3], vi[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t ix = k * (int64_t)s.n + i;
+            predict_one(D, s.x[ix], s.v[ix], s.a[ix], s.k[ix], xi[k], vi[k]);
+        }
+        double w = 0.0, wc = 0.0;
+        for (int32_t j0 = 0; j0 < n_c; j0 += TJ) {
+            __syncthreads();
+            const int32_t jl = j0 + threadIdx.x;
+            if (jl < n_c) {
+                const int32_t j = p0 + jl;
+                const double Dj = (double)(t - s.tick[j]) * s.tick_len;
+                double xj[3], vj[3];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const int64_t ix = k * (int64_t)s.n + j;
+                    predict_one(Dj, s.x[ix], s.v[ix], s.a[ix], s.k[ix], xj[k], vj[k]);
+                }
+                sx[threadIdx.x] = xj[0]; sy[threadIdx.x] = xj[1]; sz[threadIdx.x] = xj[2];
+                smm[threadIdx.x] = s.m[j];
+            } else {
+                sx[threadIdx.x] = 0.0; sy[threadIdx.x] = 0.0; sz[threadIdx.x] = 0.0;
+                smm[threadIdx.x] = 0.0;
+            }
+            __syncthreads();
+            double ts = 0.0;
+            const int32_t cnt = n_c - j0 < TJ ? n_c - j0 : TJ;
+            for (int jj = 0; jj < cnt; ++jj) {
+                const double dx = sx[jj] - xi[0], dy = sy[jj] - xi[1], dz = sz[jj] - xi[2];
+                const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, __builtin_fma(dx, dx, eps2)));
+                ts += (j0 + jj == il) ? 0.0 : smm[jj] * rsqrt_f64(r2);
+            }
+            const double y = w + ts;
+            wc += __builtin_fabs(w) >= __builtin_fabs(ts) ? (w - y) + ts : (ts - y) + w;
+            w = y;
+        }
+        if (il < n_c) {
+            const double mi = s.m[i];
+            const double pe = mi * (w + wc);
+            const double ke = 0.5 * mi * __builtin_fma(vi[2], vi[2], __builtin_fma(vi[1], vi[1], vi[0] * vi[0]));
+            double y = pot + pe;
+            pc += __builtin_fabs(pot) >= __builtin_fabs(pe) ? (pot - y) + pe : (pe - y) + pot;
+            pot = y;
+            y = kin + ke;
+            kc += __builtin_fabs(kin) >= __builtin_fabs(ke) ? (kin - y) + ke : (ke - y) + kin;
+            kin = y;
+        }
+    }
+    rk[threadIdx.x] = kin + kc;
+    rp[threadIdx.x] = pot + pc;
+    __syncthreads();
+    for (int o = WG / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            rk[threadIdx.x] += rk[threadIdx.x + o];
+            rp[threadIdx.x] += rp[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ekin[c] = rk[0];
+        epot[c] = -0.5 * rp[0];
+    }
+}
+
+}  // namespace nbody

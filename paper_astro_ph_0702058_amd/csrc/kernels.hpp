@@ -45,13 +45,29 @@ struct DevControl {
 // ------------------------------------------------------------------------------------------
 struct ForcePlan {
     int32_t n_i, n_iblk, ntiles, tps, K, items;
-    int64_t P;  // padded i rows of one partial plane
+    int32_t S;   // lanes sharing one i-particle (1 unless the i-list is small)
+    int32_t ib;  // i-particles per i-block
+    int64_t P;   // padded i rows of one partial plane
 };
 
-__host__ __device__ inline ForcePlan make_plan(int32_t n_i, int32_t n, int32_t ib,
+// Lanes per i-particle for a list of n_i with one i per work-item: the whole workgroup is
+// spread over the list, up to 64 lanes (one wave) per i.
+__host__ __device__ inline int32_t lane_split(int32_t n_i, bool allowed) {
+    if (!allowed || n_i >= WG) return 1;
+    int32_t p2 = 1;
+    while (p2 < n_i) p2 <<= 1;
+    const int32_t S = WG / p2;
+    return S > 64 ? 64 : S;
+}
+
+// ib_max: WG * (i-particles per work-item); the lane split applies when that is WG.
+__host__ __device__ inline ForcePlan make_plan(int32_t n_i, int32_t n, int32_t ib_max,
                                                int32_t target, int32_t kmax) {
     ForcePlan p;
     p.n_i = n_i;
+    p.S = lane_split(n_i, ib_max == WG);
+    const int32_t ib = ib_max / p.S;
+    p.ib = ib;
     p.n_iblk = (n_i + ib - 1) / ib;
     p.ntiles = (n + TJ - 1) / TJ;
     int32_t K = p.n_iblk > 0 ? target / p.n_iblk : 1;
@@ -121,6 +137,14 @@ struct ModeF32 {
     }
     __device__ static Tile tile_zero() { return Tile{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}; }
     __device__ static Sum sum_zero() { return Sum{0., 0., 0., 0., 0., 0., 0.}; }
+    // records built directly from FP64 predicted values (as the predictor would write them)
+    __device__ static I make_i(const double xp[3], const double vp[3], double m) {
+        return I{xp[0], xp[1], xp[2], (float)vp[0], (float)vp[1], (float)vp[2], (float)m};
+    }
+    __device__ static void put(Smem &s, int t, const double xp[3], const double vp[3], double m) {
+        s.x[t] = xp[0]; s.y[t] = xp[1]; s.z[t] = xp[2];
+        s.vm[t] = make_float4((float)vp[0], (float)vp[1], (float)vp[2], (float)m);
+    }
 
     template <bool SOFT>
     __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, float eps2,
@@ -160,6 +184,13 @@ struct ModeF32 {
     }
     __device__ static Out7 out(const Sum &S) {
         return Out7{{S.ax, S.ay, S.az, S.jx, S.jy, S.jz, S.p}};
+    }
+    // S += the same record of the lane `off` away (xor), within a wave
+    __device__ static void shfl_add(Sum &S, int off) {
+        S.ax += __shfl_xor(S.ax, off, 64); S.ay += __shfl_xor(S.ay, off, 64);
+        S.az += __shfl_xor(S.az, off, 64); S.jx += __shfl_xor(S.jx, off, 64);
+        S.jy += __shfl_xor(S.jy, off, 64); S.jz += __shfl_xor(S.jz, off, 64);
+        S.p += __shfl_xor(S.p, off, 64);
     }
 };
 
@@ -204,6 +235,20 @@ struct ModeDS {
         return Tile{z, z, z, z, z, z, z};
     }
     __device__ static Sum sum_zero() { return tile_zero(); }
+    __device__ static I make_i(const double xp[3], const double vp[3], double m) {
+        return I{ds_from_double(xp[0]), ds_from_double(xp[1]), ds_from_double(xp[2]),
+                 ds_from_double(vp[0]), ds_from_double(vp[1]), ds_from_double(vp[2]),
+                 ds_from_double(m)};
+    }
+    __device__ static void put(Smem &s, int t, const double xp[3], const double vp[3], double m) {
+        const ds X = ds_from_double(xp[0]), Y = ds_from_double(xp[1]), Z = ds_from_double(xp[2]);
+        const ds VX = ds_from_double(vp[0]), VY = ds_from_double(vp[1]), VZ = ds_from_double(vp[2]);
+        const ds M = ds_from_double(m);
+        s.q0[t] = make_float4(X.hi, Y.hi, Z.hi, M.hi);
+        s.q1[t] = make_float4(X.lo, Y.lo, Z.lo, M.lo);
+        s.q2[t] = make_float4(VX.hi, VY.hi, VZ.hi, 0.f);
+        s.q3[t] = make_float4(VX.lo, VY.lo, VZ.lo, 0.f);
+    }
 
     template <bool SOFT>
     __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, ds eps2,
@@ -249,6 +294,15 @@ struct ModeDS {
                      ds_to_double(S.jx), ds_to_double(S.jy), ds_to_double(S.jz),
                      ds_to_double(S.p)}};
     }
+    __device__ static ds shfl_ds(ds a, int off) {
+        return ds{__shfl_xor(a.hi, off, 64), __shfl_xor(a.lo, off, 64)};
+    }
+    __device__ static void shfl_add(Sum &S, int off) {
+        S.ax = ds_add(S.ax, shfl_ds(S.ax, off)); S.ay = ds_add(S.ay, shfl_ds(S.ay, off));
+        S.az = ds_add(S.az, shfl_ds(S.az, off)); S.jx = ds_add(S.jx, shfl_ds(S.jx, off));
+        S.jy = ds_add(S.jy, shfl_ds(S.jy, off)); S.jz = ds_add(S.jz, shfl_ds(S.jz, off));
+        S.p = ds_add(S.p, shfl_ds(S.p, off));
+    }
 };
 
 // ------------------------------------------------------------------------------------------
@@ -293,6 +347,13 @@ struct ModeF64 {
     }
     __device__ static Tile tile_zero() { return Tile{0., 0., 0., 0., 0., 0., 0.}; }
     __device__ static Sum sum_zero() { return tile_zero(); }
+    __device__ static I make_i(const double xp[3], const double vp[3], double m) {
+        return I{xp[0], xp[1], xp[2], vp[0], vp[1], vp[2], m};
+    }
+    __device__ static void put(Smem &s, int t, const double xp[3], const double vp[3], double m) {
+        s.x[t] = xp[0]; s.y[t] = xp[1]; s.z[t] = xp[2]; s.m[t] = m;
+        s.vx[t] = vp[0]; s.vy[t] = vp[1]; s.vz[t] = vp[2];
+    }
 
     template <bool SOFT>
     __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, double eps2,
@@ -325,18 +386,80 @@ struct ModeF64 {
     __device__ static Out7 out(const Sum &S) {
         return Out7{{S.ax, S.ay, S.az, S.jx, S.jy, S.jz, S.p}};
     }
+    __device__ static void shfl_add(Sum &S, int off) {
+        S.ax += __shfl_xor(S.ax, off, 64); S.ay += __shfl_xor(S.ay, off, 64);
+        S.az += __shfl_xor(S.az, off, 64); S.jx += __shfl_xor(S.jx, off, 64);
+        S.jy += __shfl_xor(S.jy, off, 64); S.jz += __shfl_xor(S.jz, off, 64);
+        S.p += __shfl_xor(S.p, off, 64);
+    }
 };
-
-template <class M> struct EpsOf;
-template <> struct EpsOf<ModeF32> { using T = float; };
-template <> struct EpsOf<ModeDS> { using T = ds; };
-template <> struct EpsOf<ModeF64> { using T = double; };
 
 __device__ __forceinline__ bool finite7(const Out7 &o) {
     bool ok = true;
 #pragma unroll
     for (int c = 0; c < 7; ++c) ok = ok && __builtin_isfinite(o.v[c]);
     return ok;
+}
+
+template <class M> struct EpsOf;
+template <> struct EpsOf<ModeF32> { using T = float; };
+template <> struct EpsOf<ModeDS> { using T = ds; };
+template <> struct EpsOf<ModeF64> { using T = double; };
+
+// Final sums of row q of a work item's j-range ks: straight to the outputs when K == 1,
+// else to partial plane ks.  The potential sum is negated here.
+__device__ __forceinline__ void store_result(const ForceCommon &fc, const ForcePlan &pl,
+                                             int32_t ks, int32_t q, Out7 o) {
+    o.v[6] = -o.v[6];
+    if (pl.K == 1) {
+        if (fc.ctl && !finite7(o)) fc.ctl->flag_nonfinite = 1;
+        fc.acc[0 * (int64_t)fc.ld + q] = o.v[0];
+        fc.acc[1 * (int64_t)fc.ld + q] = o.v[1];
+        fc.acc[2 * (int64_t)fc.ld + q] = o.v[2];
+        fc.jerk[0 * (int64_t)fc.ld + q] = o.v[3];
+        fc.jerk[1 * (int64_t)fc.ld + q] = o.v[4];
+        fc.jerk[2 * (int64_t)fc.ld + q] = o.v[5];
+        fc.pot[q] = o.v[6];
+    } else {
+        double *base = fc.partial + (int64_t)ks * 7 * pl.P + q;
+#pragma unroll
+        for (int c = 0; c < 7; ++c) base[(int64_t)c * pl.P] = o.v[c];
+    }
+}
+
+// Small i-lists: S adjacent lanes share one i-particle, lane `slice` of the group takes the
+// j-particles slice, slice + S, ... of every staged tile, and the S partial sums are combined
+// by xor-shuffles within the wave (a fixed order) before the result is stored.
+template <class M, int UNR, bool SOFT>
+__device__ void force_items_split(const typename M::Args &pa, const ForceCommon &fc,
+                                  const ForcePlan &pl, typename M::Smem &sm, int32_t n_i,
+                                  typename EpsOf<M>::T eps2) {
+    const int32_t Sl = pl.S;
+    const int32_t slice = (int32_t)threadIdx.x % Sl;
+    for (int32_t w = blockIdx.x; w < pl.items; w += gridDim.x) {
+        const int32_t iblk = w / pl.K, ks = w - (w / pl.K) * pl.K;
+        const int32_t q = iblk * pl.ib + (int32_t)threadIdx.x / Sl;
+        const int32_t g = q < n_i ? (fc.ilist ? fc.ilist[q] : q) : 0;
+        const typename M::I ii = M::load_i(pa, g);
+        typename M::Sum S = M::sum_zero();
+        const int32_t t0 = ks * pl.tps;
+        const int32_t t1 = t0 + pl.tps < pl.ntiles ? t0 + pl.tps : pl.ntiles;
+        for (int32_t t = t0; t < t1; ++t) {
+            __syncthreads();
+            M::stage(pa, sm, threadIdx.x, t * TJ + (int32_t)threadIdx.x, fc.n);
+            __syncthreads();
+            typename M::Tile T = M::tile_zero();
+#pragma unroll UNR
+            for (int jj = slice; jj < TJ; jj += Sl) M::template interact<SOFT>(ii, sm, jj, eps2, T);
+            M::fold(S, T);
+        }
+        for (int off = Sl >> 1; off > 0; off >>= 1) M::shfl_add(S, off);
+        const int32_t jlo = t0 * TJ, jhi = t1 * TJ;
+        if (slice == 0 && q < n_i) {
+            if (SOFT && g >= jlo && g < jhi) M::remove_self(S, ii, eps2);
+            store_result(fc, pl, ks, q, M::out(S));
+        }
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -360,6 +483,10 @@ __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCom
     if (n_i <= 0) return;
     const ForcePlan pl = make_plan(n_i, fc.n, WG * IPL, fc.target, fc.kmax);
     const auto eps2 = pa.eps2;
+    if (IPL == 1 && pl.S > 1) {
+        force_items_split<M, UNR, SOFT>(pa, fc, pl, sm, n_i, eps2);
+        return;
+    }
     for (int32_t w = blockIdx.x; w < pl.items; w += gridDim.x) {
         const int32_t iblk = w / pl.K, ks = w - (w / pl.K) * pl.K;
         int32_t q[IPL], g[IPL];
@@ -394,22 +521,7 @@ __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCom
         for (int p = 0; p < IPL; ++p) {
             if (q[p] >= n_i) continue;
             if (SOFT && g[p] >= jlo && g[p] < jhi) M::remove_self(S[p], ii[p], eps2);
-            Out7 o = M::out(S[p]);
-            o.v[6] = -o.v[6];
-            if (pl.K == 1) {
-                if (fc.ctl && !finite7(o)) fc.ctl->flag_nonfinite = 1;
-                fc.acc[0 * (int64_t)fc.ld + q[p]] = o.v[0];
-                fc.acc[1 * (int64_t)fc.ld + q[p]] = o.v[1];
-                fc.acc[2 * (int64_t)fc.ld + q[p]] = o.v[2];
-                fc.jerk[0 * (int64_t)fc.ld + q[p]] = o.v[3];
-                fc.jerk[1 * (int64_t)fc.ld + q[p]] = o.v[4];
-                fc.jerk[2 * (int64_t)fc.ld + q[p]] = o.v[5];
-                fc.pot[q[p]] = o.v[6];
-            } else {
-                double *base = fc.partial + (int64_t)ks * 7 * pl.P + q[p];
-#pragma unroll
-                for (int c = 0; c < 7; ++c) base[(int64_t)c * pl.P] = o.v[c];
-            }
+            store_result(fc, pl, ks, q[p], M::out(S[p]));
         }
     }
 }
@@ -561,47 +673,68 @@ __global__ void __launch_bounds__(WG) init_levels(StateRW s, const double *acc, 
 // ------------------------------------------------------------------------------------------
 // Sec. 2 corrector (FP64) on the selected block.
 // ------------------------------------------------------------------------------------------
+// Corrector of particle i over its step dt from the new acceleration/jerk/potential; writes
+// the corrected state, the criterion inputs and the particle's time; false if not finite.
+__device__ __forceinline__ bool correct_particle(const StateRW &s, int32_t i, double dt,
+                                                 const double a1v[3], const double k1v[3],
+                                                 double pot1, int64_t t_new, double *crit,
+                                                 double *crit_num = nullptr,
+                                                 double *crit_den = nullptr) {
+    const int32_t n = s.n;
+    const double idt = 1.0 / dt;  // a power of two: exact
+    const double dt2 = dt * dt, dt3 = dt2 * dt, dt4 = dt3 * dt, dt5 = dt4 * dt;
+    double na1 = 0.0, nk1 = 0.0, na2p = 0.0, na3 = 0.0;
+    bool ok = true;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int64_t e = c * (int64_t)n + i;
+        const double x = s.x[e], v = s.v[e], a0 = s.a[e], k0 = s.k[e];
+        const double a1 = a1v[c], k1 = k1v[c];
+        double xp, vp;
+        predict_one(dt, x, v, a0, k0, xp, vp);
+        const double da = a0 - a1;
+        const double a2 = (-6.0 * da * idt - (4.0 * k0 + 2.0 * k1)) * idt;
+        const double a3 = (12.0 * da * idt + 6.0 * (k0 + k1)) * idt * idt;
+        const double xn = xp + a2 * (dt4 * (1.0 / 24.0)) + a3 * (dt5 * (1.0 / 120.0));
+        const double vn = vp + a2 * (dt3 * (1.0 / 6.0)) + a3 * (dt4 * (1.0 / 24.0));
+        const double a2p = a2 + a3 * dt;
+        ok = ok && __builtin_isfinite(xn) && __builtin_isfinite(vn) && __builtin_isfinite(a2p);
+        s.x[e] = xn; s.v[e] = vn; s.a[e] = a1; s.k[e] = k1;
+        na1 = __builtin_fma(a1, a1, na1);
+        nk1 = __builtin_fma(k1, k1, nk1);
+        na2p = __builtin_fma(a2p, a2p, na2p);
+        na3 = __builtin_fma(a3, a3, na3);
+    }
+    s.pot[i] = pot1;
+    na1 = __builtin_sqrt(na1); nk1 = __builtin_sqrt(nk1);
+    na2p = __builtin_sqrt(na2p); na3 = __builtin_sqrt(na3);
+    const double num = na1 * na2p + nk1 * nk1, den = nk1 * na3 + na2p * na2p;
+    if (crit) {
+        crit[2 * (int64_t)i] = num;
+        crit[2 * (int64_t)i + 1] = den;
+    }
+    if (crit_num) *crit_num = num;
+    if (crit_den) *crit_den = den;
+    s.tick[i] = t_new;
+    return ok;
+}
+
 __global__ void __launch_bounds__(WG) correct_kernel(StateRW s, const int32_t *active,
                                                      const double *acc, const double *jerk,
                                                      const double *pot, int32_t ld,
                                                      double *crit, DevControl *ctl) {
     const int32_t n_act = ctl->n_act;
     const int64_t t_next = ctl->t_next;
-    const int32_t n = s.n;
     for (int32_t q = blockIdx.x * WG + threadIdx.x; q < n_act; q += gridDim.x * WG) {
         const int32_t i = active[q];
         const double dt = (double)(t_next - s.tick[i]) * s.tick_len;
-        const double idt = 1.0 / dt;  // a power of two: exact
-        const double dt2 = dt * dt, dt3 = dt2 * dt, dt4 = dt3 * dt, dt5 = dt4 * dt;
-        double na1 = 0.0, nk1 = 0.0, na2p = 0.0, na3 = 0.0;
-        bool ok = true;
+        double a1[3], k1[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const int64_t e = c * (int64_t)n + i;
-            const double x = s.x[e], v = s.v[e], a0 = s.a[e], k0 = s.k[e];
-            const double a1 = acc[c * (int64_t)ld + q], k1 = jerk[c * (int64_t)ld + q];
-            double xp, vp;
-            predict_one(dt, x, v, a0, k0, xp, vp);
-            const double da = a0 - a1;
-            const double a2 = (-6.0 * da * idt - (4.0 * k0 + 2.0 * k1)) * idt;
-            const double a3 = (12.0 * da * idt + 6.0 * (k0 + k1)) * idt * idt;
-            const double xn = xp + a2 * (dt4 * (1.0 / 24.0)) + a3 * (dt5 * (1.0 / 120.0));
-            const double vn = vp + a2 * (dt3 * (1.0 / 6.0)) + a3 * (dt4 * (1.0 / 24.0));
-            const double a2p = a2 + a3 * dt;
-            ok = ok && __builtin_isfinite(xn) && __builtin_isfinite(vn) && __builtin_isfinite(a2p);
-            s.x[e] = xn; s.v[e] = vn; s.a[e] = a1; s.k[e] = k1;
-            na1 = __builtin_fma(a1, a1, na1);
-            nk1 = __builtin_fma(k1, k1, nk1);
-            na2p = __builtin_fma(a2p, a2p, na2p);
-            na3 = __builtin_fma(a3, a3, na3);
+            a1[c] = acc[c * (int64_t)ld + q];
+            k1[c] = jerk[c * (int64_t)ld + q];
         }
-        s.pot[i] = pot[q];
-        na1 = __builtin_sqrt(na1); nk1 = __builtin_sqrt(nk1);
-        na2p = __builtin_sqrt(na2p); na3 = __builtin_sqrt(na3);
-        crit[2 * (int64_t)i] = na1 * na2p + nk1 * nk1;
-        crit[2 * (int64_t)i + 1] = nk1 * na3 + na2p * na2p;
-        s.tick[i] = t_next;
-        if (!ok) ctl->flag_nonfinite = 1;
+        if (!correct_particle(s, i, dt, a1, k1, pot[q], t_next, crit)) ctl->flag_nonfinite = 1;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && n_act > 0) {
         ctl->t_cur = t_next;
@@ -614,6 +747,20 @@ __global__ void __launch_bounds__(WG) correct_kernel(StateRW s, const int32_t *a
 // ------------------------------------------------------------------------------------------
 // Sec. 2 block scheduling.
 // ------------------------------------------------------------------------------------------
+// Power-of-two rule for a particle on level l at tick t whose criterion gives dt: halve until
+// not above dt; or double once when dt allows it, t is a multiple of the doubled step and the
+// doubled step is within 2^-lmin.
+__device__ __forceinline__ int32_t next_level(double dt, int32_t l, int64_t t, int32_t lmin,
+                                              int32_t lmax) {
+    if (dt < __builtin_ldexp(1.0, -l)) {
+        while (l < lmax && __builtin_ldexp(1.0, -l) > dt) ++l;
+    } else if (l > lmin && dt >= __builtin_ldexp(1.0, -(l - 1))) {
+        const int64_t two_dt = (int64_t)1 << (lmax - l + 1);
+        if (t % two_dt == 0) --l;
+    }
+    return l;
+}
+
 // New level of each particle corrected last (Eq. timestep, power-of-two rules).
 __global__ void __launch_bounds__(WG) sched_newlevel(StateRW s, const int32_t *active,
                                                      const double *crit, double eta,
@@ -626,14 +773,7 @@ __global__ void __launch_bounds__(WG) sched_newlevel(StateRW s, const int32_t *a
         const double dt = den > 0.0 ? __builtin_sqrt(eta * num / den) : __builtin_inf();
         if (__builtin_isnan(dt)) ctl->flag_nonfinite = 1;
         else if (dt < s.tick_len) ctl->flag_dtmin = 1;
-        int32_t l = s.level[i];
-        if (dt < __builtin_ldexp(1.0, -l)) {
-            while (l < lmax && __builtin_ldexp(1.0, -l) > dt) ++l;
-        } else if (l > lmin && dt >= __builtin_ldexp(1.0, -(l - 1))) {
-            const int64_t two_dt = (int64_t)1 << (lmax - l + 1);
-            if (s.tick[i] % two_dt == 0) --l;
-        }
-        s.level[i] = l;
+        s.level[i] = next_level(dt, s.level[i], s.tick[i], lmin, lmax);
     }
 }
 

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/nbody.h"
+#include "ensemble.hpp"
 #include "kernels.hpp"
 
 using namespace nbody;
@@ -81,7 +82,42 @@ struct nb_ctx {
     std::string err;
 };
 
+struct nb_ens {
+    int32_t C = 0, ntot = 0, lmin = 0, lmax = 0, prec = 0;
+    int device = 0, num_cu = 256;
+    hipStream_t stream = nullptr, cap_stream = nullptr;
+    nb_state st{};
+    bool bound = false, initialised = false;
+    std::vector<int32_t> off_h, tpi_h, K_h, prow_h;
+    std::vector<int64_t> part_off_h;
+    std::vector<double> eps2_h;
+    int32_t *off = nullptr, *K = nullptr, *tpi = nullptr, *prow = nullptr, *active = nullptr;
+    int32_t *flags = nullptr, *item_start = nullptr;
+    int64_t *part_off = nullptr;
+    double *eps2 = nullptr, *partial = nullptr, *crit = nullptr, *ek = nullptr, *ep = nullptr;
+    EnsCluster *cl = nullptr;
+    int32_t unroll = 2, grid_force = 1;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    double g_eta = -1.0;
+    int64_t g_tend = -1;
+    int32_t g_steps = 0;
+    std::string err;
+};
+
 namespace {
+
+nb_status fail(nb_ens *e, nb_status s, const char *fmt, ...) {
+    if (e) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        e->err = buf;
+    }
+    return s;
+}
 
 nb_status fail(nb_ctx *c, nb_status s, const char *fmt, ...) {
     if (c) {
@@ -705,6 +741,312 @@ nb_status nb_sync(nb_ctx *c) {
     if (!c) return NB_EINVAL;
     HIP_OK(c, hipSetDevice(c->device));
     return latched(c);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// Ensemble of independent clusters
+// ------------------------------------------------------------------------------------------
+namespace {
+
+EnsView ens_view(const nb_ens *e, int64_t t_end) {
+    EnsView v;
+    v.C = e->C; v.off = e->off; v.K = e->K; v.tpi = e->tpi; v.part_off = e->part_off;
+    v.prow = e->prow; v.eps2 = e->eps2; v.cl = e->cl; v.active = e->active;
+    v.item_start = e->item_start; v.partial = e->partial; v.crit = e->crit; v.flags = e->flags;
+    v.lmin = e->lmin; v.lmax = e->lmax; v.tick_len = std::ldexp(1.0, -e->lmax); v.t_end = t_end;
+    return v;
+}
+
+StateRW ens_state(const nb_ens *e) {
+    return StateRW{e->st.x, e->st.v, e->st.a, e->st.k, e->st.m, e->st.pot, e->st.tick,
+                   e->st.level, e->ntot, std::ldexp(1.0, -e->lmax)};
+}
+
+// K of each cluster from its tiles per item; the partial planes were sized for tpi = 1.
+void ens_derive(nb_ens *e) {
+    e->K_h.resize(e->C);
+    int64_t items = 0;
+    for (int32_t c = 0; c < e->C; ++c) {
+        const int32_t n_c = e->off_h[c + 1] - e->off_h[c];
+        const int32_t ntiles = (n_c + TJ - 1) / TJ;
+        e->K_h[c] = (ntiles + e->tpi_h[c] - 1) / e->tpi_h[c];
+        items += (int64_t)((n_c + WG - 1) / WG) * e->K_h[c];
+    }
+    e->grid_force = (int32_t)std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)e->num_cu * 8));
+}
+
+#define EHIP_OK(ens, call)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ens), NB_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));   \
+    } while (0)
+
+#define ELAUNCH_OK(ens)                                                                      \
+    do {                                                                                     \
+        hipError_t e_ = hipGetLastError();                                                   \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ens), NB_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+template <class M>
+void ens_launch_force(nb_ens *e, const EnsView &v, hipStream_t s) {
+    const StateRW rw = ens_state(e);
+    const size_t lds = (size_t)(e->C + 1) * sizeof(int32_t);
+    if (e->unroll == 1) ens_force<M, 1><<<e->grid_force, WG, lds, s>>>(v, rw);
+    else ens_force<M, 2><<<e->grid_force, WG, lds, s>>>(v, rw);
+}
+
+nb_status ens_enqueue_local(nb_ens *e, double eta, int32_t phase, int64_t t_end, hipStream_t s) {
+    ens_local<<<e->C, WGL, 0, s>>>(ens_view(e, t_end), ens_state(e), eta, phase);
+    ELAUNCH_OK(e);
+    return NB_OK;
+}
+
+nb_status ens_enqueue_force(nb_ens *e, int64_t t_end, hipStream_t s) {
+    const EnsView v = ens_view(e, t_end);
+    ens_plan<<<1, WGL, 0, s>>>(v);
+    ELAUNCH_OK(e);
+    switch (e->prec) {
+        case NB_FP32: ens_launch_force<ModeF32>(e, v, s); break;
+        case NB_DS: ens_launch_force<ModeDS>(e, v, s); break;
+        default: ens_launch_force<ModeF64>(e, v, s); break;
+    }
+    ELAUNCH_OK(e);
+    return NB_OK;
+}
+
+// One global step: the force of every cluster's selected block, then each cluster corrects it
+// and selects and predicts its next block.
+nb_status ens_enqueue_step(nb_ens *e, double eta, int64_t t_end, hipStream_t s) {
+    nb_status r = ens_enqueue_force(e, t_end, s);
+    if (r != NB_OK) return r;
+    return ens_enqueue_local(e, eta, 2, t_end, s);
+}
+
+nb_status ens_upload_tables(nb_ens *e) {
+    EHIP_OK(e, hipMemcpy(e->K, e->K_h.data(), e->C * sizeof(int32_t), hipMemcpyHostToDevice));
+    EHIP_OK(e, hipMemcpy(e->tpi, e->tpi_h.data(), e->C * sizeof(int32_t), hipMemcpyHostToDevice));
+    return NB_OK;
+}
+
+void ens_drop_graph(nb_ens *e) {
+    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+    if (e->graph) (void)hipGraphDestroy(e->graph);
+    e->gexec = nullptr;
+    e->graph = nullptr;
+    e->g_steps = 0;
+}
+
+nb_status ens_flags(nb_ens *e) {
+    int32_t f[2];
+    EHIP_OK(e, hipMemcpyAsync(f, e->flags, sizeof f, hipMemcpyDeviceToHost, e->stream));
+    EHIP_OK(e, hipStreamSynchronize(e->stream));
+    if (f[0]) return fail(e, NB_ENONFINITE, "non-finite force or state on device");
+    if (f[1]) return fail(e, NB_EDTMIN, "time step below 2^-%d requested (clamped)", e->lmax);
+    return NB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nb_ens_last_error(const nb_ens *e) { return e ? e->err.c_str() : "null ensemble"; }
+
+nb_status nb_ens_create(nb_ens **out, int32_t n_clusters, const int32_t *offsets,
+                        const double *eps, int32_t lmin, int32_t lmax, int32_t precision) {
+    if (!out) return NB_EINVAL;
+    *out = nullptr;
+    if (n_clusters < 1 || !offsets || !eps || lmin < 0 || lmax < lmin || lmax > 52 ||
+        precision < NB_FP32 || precision > NB_FP64 || offsets[0] != 0)
+        return NB_EINVAL;
+    for (int32_t c = 0; c < n_clusters; ++c)
+        if (offsets[c + 1] <= offsets[c] || !(eps[c] > 0.0) || !std::isfinite(eps[c])) return NB_EINVAL;
+    if (offsets[n_clusters] > (1 << 28) || n_clusters > 8192) return NB_EINVAL;
+    nb_ens *e = new nb_ens();
+    e->C = n_clusters; e->ntot = offsets[n_clusters]; e->lmin = lmin; e->lmax = lmax;
+    e->prec = precision;
+    if (hipGetDevice(&e->device) != hipSuccess) { delete e; return NB_EDEVICE; }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, e->device) == hipSuccess && prop.multiProcessorCount > 0)
+        e->num_cu = prop.multiProcessorCount;
+    e->off_h.assign(offsets, offsets + n_clusters + 1);
+    e->eps2_h.resize(n_clusters);
+    for (int32_t c = 0; c < n_clusters; ++c) e->eps2_h[c] = eps[c] * eps[c];
+    e->tpi_h.assign(n_clusters, 1);
+    e->prow_h.resize(n_clusters);
+    e->part_off_h.resize(n_clusters + 1);
+    e->part_off_h[0] = 0;
+    for (int32_t c = 0; c < n_clusters; ++c) {
+        const int32_t n_c = offsets[c + 1] - offsets[c];
+        e->prow_h[c] = n_c;
+        e->part_off_h[c + 1] = e->part_off_h[c] + (int64_t)((n_c + TJ - 1) / TJ) * 7 * n_c;
+    }
+    e->unroll = 2;
+    ens_derive(e);
+    const size_t C = (size_t)n_clusters, N = (size_t)e->ntot;
+    auto A = [&](void **p, size_t bytes) {
+        return hipMalloc(p, bytes > 0 ? bytes : 16) == hipSuccess;
+    };
+    void *p;
+    bool ok = true;
+    ok = ok && A(&p, (C + 1) * sizeof(int32_t)); if (ok) e->off = (int32_t *)p;
+    ok = ok && A(&p, C * sizeof(int32_t)); if (ok) e->K = (int32_t *)p;
+    ok = ok && A(&p, C * sizeof(int32_t)); if (ok) e->tpi = (int32_t *)p;
+    ok = ok && A(&p, C * sizeof(int32_t)); if (ok) e->prow = (int32_t *)p;
+    ok = ok && A(&p, (C + 1) * sizeof(int64_t)); if (ok) e->part_off = (int64_t *)p;
+    ok = ok && A(&p, C * sizeof(double)); if (ok) e->eps2 = (double *)p;
+    ok = ok && A(&p, C * sizeof(EnsCluster)); if (ok) e->cl = (EnsCluster *)p;
+    ok = ok && A(&p, N * sizeof(int32_t)); if (ok) e->active = (int32_t *)p;
+    ok = ok && A(&p, 2 * sizeof(int32_t)); if (ok) e->flags = (int32_t *)p;
+    ok = ok && A(&p, (C + 1) * sizeof(int32_t)); if (ok) e->item_start = (int32_t *)p;
+    ok = ok && A(&p, (size_t)e->part_off_h[C] * sizeof(double)); if (ok) e->partial = (double *)p;
+    ok = ok && A(&p, 2 * N * sizeof(double)); if (ok) e->crit = (double *)p;
+    ok = ok && A(&p, 2 * C * sizeof(double)); if (ok) { e->ek = (double *)p; e->ep = e->ek + C; }
+    if (!ok) { nb_ens_destroy(e); return NB_ENOMEM; }
+    ok = hipMemcpy(e->off, e->off_h.data(), (C + 1) * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(e->prow, e->prow_h.data(), C * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(e->part_off, e->part_off_h.data(), (C + 1) * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(e->eps2, e->eps2_h.data(), C * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemset(e->flags, 0, 2 * sizeof(int32_t)) == hipSuccess &&
+         hipMemset(e->cl, 0, C * sizeof(EnsCluster)) == hipSuccess &&
+         ens_upload_tables(e) == NB_OK &&
+         hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking) == hipSuccess &&
+         hipDeviceSynchronize() == hipSuccess;
+    if (!ok) { nb_ens_destroy(e); return NB_EDEVICE; }
+    *out = e;
+    return NB_OK;
+}
+
+nb_status nb_ens_destroy(nb_ens *e) {
+    if (!e) return NB_OK;
+    (void)hipSetDevice(e->device);
+    (void)hipDeviceSynchronize();
+    ens_drop_graph(e);
+    void *bufs[] = {e->off, e->K, e->tpi, e->prow, e->part_off, e->eps2, e->cl, e->active,
+                    e->flags, e->item_start, e->partial, e->crit, e->ek};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
+    delete e;
+    return NB_OK;
+}
+
+nb_status nb_ens_set_stream(nb_ens *e, void *stream) {
+    if (!e) return NB_EINVAL;
+    e->stream = (hipStream_t)stream;
+    return NB_OK;
+}
+
+nb_status nb_ens_bind(nb_ens *e, const nb_state *s) {
+    if (!e || !s) return NB_EINVAL;
+    if (!s->x || !s->v || !s->a || !s->k || !s->m || !s->pot || !s->tick || !s->level)
+        return fail(e, NB_EINVAL, "nb_ens_bind: every state array is required");
+    e->st = *s;
+    e->bound = true;
+    e->initialised = false;
+    ens_drop_graph(e);
+    return NB_OK;
+}
+
+nb_status nb_ens_set_layout(nb_ens *e, const int32_t *tiles_per_item, int32_t ipl, int32_t unroll) {
+    if (!e) return NB_EINVAL;
+    if (ipl != 1 || (unroll != 1 && unroll != 2))
+        return fail(e, NB_EINVAL, "layout ipl=%d unroll=%d not available", ipl, unroll);
+    if (tiles_per_item)
+        for (int32_t c = 0; c < e->C; ++c)
+            if (tiles_per_item[c] < 1) return fail(e, NB_EINVAL, "tiles per item must be >= 1");
+    EHIP_OK(e, hipSetDevice(e->device));
+    EHIP_OK(e, hipStreamSynchronize(e->stream));
+    if (tiles_per_item) e->tpi_h.assign(tiles_per_item, tiles_per_item + e->C);
+    e->unroll = unroll;
+    ens_derive(e);
+    ens_drop_graph(e);
+    return ens_upload_tables(e);
+}
+
+nb_status nb_ens_init(nb_ens *e, double eta) {
+    if (!e) return NB_EINVAL;
+    if (!e->bound) return fail(e, NB_ESTATE, "state not bound");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return fail(e, NB_EINVAL, "eta must be > 0");
+    EHIP_OK(e, hipSetDevice(e->device));
+    EHIP_OK(e, hipMemsetAsync(e->flags, 0, 2 * sizeof(int32_t), e->stream));
+    nb_status r;
+    if ((r = ens_enqueue_local(e, eta, 0, INT64_MAX, e->stream)) != NB_OK) return r;
+    if ((r = ens_enqueue_force(e, INT64_MAX, e->stream)) != NB_OK) return r;
+    if ((r = ens_enqueue_local(e, eta, 1, INT64_MAX, e->stream)) != NB_OK) return r;
+    e->initialised = true;
+    return NB_OK;
+}
+
+nb_status nb_ens_run(nb_ens *e, double eta, int64_t t_end, int32_t steps_per_launch,
+                     int64_t max_steps, int32_t use_graph) {
+    if (!e) return NB_EINVAL;
+    if (!e->initialised) return fail(e, NB_ESTATE, "nb_ens_run before nb_ens_init");
+    if (!(eta > 0.0) || steps_per_launch < 1) return fail(e, NB_EINVAL, "bad arguments");
+    EHIP_OK(e, hipSetDevice(e->device));
+    if (use_graph && (!e->gexec || e->g_eta != eta || e->g_tend != t_end ||
+                      e->g_steps != steps_per_launch)) {
+        ens_drop_graph(e);
+        EHIP_OK(e, hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal));
+        nb_status rs = NB_OK;
+        for (int32_t i = 0; i < steps_per_launch && rs == NB_OK; ++i)
+            rs = ens_enqueue_step(e, eta, t_end, e->cap_stream);
+        hipGraph_t g = nullptr;
+        hipError_t ec = hipStreamEndCapture(e->cap_stream, &g);
+        if (rs != NB_OK) { if (g) (void)hipGraphDestroy(g); return rs; }
+        if (ec != hipSuccess) return fail(e, NB_EDEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+        e->graph = g;
+        EHIP_OK(e, hipGraphInstantiate(&e->gexec, e->graph, nullptr, nullptr, 0));
+        e->g_eta = eta; e->g_tend = t_end; e->g_steps = steps_per_launch;
+    }
+    std::vector<EnsCluster> h(e->C);
+    int64_t done_steps = 0;
+    for (;;) {
+        if (use_graph) {
+            EHIP_OK(e, hipGraphLaunch(e->gexec, e->stream));
+        } else {
+            for (int32_t i = 0; i < steps_per_launch; ++i) {
+                nb_status r = ens_enqueue_step(e, eta, t_end, e->stream);
+                if (r != NB_OK) return r;
+            }
+        }
+        done_steps += steps_per_launch;
+        EHIP_OK(e, hipMemcpyAsync(h.data(), e->cl, e->C * sizeof(EnsCluster), hipMemcpyDeviceToHost, e->stream));
+        EHIP_OK(e, hipStreamSynchronize(e->stream));
+        bool all = true;
+        for (const auto &x : h) all = all && x.done;
+        if (all || (max_steps > 0 && done_steps >= max_steps)) break;
+    }
+    return ens_flags(e);
+}
+
+nb_status nb_ens_control(nb_ens *e, nb_control *out) {
+    if (!e || !out) return NB_EINVAL;
+    EHIP_OK(e, hipSetDevice(e->device));
+    std::vector<EnsCluster> h(e->C);
+    EHIP_OK(e, hipMemcpyAsync(h.data(), e->cl, e->C * sizeof(EnsCluster), hipMemcpyDeviceToHost, e->stream));
+    EHIP_OK(e, hipStreamSynchronize(e->stream));
+    for (int32_t c = 0; c < e->C; ++c) {
+        out[c].t_cur = h[c].t_cur; out[c].t_next = h[c].t_next; out[c].t_end = e->g_tend;
+        out[c].n_steps = h[c].n_steps; out[c].n_active_sum = h[c].n_active_sum;
+        out[c].n_act = h[c].n_act; out[c].flags = h[c].done;
+    }
+    return ens_flags(e);
+}
+
+nb_status nb_ens_energy(nb_ens *e, double *ekin, double *epot) {
+    if (!e || !ekin || !epot) return NB_EINVAL;
+    if (!e->initialised) return fail(e, NB_ESTATE, "nb_ens_energy before nb_ens_init");
+    EHIP_OK(e, hipSetDevice(e->device));
+    ens_energy<<<e->C, WG, 0, e->stream>>>(ens_view(e, INT64_MAX), ens_state(e), e->ek, e->ep);
+    ELAUNCH_OK(e);
+    EHIP_OK(e, hipMemcpyAsync(ekin, e->ek, e->C * sizeof(double), hipMemcpyDeviceToHost, e->stream));
+    EHIP_OK(e, hipMemcpyAsync(epot, e->ep, e->C * sizeof(double), hipMemcpyDeviceToHost, e->stream));
+    EHIP_OK(e, hipStreamSynchronize(e->stream));
+    return ens_flags(e);
 }
 
 }  // extern "C"

@@ -47,7 +47,10 @@ class nb_variant(ctypes.Structure):
 EXPORTS = ["nb_create", "nb_destroy", "nb_set_stream", "nb_bind", "nb_init",
            "nb_schedule_block", "nb_active", "nb_predict", "nb_force", "nb_correct", "nb_step",
            "nb_run", "nb_energy", "nb_read_control", "nb_get_variant", "nb_set_variant",
-           "nb_tune", "nb_profile", "nb_profile_read", "nb_sync", "nb_last_error", "nb_version"]
+           "nb_tune", "nb_profile", "nb_profile_read", "nb_sync", "nb_last_error", "nb_version",
+           "nb_ens_create", "nb_ens_destroy", "nb_ens_set_stream", "nb_ens_bind",
+           "nb_ens_set_layout", "nb_ens_init", "nb_ens_run", "nb_ens_control", "nb_ens_energy",
+           "nb_ens_last_error"]
 
 _lib = None
 
@@ -86,6 +89,15 @@ def load_library(path: str = LIB_PATH):
         "nb_profile": [P, I32],
         "nb_profile_read": [P, I32, ctypes.POINTER(D), ctypes.POINTER(I64)],
         "nb_sync": [P],
+        "nb_ens_create": [ctypes.POINTER(P), I32, P, P, I32, I32, I32],
+        "nb_ens_destroy": [P],
+        "nb_ens_set_stream": [P, P],
+        "nb_ens_bind": [P, ctypes.POINTER(nb_state)],
+        "nb_ens_set_layout": [P, P, I32, I32],
+        "nb_ens_init": [P, D],
+        "nb_ens_run": [P, D, I64, I32, I64, I32],
+        "nb_ens_control": [P, ctypes.POINTER(nb_control)],
+        "nb_ens_energy": [P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -93,6 +105,8 @@ def load_library(path: str = LIB_PATH):
         f.restype = ctypes.c_int
     lib.nb_last_error.argtypes = [P]
     lib.nb_last_error.restype = ctypes.c_char_p
+    lib.nb_ens_last_error.argtypes = [P]
+    lib.nb_ens_last_error.restype = ctypes.c_char_p
     lib.nb_version.argtypes = []
     lib.nb_version.restype = ctypes.c_char_p
     if path == LIB_PATH:
@@ -326,3 +340,84 @@ def force_on_state(x, v, m, eps, precision="fp32", idx=None, device="cuda"):
             ctx.nb_force(acc, jerk, pot, i_idx=ii)
         ctx.nb_sync()
         return acc.cpu().numpy().T.copy(), jerk.cpu().numpy().T.copy(), pot.cpu().numpy()
+
+
+class Ensemble:
+    """Many independent clusters stepped together (nb_ens_*).  `sizes`: particles per
+    cluster; `eps`: softening per cluster; the state is one DeviceState over all particles,
+    clusters contiguous in the given order."""
+
+    def __init__(self, sizes, eps, lmin=3, lmax=26, precision="fp32", stream=None):
+        self.lib = load_library()
+        sizes = np.asarray(sizes, np.int64)
+        self.C = int(sizes.size)
+        self.offsets = np.zeros(self.C + 1, np.int32)
+        self.offsets[1:] = np.cumsum(sizes)
+        self.eps = np.ascontiguousarray(np.broadcast_to(np.asarray(eps, np.float64), (self.C,)))
+        self.lmin, self.lmax, self.precision = int(lmin), int(lmax), precision
+        h = ctypes.c_void_p()
+        st = self.lib.nb_ens_create(ctypes.byref(h), self.C,
+                                    self.offsets.ctypes.data_as(ctypes.c_void_p),
+                                    self.eps.ctypes.data_as(ctypes.c_void_p), self.lmin, self.lmax,
+                                    PRECISIONS[precision])
+        if st != NB_OK:
+            raise NBodyError(st, "nb_ens_create failed")
+        self.h = h
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self._check(self.lib.nb_ens_set_stream(self.h, ctypes.c_void_p(s.cuda_stream)))
+
+    def _check(self, status):
+        if status != NB_OK:
+            raise NBodyError(status, self.lib.nb_ens_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nb_ens_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def nb_ens_bind(self, state: DeviceState):
+        assert state.n == int(self.offsets[-1])
+        self.state = state
+        self._struct = state.as_struct()
+        self._check(self.lib.nb_ens_bind(self.h, ctypes.byref(self._struct)))
+
+    def nb_ens_set_layout(self, tiles_per_item=None, ipl=1, unroll=2):
+        arr = None
+        if tiles_per_item is not None:
+            self._tpi = np.ascontiguousarray(np.broadcast_to(np.asarray(tiles_per_item, np.int32),
+                                                             (self.C,)))
+            arr = self._tpi.ctypes.data_as(ctypes.c_void_p)
+        self._check(self.lib.nb_ens_set_layout(self.h, arr, int(ipl), int(unroll)))
+
+    def nb_ens_init(self, eta):
+        self._check(self.lib.nb_ens_init(self.h, float(eta)))
+
+    def nb_ens_run(self, eta, t_end, steps_per_launch=16, max_steps=0, use_graph=True):
+        t_ticks = int(round(float(t_end) * 2.0 ** self.lmax))
+        self._check(self.lib.nb_ens_run(self.h, float(eta), t_ticks, int(steps_per_launch),
+                                        int(max_steps), int(bool(use_graph))))
+
+    def nb_ens_control(self):
+        arr = (nb_control * self.C)()
+        self._check(self.lib.nb_ens_control(self.h, arr))
+        return [Control(c.t_cur, c.t_next, c.t_end, c.n_steps, c.n_active_sum, c.n_act, c.flags)
+                for c in arr]
+
+    def nb_ens_energy(self):
+        ek = np.zeros(self.C); ep = np.zeros(self.C)
+        self._check(self.lib.nb_ens_energy(self.h, ek.ctypes.data_as(ctypes.c_void_p),
+                                           ep.ctypes.data_as(ctypes.c_void_p)))
+        return ek, ep

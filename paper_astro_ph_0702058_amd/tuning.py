@@ -52,3 +52,48 @@ def autotune(ctx, cache_path: str | None = DEFAULT_CACHE, reps: int = 2, retune:
         except OSError:
             pass
     return chosen
+
+
+def ensemble_autotune(ens, state, x0, v0, eta, t_probe=1.0 / 32, steps_per_launch=32):
+    """Choose the ensemble's force work layout by timing short runs from the initial state:
+    first the j-loop unroll (all clusters one tile per item), then, for each
+    size class of clusters (N < 512, 512 <= N < 2048, N >= 2048), the whole j-tiles per work
+    item.  The state is restored from (x0, v0) before every trial and after tuning.
+    Returns the chosen layout."""
+    import time
+    import numpy as np
+    import torch
+
+    sizes = np.diff(ens.offsets)
+    classes = [sizes < 512, (sizes >= 512) & (sizes < 2048), sizes >= 2048]
+
+    def trial(tpi, ipl, unroll):
+        ens.nb_ens_set_layout(tpi, ipl, unroll)
+        state.x.copy_(x0); state.v.copy_(v0)
+        ens.nb_ens_init(eta)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ens.nb_ens_run(eta, t_probe, steps_per_launch=steps_per_launch)
+        return time.perf_counter() - t
+
+    tpi = np.ones(ens.C, np.int32)
+    combos = [(1, 2), (1, 1)]
+    timed = {c: trial(tpi, *c) for c in combos}
+    ipl, unroll = min(timed, key=timed.get)
+    best = timed[(ipl, unroll)]
+    for mask in classes:
+        if not mask.any():
+            continue
+        choice = 1
+        for cand in (2, 4, 8):
+            t2 = tpi.copy()
+            t2[mask] = cand
+            t = trial(t2, ipl, unroll)
+            if t < best:
+                best, choice = t, cand
+        tpi[mask] = choice
+    ens.nb_ens_set_layout(tpi, ipl, unroll)
+    state.x.copy_(x0); state.v.copy_(v0)
+    return {"ipl": int(ipl), "unroll": int(unroll),
+            "tiles_per_item_by_class": [int(tpi[m][0]) if m.any() else None for m in classes],
+            "probe_seconds": best}

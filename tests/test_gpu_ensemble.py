@@ -1,0 +1,102 @@
+"""GPU parity of the ensemble path (nb_ens_*): every cluster of an ensemble integrated together
+must match an independent oracle run of that cluster."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_astro_ph_0702058_amd import nbody
+from paper_astro_ph_0702058_amd.plummer import ensemble_sizes, plummer
+
+pytestmark = pytest.mark.gpu
+
+LMAX = 26
+
+
+def build(sizes, seed0=100):
+    xs, vs, ms = [], [], []
+    for c, n in enumerate(sizes):
+        x, v, m = plummer(int(n), seed0 + c)
+        xs.append(x); vs.append(v); ms.append(m)
+    return xs, vs, ms
+
+
+def run_ensemble(sizes, eps, eta, t_end, prec, lmin=3, layout=None, graph=True, spl=8):
+    xs, vs, ms = build(sizes)
+    st = nbody.DeviceState(np.concatenate(xs), np.concatenate(vs), np.concatenate(ms))
+    ens = nbody.Ensemble(sizes, eps, lmin=lmin, lmax=LMAX, precision=prec)
+    ens.nb_ens_bind(st)
+    if layout:
+        ens.nb_ens_set_layout(**layout)
+    ens.nb_ens_init(eta)
+    e0 = ens.nb_ens_energy()
+    ens.nb_ens_run(eta, t_end, steps_per_launch=spl, max_steps=200000, use_graph=graph)
+    ctl = ens.nb_ens_control()
+    e1 = ens.nb_ens_energy()
+    g = st.numpy()
+    ens.close()
+    return xs, vs, ms, g, ctl, e0, e1
+
+
+def test_ensemble_fp64_matches_independent_oracle_runs():
+    """Six clusters of uneven size (tiles plus ragged tails), eps = 1/N_c, eta = 0.02, to
+    t = 1/8, FP64 interaction: each cluster follows its own oracle run step for step."""
+    sizes = [64, 100, 257, 300, 513, 1000]
+    eps = [1.0 / n for n in sizes]
+    xs, vs, ms, g, ctl, e0, e1 = run_ensemble(sizes, eps, 0.02, 0.125, "fp64")
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    for c, n in enumerate(sizes):
+        ref = oracle.BlockIntegrator(xs[c], vs[c], ms[c], eps=eps[c], nu=0.02, lmin=3)
+        E0 = ref.energy()
+        ref.run_until(0.125)
+        sl = slice(off[c], off[c + 1])
+        assert ctl[c].n_steps == ref.n_steps, (c, ctl[c].n_steps, ref.n_steps)
+        assert ctl[c].n_active_sum == ref.n_active_total
+        assert ctl[c].t_cur == ref.t and ctl[c].flags == 1
+        assert np.array_equal(g["level"][sl], ref.level) and np.array_equal(g["tick"][sl], ref.tick)
+        assert np.max(np.abs(g["x"][sl] - ref.x)) < 1e-10, c
+        assert abs((e0[0][c] + e0[1][c]) - E0) < 1e-13 * abs(E0)
+        assert abs((e1[0][c] + e1[1][c]) - ref.energy()) < 1e-11 * abs(E0)
+
+
+def test_ensemble_layouts_agree():
+    """Different work layouts (tiles per item, unroll) only reorder sums."""
+    sizes = [70, 600, 1300]
+    eps = [1.0 / n for n in sizes]
+    outs = []
+    for layout in (dict(tiles_per_item=1, ipl=1, unroll=2), dict(tiles_per_item=4, ipl=1, unroll=1),
+                   dict(tiles_per_item=[1, 2, 3], ipl=1, unroll=2)):
+        *_, g, ctl, e0, e1 = run_ensemble(sizes, eps, 0.02, 1 / 32, "fp64", layout=layout)
+        outs.append((g, [c.n_steps for c in ctl]))
+    for g, steps in outs[1:]:
+        assert steps == outs[0][1]
+        assert np.max(np.abs(g["x"] - outs[0][0]["x"])) < 1e-12
+
+
+def test_ensemble_graph_equals_eager():
+    sizes = [90, 400, 700]
+    eps = [1.0 / n for n in sizes]
+    a = run_ensemble(sizes, eps, 0.02, 1 / 16, "fp32", graph=False, spl=4)
+    b = run_ensemble(sizes, eps, 0.02, 1 / 16, "fp32", graph=True, spl=4)
+    for key in ("x", "v", "tick", "level"):
+        assert np.array_equal(a[3][key], b[3][key]), key
+
+
+def test_ensemble_fp32_log_uniform_sizes():
+    """48 clusters, sizes log-uniform in [64, 4096], eps = 1/N_c, eta = 0.02, to t = 1/4, in FP32
+    and in FP64 (the FP64 ensemble follows the oracle step for step, see above): every cluster
+    finishes; at eta = 0.02 the energy error is the integrator's (Sec. 4.2), so the FP32 run's
+    error stays within 10x of the FP64 run's (plus 1e-6), and step counts agree within 10 %."""
+    sizes = ensemble_sizes(48, 4)
+    eps = 1.0 / sizes
+    res = {}
+    for prec in ("fp32", "fp64"):
+        xs, vs, ms, g, ctl, e0, e1 = run_ensemble(sizes, eps, 0.02, 0.25, prec, spl=16)
+        de = np.abs((e1[0] + e1[1]) - (e0[0] + e0[1])) / np.abs(e0[0] + e0[1])
+        assert all(c.flags == 1 and c.t_cur == 1 << (LMAX - 2) for c in ctl)
+        res[prec] = (de, np.array([c.n_steps for c in ctl]))
+    de32, st32 = res["fp32"]
+    de64, st64 = res["fp64"]
+    print("dE/E fp32 median %.2e max %.2e; fp64 median %.2e max %.2e" %
+          (np.median(de32), de32.max(), np.median(de64), de64.max()), flush=True)
+    assert np.all(de32 <= 10 * de64 + 1e-6), np.max(de32 / (10 * de64 + 1e-6))
+    assert np.all(np.abs(st32 - st64) <= 0.1 * st64)

@@ -151,3 +151,17 @@ def test_argument_errors_on_device():
         with pytest.raises(nbody.NBodyError) as e:
             ctx.nb_force(acc, acc, acc[0])          # not predicted yet
         assert e.value.status == nbody.NB_ESTATE
+
+
+@pytest.mark.parametrize("prec", ["fp32", "ds", "fp64"])
+@pytest.mark.parametrize("n_i", [1, 3, 37, 130, 255])
+def test_force_small_lists_lane_split(prec, n_i):
+    """Fewer i-particles than a workgroup: several lanes share each i, take interleaved j of
+    every tile and are combined by wave shuffles; eps > 0 and eps = 0."""
+    n = 5000
+    x, v, m = plummer(n, 17)
+    idx = sample_indices(n, n_i, 9 + n_i)
+    for eps in (1 / 256, 0.0):
+        got = nbody.force_on_state(x, v, m, eps, prec, idx=idx)
+        ref = oracle.force(x, v, m, eps * eps, idx=idx)
+        check(prec, got, ref, f"n_i={n_i} eps={eps}")
