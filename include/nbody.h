@@ -80,7 +80,7 @@ typedef struct {
 /* Create a context for n particles (1 <= n <= 2^28) with Plummer softening eps >= 0, largest
  * step 2^-lmin and smallest step 2^-lmax (0 <= lmin <= lmax <= 52), interaction arithmetic
  * `precision`.  Allocates the library's own device work buffers on the current device (about
- * 200 bytes per particle).  *out is set to NULL on failure. */
+ * 300 bytes per particle plus j-split partial sums).  *out is set to NULL on failure. */
 nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t lmax,
                     int32_t precision);
 
@@ -171,6 +171,30 @@ nb_status nb_profile(nb_ctx *ctx, int32_t enable);
  * launches (which = 1: block steps and small lists) or all (which = -1).  The two classes are
  * also distinct kernel symbols.  Synchronising. */
 nb_status nb_profile_read(nb_ctx *ctx, int32_t which, double *ms_total, int64_t *launches);
+
+/* ------------------------------------------------------------------------------------------
+ * Shared-step runs and their derivatives (fp32 and fp64 contexts).
+ * A shared step advances every particle by the same dt = 2^-l (lmin <= l <= lmax): the
+ * predictor, the force on all particles and the corrector of Sec. 2 with that dt.  Start a run
+ * with nb_init (it sets a, k from the force at time 0).
+ * ------------------------------------------------------------------------------------------ */
+nb_status nb_shared_step(nb_ctx *ctx, double dt, int32_t nsteps);
+
+/* Vector-Jacobian product of the force on all particles (Sec. 2 Eq. Force with App. A
+ * softening) at the predicted stream (call nb_predict first): given abar, kbar (3n each,
+ * adjoints of the accelerations and jerks), ADDS to xbar, vbar (3n, adjoints of the predicted
+ * positions and velocities) and mbar (n, adjoints of the masses) the derivative of
+ * sum_i abar_i . acc_i + kbar_i . jerk_i.  Structure of arrays, leading dimension n. */
+nb_status nb_force_vjp(nb_ctx *ctx, const double *abar, const double *kbar, double *xbar,
+                       double *vbar, double *mbar);
+
+/* Vector-Jacobian product of one shared step of size dt taken from the bound state (x, v, a,
+ * k: the state BEFORE the step; it is not modified).  On entry xbar, vbar, abar, kbar (3n
+ * each) hold the adjoints of the step's outputs (x', v', a', k'); on return, the adjoints of
+ * its inputs (x, v, a, k).  mbar (n) accumulates the masses' adjoint.  Uses the context's own
+ * scratch and the j-particle stream. */
+nb_status nb_step_vjp(nb_ctx *ctx, double dt, double *xbar, double *vbar, double *abar,
+                      double *kbar, double *mbar);
 
 /* Force-kernel launch variant: i-particles held per work-item (ipl), unroll of the j-loop,
  * desired number of equal work items per launch (target; the j-range is split K ways when the

@@ -251,3 +251,43 @@ class SharedStepIntegrator:
     def energy(self):
         ek, ep = energy(self.x, self.v, self.m, self.eps2)
         return ek + ep
+
+
+# ------------------------------------------------------------------ derivatives of shared runs
+def shared_run(x0, v0, m, eps, dt, nsteps):
+    """Final (x, v) of `nsteps` shared Hermite steps of size dt (FP64)."""
+    it = SharedStepIntegrator(x0, v0, m, eps, dt)
+    it.step(nsteps)
+    return it.x, it.v
+
+
+def mean_sq_distance(x, target):
+    """Trajectory loss: mean over particles of |x_i - target_i|^2."""
+    return float(np.mean(np.sum((np.asarray(x) - np.asarray(target)) ** 2, axis=1)))
+
+
+def fd_gradient(x0, v0, m, eps, dt, nsteps, target, coords, rel_h=1e-6, rel_h_mass=1e-3):
+    """Central finite differences of mean_sq_distance(shared_run(...), target) with respect
+    to the listed coordinates: ("x" | "v", particle, component) or ("m", particle, 0).
+    Step h = rel_h * max(|value|, 1) for x and v; rel_h_mass * m_i for a mass (a mass changes
+    the trajectory so little that a smaller step leaves the quotient at the rounding noise of
+    the run)."""
+    x0 = _f64(x0, (-1, 3)); v0 = _f64(v0, (-1, 3)); m = _f64(m)
+    out = []
+    for kind, i, c in coords:
+        arrs = {"x": x0, "v": v0, "m": m}
+        base = arrs[kind]
+        val = base[i, c] if kind != "m" else base[i]
+        h = rel_h * max(abs(val), 1.0) if kind != "m" else rel_h_mass * abs(val)
+        vals = []
+        for sgn in (1, -1):
+            xx, vv, mm = x0.copy(), v0.copy(), m.copy()
+            tgt = {"x": xx, "v": vv, "m": mm}[kind]
+            if kind == "m":
+                tgt[i] = val + sgn * h
+            else:
+                tgt[i, c] = val + sgn * h
+            xf, _ = shared_run(xx, vv, mm, eps, dt, nsteps)
+            vals.append(mean_sq_distance(xf, target))
+        out.append((vals[0] - vals[1]) / (2 * h))
+    return np.array(out)

@@ -1,0 +1,98 @@
+"""Gradients of shared-step Hermite runs through the library's hand-written adjoint.
+
+`HermiteRun.apply(x0, v0, m, runner)` integrates `runner.nsteps` shared steps of size
+`runner.dt` from (x0, v0) with masses m (all (3, n) / (n,) float64 CUDA tensors, structure of
+arrays) and returns the final positions and velocities.  Its backward pass recomputes the
+trajectory from checkpoints kept every `runner.checkpoint_every` steps and applies
+nb_step_vjp step by step in reverse, then the VJP of the initial force evaluation
+(a0, k0 = F(x0, v0, m)); all arithmetic runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import nbody
+
+
+class SharedRunner:
+    """A context and device state for differentiable shared-step runs of n particles."""
+
+    def __init__(self, n, eps, dt, nsteps, checkpoint_every=8, precision="fp32", lmin=0):
+        self.n, self.eps, self.dt = int(n), float(eps), float(dt)
+        self.nsteps, self.checkpoint_every = int(nsteps), int(checkpoint_every)
+        self.ctx = nbody.Context(self.n, self.eps, lmin=lmin, lmax=26, precision=precision)
+        z = torch.zeros((self.n, 3), dtype=torch.float64)
+        self.state = nbody.DeviceState(z.numpy(), z.numpy(), torch.ones(self.n).numpy())
+        self.ctx.nb_bind(self.state)
+        self.t0 = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+    def _load(self, x, v, a=None, k=None):
+        st = self.state
+        st.x.copy_(x); st.v.copy_(v)
+        if a is not None:
+            st.a.copy_(a); st.k.copy_(k)
+
+    def _snapshot(self):
+        st = self.state
+        return (st.x.clone(), st.v.clone(), st.a.clone(), st.k.clone())
+
+    def forward(self, x0, v0, m):
+        """Run from (x0, v0, m); returns (x, v) at the end and the checkpoints."""
+        st = self.state
+        st.m.copy_(m)
+        self._load(x0, v0)
+        self.ctx.nb_init(0.01)           # a0, k0 = F(x0, v0, m); times 0
+        checkpoints = []
+        done = 0
+        while done < self.nsteps:
+            checkpoints.append(self._snapshot())
+            k = min(self.checkpoint_every, self.nsteps - done)
+            self.ctx.nb_shared_step(self.dt, k)
+            done += k
+        self.ctx.nb_sync()
+        return st.x.clone(), st.v.clone(), checkpoints
+
+    def backward(self, x0, v0, m, checkpoints, gx, gv):
+        """Adjoints (x0_bar, v0_bar, m_bar) from those of the final positions and velocities."""
+        n = self.n
+        xb = gx.clone() if gx is not None else torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        vb = gv.clone() if gv is not None else torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        ab = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        kb = torch.zeros_like(ab)
+        mb = torch.zeros(n, dtype=torch.float64, device="cuda")
+        self.state.m.copy_(m)
+        seg_len = [min(self.checkpoint_every, self.nsteps - s * self.checkpoint_every)
+                   for s in range(len(checkpoints))]
+        for seg in reversed(range(len(checkpoints))):
+            # recompute the states before each step of the segment
+            self._load(*checkpoints[seg])
+            states = [checkpoints[seg]]
+            for _ in range(seg_len[seg] - 1):
+                self.ctx.nb_shared_step(self.dt, 1)
+                states.append(self._snapshot())
+            for s in reversed(states):
+                self._load(*s)
+                self.ctx.nb_step_vjp(self.dt, xb, vb, ab, kb, mb)
+        # the initial force a0, k0 = F(x0, v0, m)
+        self._load(x0, v0)
+        self.state.tick.zero_()
+        self.ctx.nb_predict(self.t0)
+        self.ctx.nb_force_vjp(ab, kb, xb, vb, mb)
+        self.ctx.nb_sync()
+        return xb, vb, mb
+
+
+class HermiteRun(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, x0, v0, m, runner: SharedRunner):
+        x, v, cps = runner.forward(x0, v0, m)
+        ctx.runner = runner
+        ctx.cps = cps
+        ctx.save_for_backward(x0, v0, m)
+        return x, v
+
+    @staticmethod
+    def backward(ctx, gx, gv):
+        x0, v0, m = ctx.saved_tensors
+        xb, vb, mb = ctx.runner.backward(x0, v0, m, ctx.cps, gx, gv)
+        return xb, vb, mb, None

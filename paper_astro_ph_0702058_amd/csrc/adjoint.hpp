@@ -1,0 +1,260 @@
+// adjoint.hpp -- gfx950 device code for differentiating shared-step Hermite runs.
+//
+// One shared step of the Sec. 2 scheme with fixed dt, written out as a map of the state
+// (x, v, a, k) and the new force (a1, k1) = F(x_p, v_p, m) at the predicted state:
+//   x_p = x + dt v + dt^2/2 a + dt^3/6 k,         v_p = v + dt a + dt^2/2 k,
+//   x'  = x + dt v + 7/20 dt^2 a + 3/20 dt^2 a1 + 1/20 dt^3 k - 1/30 dt^3 k1,
+//   v'  = v + dt/2 (a + a1) + dt^2/12 (k - k1),    a' = a1,  k' = k1
+// (the corrector's a2 dt^4/24 + a3 dt^5/120 and a2 dt^3/6 + a3 dt^4/24 expanded).  Its
+// vector-Jacobian product is the transposed linear part plus the VJP of F, whose pair form is
+//   phi(d, u; A, B) = A.d s^-3/2 + B.u s^-3/2 - 3 (d.u)(B.d) s^-5/2
+// (A, B: adjoints of the acceleration and jerk of i; d = x_j - x_i, u = v_j - v_i), with
+//   dphi/dd = A s^-3/2 - 3 s^-5/2 [(A.d + B.u) d + (B.d) u + (d.u) B] + 15 s^-7/2 (d.u)(B.d) d
+//   dphi/du = B s^-3/2 - 3 s^-5/2 (B.d) d,      dphi/dm_j = phi / m_j.
+// Every particle p gathers, over all q != p, its i-side terms (A_p, B_p against q) and its
+// j-side terms (A_q, B_q of q against p).
+#pragma once
+
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace nbody {
+
+// Predictor of every particle over the shared step dt, into the j-particle stream.
+template <int MODE>
+__global__ void __launch_bounds__(WG) shared_predict(StateView s, JStreamView js, double dt) {
+    const int32_t n = s.n;
+    for (int32_t i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+        double xp[3], vp[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            predict_one(dt, s.x[c * (int64_t)n + i], s.v[c * (int64_t)n + i],
+                        s.a[c * (int64_t)n + i], s.k[c * (int64_t)n + i], xp[c], vp[c]);
+        const double m = s.m[i];
+        if (MODE == 0) {
+            js.px[i] = xp[0]; js.py[i] = xp[1]; js.pz[i] = xp[2];
+            js.vm[i] = make_float4((float)vp[0], (float)vp[1], (float)vp[2], (float)m);
+        } else {
+            js.px[i] = xp[0]; js.py[i] = xp[1]; js.pz[i] = xp[2]; js.pm[i] = m;
+            js.vx[i] = vp[0]; js.vy[i] = vp[1]; js.vz[i] = vp[2];
+        }
+    }
+}
+
+// Corrector of every particle over the shared step dt (advances each time by dt_ticks).
+__global__ void __launch_bounds__(WG) shared_correct(StateRW s, const double *acc,
+                                                     const double *jerk, const double *pot,
+                                                     double dt, int64_t dt_ticks,
+                                                     int32_t *flag) {
+    const int32_t n = s.n;
+    for (int32_t i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
+        double a1[3], k1[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a1[c] = acc[c * (int64_t)n + i];
+            k1[c] = jerk[c * (int64_t)n + i];
+        }
+        if (!correct_particle(s, i, dt, a1, k1, pot[i], s.tick[i] + dt_ticks, nullptr)) *flag = 1;
+    }
+}
+
+// Step VJP, first part: adjoints of the new force from those of the step's outputs.
+//   a1_bar = 3/20 dt^2 x'_bar + dt/2 v'_bar + a'_bar,  k1_bar = -1/30 dt^3 x'_bar - dt^2/12 v'_bar + k'_bar
+__global__ void __launch_bounds__(WG) vjp_pre(int32_t n, double dt, const double *xb,
+                                              const double *vb, const double *ab,
+                                              const double *kb, double *a1b, double *k1b) {
+    const double dt2 = dt * dt, dt3 = dt2 * dt;
+    for (int64_t e = blockIdx.x * (int64_t)WG + threadIdx.x; e < 3 * (int64_t)n;
+         e += (int64_t)gridDim.x * WG) {
+        a1b[e] = (3.0 / 20.0) * dt2 * xb[e] + 0.5 * dt * vb[e] + ab[e];
+        k1b[e] = -(1.0 / 30.0) * dt3 * xb[e] - (1.0 / 12.0) * dt2 * vb[e] + kb[e];
+    }
+}
+
+// Step VJP, last part: adjoints of the step's inputs, in place, from those of its outputs and
+// of the predicted state (xpb, vpb: the force VJP).
+__global__ void __launch_bounds__(WG) vjp_post(int32_t n, double dt, double *xb, double *vb,
+                                               double *ab, double *kb, const double *xpb,
+                                               const double *vpb) {
+    const double dt2 = dt * dt, dt3 = dt2 * dt;
+    for (int64_t e = blockIdx.x * (int64_t)WG + threadIdx.x; e < 3 * (int64_t)n;
+         e += (int64_t)gridDim.x * WG) {
+        const double X = xb[e], V = vb[e], XP = xpb[e], VP = vpb[e];
+        xb[e] = X + XP;
+        vb[e] = dt * X + V + dt * XP + VP;
+        ab[e] = (7.0 / 20.0) * dt2 * X + 0.5 * dt * V + 0.5 * dt2 * XP + dt * VP;
+        kb[e] = (1.0 / 20.0) * dt3 * X + (1.0 / 12.0) * dt2 * V + (1.0 / 6.0) * dt3 * XP +
+                0.5 * dt2 * VP;
+    }
+}
+
+// Pair terms of the force VJP for particle p against q, arithmetic type T.  d = x_q - x_p,
+// u = v_q - v_p; (A, B) adjoints of p, (Aq, Bq) adjoints of q; rinv = s^-1/2 or 0 (self).
+// Adds the i-side -m_q dphi/d(d,u) and the j-side +m_p dphi/d(d,u) with q's adjoints (the
+// derivatives are even in (d, u)) to gx, gu, and phi at (-d, -u) with q's adjoints to gm.
+template <class T>
+__device__ __forceinline__ void vjp_pair(T dx, T dy, T dz, T ux, T uy, T uz, T rinv, T mp, T mq,
+                                         const T A[3], const T B[3], const T Aq[3],
+                                         const T Bq[3], T gx[3], T gu[3], T &gm) {
+    const T r2 = rinv * rinv, r3 = rinv * r2, r5 = r3 * r2, r7 = r5 * r2;
+    const T du = dx * ux + dy * uy + dz * uz;
+    const T d[3] = {dx, dy, dz}, u[3] = {ux, uy, uz};
+    // i-side, (A, B) of p
+    {
+        const T Ad = A[0] * dx + A[1] * dy + A[2] * dz;
+        const T Bd = B[0] * dx + B[1] * dy + B[2] * dz;
+        const T Bu = B[0] * ux + B[1] * uy + B[2] * uz;
+        const T c1 = -T(3) * r5 * (Ad + Bu) + T(15) * r7 * du * Bd;
+        const T c2 = -T(3) * r5 * Bd;
+        const T c3 = -T(3) * r5 * du;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const T gd = A[k] * r3 + c1 * d[k] + c2 * u[k] + c3 * B[k];
+            const T gv = B[k] * r3 + c2 * d[k];
+            gx[k] -= mq * gd;
+            gu[k] -= mq * gv;
+        }
+    }
+    // j-side, (Aq, Bq) of q acting on p
+    {
+        const T Ad = Aq[0] * dx + Aq[1] * dy + Aq[2] * dz;
+        const T Bd = Bq[0] * dx + Bq[1] * dy + Bq[2] * dz;
+        const T Bu = Bq[0] * ux + Bq[1] * uy + Bq[2] * uz;
+        const T c1 = -T(3) * r5 * (Ad + Bu) + T(15) * r7 * du * Bd;
+        const T c2 = -T(3) * r5 * Bd;
+        const T c3 = -T(3) * r5 * du;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const T gd = Aq[k] * r3 + c1 * d[k] + c2 * u[k] + c3 * Bq[k];
+            const T gv = Bq[k] * r3 + c2 * d[k];
+            gx[k] += mp * gd;
+            gu[k] += mp * gv;
+        }
+        // phi(-d, -u; Aq, Bq)
+        gm += -(Ad + Bu) * r3 + T(3) * du * Bd * r5;
+    }
+}
+
+struct VjpArgs {
+    int32_t n;
+    const double *px, *py, *pz;  // predicted positions (FP64)
+    const float4 *vm;            // FP32 mode: predicted velocity + mass
+    const double *pm, *vx, *vy, *vz;  // FP64 mode
+    const double *ab, *kb;       // adjoints of acc and jerk, 3 x n
+    double eps2;
+    double *partial;             // [K][7][P]
+    int32_t target, kmax;
+};
+
+template <class T>
+struct VjpSmem {
+    double x[TJ], y[TJ], z[TJ];
+    T vx[TJ], vy[TJ], vz[TJ], m[TJ];
+    T A[3][TJ], B[3][TJ];
+};
+
+// Force VJP over all particles; j-split into K ranges, partial sums (7 per particle: x_bar,
+// v_bar, m_bar) per range, summed by vjp_reduce.  MODE 0: float arithmetic on separations
+// formed in double (tile sums folded into double); MODE 2: double throughout.
+template <int MODE>
+__global__ void __launch_bounds__(WG) force_vjp_kernel(VjpArgs a) {
+    using T = typename std::conditional<MODE == 0, float, double>::type;
+    __shared__ VjpSmem<T> sm;
+    const int32_t n = a.n;
+    const ForcePlan pl = make_plan(n, n, WG, a.target, a.kmax);
+    for (int32_t w = blockIdx.x; w < pl.items; w += gridDim.x) {
+        const int32_t iblk = w / pl.K, ks = w - (w / pl.K) * pl.K;
+        const int32_t p = iblk * WG + (int32_t)threadIdx.x;
+        const int32_t pc = p < n ? p : 0;
+        const double xp = a.px[pc], yp = a.py[pc], zp = a.pz[pc];
+        T vxp, vyp, vzp, mp;
+        if (MODE == 0) {
+            const float4 q = a.vm[pc];
+            vxp = q.x; vyp = q.y; vzp = q.z; mp = q.w;
+        } else {
+            vxp = a.vx[pc]; vyp = a.vy[pc]; vzp = a.vz[pc]; mp = a.pm[pc];
+        }
+        T A[3], B[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            A[k] = (T)a.ab[k * (int64_t)n + pc];
+            B[k] = (T)a.kb[k * (int64_t)n + pc];
+        }
+        double S[7] = {0, 0, 0, 0, 0, 0, 0};
+        const T eps2 = (T)a.eps2;
+        const int32_t t0 = ks * pl.tps;
+        const int32_t t1 = t0 + pl.tps < pl.ntiles ? t0 + pl.tps : pl.ntiles;
+        for (int32_t t = t0; t < t1; ++t) {
+            __syncthreads();
+            {
+                const int32_t j = t * TJ + (int32_t)threadIdx.x;
+                const bool ok = j < n;
+                const int32_t jc = ok ? j : 0;
+                sm.x[threadIdx.x] = a.px[jc]; sm.y[threadIdx.x] = a.py[jc]; sm.z[threadIdx.x] = a.pz[jc];
+                if (MODE == 0) {
+                    const float4 q = a.vm[jc];
+                    sm.vx[threadIdx.x] = q.x; sm.vy[threadIdx.x] = q.y; sm.vz[threadIdx.x] = q.z;
+                    sm.m[threadIdx.x] = ok ? q.w : 0.f;
+                } else {
+                    sm.vx[threadIdx.x] = a.vx[jc]; sm.vy[threadIdx.x] = a.vy[jc];
+                    sm.vz[threadIdx.x] = a.vz[jc]; sm.m[threadIdx.x] = ok ? a.pm[jc] : 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    sm.A[k][threadIdx.x] = ok ? (T)a.ab[k * (int64_t)n + jc] : T(0);
+                    sm.B[k][threadIdx.x] = ok ? (T)a.kb[k * (int64_t)n + jc] : T(0);
+                }
+            }
+            __syncthreads();
+            T gx[3] = {0, 0, 0}, gu[3] = {0, 0, 0}, gm = 0;
+            for (int jj = 0; jj < TJ; ++jj) {
+                const T dx = (T)(sm.x[jj] - xp), dy = (T)(sm.y[jj] - yp), dz = (T)(sm.z[jj] - zp);
+                const T ux = sm.vx[jj] - vxp, uy = sm.vy[jj] - vyp, uz = sm.vz[jj] - vzp;
+                const T s = dx * dx + dy * dy + dz * dz + eps2;
+                T rinv;
+                if (MODE == 0) rinv = __builtin_amdgcn_rsqf((float)s);
+                else rinv = (T)rsqrt_f64((double)s);
+                // the self pair and padding (zero mass, zero adjoints) contribute nothing
+                if (t * TJ + jj == p || !(s > T(0))) rinv = T(0);
+                const T Aq[3] = {sm.A[0][jj], sm.A[1][jj], sm.A[2][jj]};
+                const T Bq[3] = {sm.B[0][jj], sm.B[1][jj], sm.B[2][jj]};
+                vjp_pair<T>(dx, dy, dz, ux, uy, uz, rinv, mp, sm.m[jj], A, B, Aq, Bq, gx, gu, gm);
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                S[k] += (double)gx[k];
+                S[3 + k] += (double)gu[k];
+            }
+            S[6] += (double)gm;
+        }
+        if (p < n) {
+            double *base = a.partial + (int64_t)ks * 7 * pl.P + p;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) base[(int64_t)k * pl.P] = S[k];
+        }
+    }
+}
+
+// Sums the K partial planes (fixed order): x_bar, v_bar of the predicted state written to
+// (accumulate = 0) or added to (accumulate = 1) xpb, vpb; m_bar added to mb.
+__global__ void __launch_bounds__(WG) vjp_reduce(int32_t n, const double *partial, int32_t target,
+                                                 int32_t kmax, double *xpb, double *vpb,
+                                                 double *mb, int32_t accumulate) {
+    const ForcePlan pl = make_plan(n, n, WG, target, kmax);
+    for (int32_t p = blockIdx.x * WG + threadIdx.x; p < n; p += gridDim.x * WG) {
+        double o[7] = {0, 0, 0, 0, 0, 0, 0};
+        for (int32_t k = 0; k < pl.K; ++k)
+#pragma unroll
+            for (int c = 0; c < 7; ++c) o[c] += partial[((int64_t)k * 7 + c) * pl.P + p];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t e = c * (int64_t)n + p;
+            xpb[e] = (accumulate ? xpb[e] : 0.0) + o[c];
+            vpb[e] = (accumulate ? vpb[e] : 0.0) + o[3 + c];
+        }
+        mb[p] += o[6];
+    }
+}
+
+}  // namespace nbody

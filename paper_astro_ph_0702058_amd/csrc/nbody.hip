@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/nbody.h"
+#include "adjoint.hpp"
 #include "ensemble.hpp"
 #include "kernels.hpp"
 
@@ -59,6 +60,8 @@ struct nb_ctx {
     DevControl *ctl = nullptr;
     double *exp_ = nullptr, *evp = nullptr, *ew = nullptr, *ek = nullptr, *eout = nullptr;
     int64_t *t_zero = nullptr;
+    double *adj = nullptr;  // a1_bar, k1_bar, xp_bar, vp_bar (3n each) for the step VJP
+    int32_t *adj_flag = nullptr;
 
     int32_t sched_groups = 1, sched_chunk = 1;
     Variant var_full{2, 2, 4096, 256};   // calls on (nearly) all particles
@@ -424,10 +427,14 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
     if ((r = alloc(c, &p, (8 * N + 2) * sizeof(double))) != NB_OK) { nb_destroy(c); return r; }
     c->exp_ = (double *)p; c->evp = c->exp_ + 3 * N; c->ew = c->evp + 3 * N; c->ek = c->ew + N;
     c->eout = c->ek + N;
+    if ((r = alloc(c, &p, 12 * N * sizeof(double) + 16)) != NB_OK) { nb_destroy(c); return r; }
+    c->adj = (double *)p;
+    c->adj_flag = (int32_t *)(c->adj + 12 * N);
     if ((r = alloc(c, &p, 2 * sizeof(int64_t))) != NB_OK) { nb_destroy(c); return r; }
     c->t_zero = (int64_t *)p;
     c->tune_n = (int32_t *)(c->t_zero + 1);
     if (hipMemset(c->t_zero, 0, 2 * sizeof(int64_t)) != hipSuccess ||
+        hipMemset(c->adj_flag, 0, 16) != hipSuccess ||
         hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         nb_destroy(c);
         return NB_EDEVICE;
@@ -449,7 +456,7 @@ nb_status nb_destroy(nb_ctx *c) {
         (void)hipEventDestroy(p.stop);
     }
     void *bufs[] = {c->jbuf, c->acc1, c->partial, c->active, c->crit, c->wgmin, c->cnt, c->ctl,
-                    c->exp_, c->t_zero};
+                    c->exp_, c->t_zero, c->adj};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -629,6 +636,96 @@ nb_status nb_read_control(nb_ctx *c, nb_control *out) {
     out->flags = (h.flag_nonfinite ? 1 : 0) | (h.flag_dtmin ? 2 : 0);
     if (h.flag_nonfinite) return fail(c, NB_ENONFINITE, "non-finite force or state on device");
     if (h.flag_dtmin) return fail(c, NB_EDTMIN, "time step below 2^-%d requested (clamped)", c->lmax);
+    return NB_OK;
+}
+
+static nb_status check_shared_dt(nb_ctx *c, double dt, int64_t *dt_ticks) {
+    int e = 0;
+    const double f = std::frexp(dt, &e);  // dt = f 2^e, f in [0.5, 1)
+    const int l = 1 - e;                  // dt = 2^-l when f == 0.5
+    if (!(dt > 0.0) || f != 0.5 || l < c->lmin || l > c->lmax)
+        return fail(c, NB_EINVAL, "shared step dt must be 2^-l with %d <= l <= %d", c->lmin, c->lmax);
+    *dt_ticks = (int64_t)1 << (c->lmax - l);
+    return NB_OK;
+}
+
+static nb_status enqueue_force_vjp(nb_ctx *c, const double *ab, const double *kb, double *xb,
+                                   double *vb, double *mb, int32_t accumulate, hipStream_t s) {
+    VjpArgs a;
+    a.n = c->n;
+    a.px = c->js.px; a.py = c->js.py; a.pz = c->js.pz; a.vm = c->js.vm;
+    a.pm = c->js.pm; a.vx = c->js.vx; a.vy = c->js.vy; a.vz = c->js.vz;
+    a.ab = ab; a.kb = kb; a.eps2 = c->eps * c->eps; a.partial = c->partial;
+    a.target = c->max_target; a.kmax = 1 << 16;
+    const ForcePlan pl = make_plan(c->n, c->n, WG, a.target, a.kmax);
+    const int32_t grid = std::max(1, std::min(pl.items, 1 << 20));
+    if (c->prec == NB_FP32) force_vjp_kernel<0><<<grid, WG, 0, s>>>(a);
+    else force_vjp_kernel<2><<<grid, WG, 0, s>>>(a);
+    LAUNCH_OK(c);
+    vjp_reduce<<<grid_for(c->n, 4096), WG, 0, s>>>(c->n, c->partial, a.target, a.kmax, xb, vb, mb,
+                                                   accumulate);
+    LAUNCH_OK(c);
+    return NB_OK;
+}
+
+static nb_status enqueue_shared_predict(nb_ctx *c, double dt, hipStream_t s) {
+    const int32_t grid = grid_for(c->n, 8192);
+    if (c->prec == NB_FP32) shared_predict<0><<<grid, WG, 0, s>>>(state_view(c), c->js, dt);
+    else shared_predict<2><<<grid, WG, 0, s>>>(state_view(c), c->js, dt);
+    LAUNCH_OK(c);
+    return NB_OK;
+}
+
+nb_status nb_shared_step(nb_ctx *c, double dt, int32_t nsteps) {
+    nb_status r;
+    if ((r = need(c)) != NB_OK) return r;
+    if (c->prec == NB_DS) return fail(c, NB_EINVAL, "shared steps: fp32 or fp64 contexts only");
+    int64_t dt_ticks = 0;
+    if ((r = check_shared_dt(c, dt, &dt_ticks)) != NB_OK) return r;
+    if (nsteps < 0) return fail(c, NB_EINVAL, "nsteps < 0");
+    hipStream_t s = c->stream;
+    for (int32_t k = 0; k < nsteps; ++k) {
+        if ((r = enqueue_shared_predict(c, dt, s)) != NB_OK) return r;
+        if ((r = enqueue_force(c, c->var_full, 0, nullptr, nullptr, c->n, c->acc1, c->jerk1,
+                               c->pot1, c->n, s)) != NB_OK)
+            return r;
+        shared_correct<<<grid_for(c->n, 8192), WG, 0, s>>>(state_rw(c), c->acc1, c->jerk1,
+                                                           c->pot1, dt, dt_ticks, c->adj_flag);
+        LAUNCH_OK(c);
+    }
+    c->predicted = true;
+    return NB_OK;
+}
+
+nb_status nb_force_vjp(nb_ctx *c, const double *abar, const double *kbar, double *xbar,
+                       double *vbar, double *mbar) {
+    nb_status r;
+    if ((r = need(c)) != NB_OK) return r;
+    if (c->prec == NB_DS) return fail(c, NB_EINVAL, "force VJP: fp32 or fp64 contexts only");
+    if (!c->predicted) return fail(c, NB_ESTATE, "nb_force_vjp before nb_predict");
+    if (!abar || !kbar || !xbar || !vbar || !mbar) return fail(c, NB_EINVAL, "nb_force_vjp: arrays required");
+    return enqueue_force_vjp(c, abar, kbar, xbar, vbar, mbar, 1, c->stream);
+}
+
+nb_status nb_step_vjp(nb_ctx *c, double dt, double *xbar, double *vbar, double *abar,
+                      double *kbar, double *mbar) {
+    nb_status r;
+    if ((r = need(c)) != NB_OK) return r;
+    if (c->prec == NB_DS) return fail(c, NB_EINVAL, "step VJP: fp32 or fp64 contexts only");
+    int64_t dt_ticks = 0;
+    if ((r = check_shared_dt(c, dt, &dt_ticks)) != NB_OK) return r;
+    if (!xbar || !vbar || !abar || !kbar || !mbar) return fail(c, NB_EINVAL, "nb_step_vjp: arrays required");
+    hipStream_t s = c->stream;
+    const int64_t N3 = 3 * (int64_t)c->n;
+    double *a1b = c->adj, *k1b = a1b + N3, *xpb = k1b + N3, *vpb = xpb + N3;
+    const int32_t g = grid_for(N3, 8192);
+    if ((r = enqueue_shared_predict(c, dt, s)) != NB_OK) return r;
+    vjp_pre<<<g, WG, 0, s>>>(c->n, dt, xbar, vbar, abar, kbar, a1b, k1b);
+    LAUNCH_OK(c);
+    if ((r = enqueue_force_vjp(c, a1b, k1b, xpb, vpb, mbar, 0, s)) != NB_OK) return r;
+    vjp_post<<<g, WG, 0, s>>>(c->n, dt, xbar, vbar, abar, kbar, xpb, vpb);
+    LAUNCH_OK(c);
+    c->predicted = true;
     return NB_OK;
 }
 

@@ -50,7 +50,7 @@ EXPORTS = ["nb_create", "nb_destroy", "nb_set_stream", "nb_bind", "nb_init",
            "nb_tune", "nb_profile", "nb_profile_read", "nb_sync", "nb_last_error", "nb_version",
            "nb_ens_create", "nb_ens_destroy", "nb_ens_set_stream", "nb_ens_bind",
            "nb_ens_set_layout", "nb_ens_init", "nb_ens_run", "nb_ens_control", "nb_ens_energy",
-           "nb_ens_last_error"]
+           "nb_ens_last_error", "nb_shared_step", "nb_force_vjp", "nb_step_vjp"]
 
 _lib = None
 
@@ -89,6 +89,9 @@ def load_library(path: str = LIB_PATH):
         "nb_profile": [P, I32],
         "nb_profile_read": [P, I32, ctypes.POINTER(D), ctypes.POINTER(I64)],
         "nb_sync": [P],
+        "nb_shared_step": [P, D, I32],
+        "nb_force_vjp": [P, P, P, P, P, P],
+        "nb_step_vjp": [P, D, P, P, P, P, P],
         "nb_ens_create": [ctypes.POINTER(P), I32, P, P, I32, I32, I32],
         "nb_ens_destroy": [P],
         "nb_ens_set_stream": [P, P],
@@ -302,6 +305,19 @@ class Context:
         self._check(self.lib.nb_tune(self.h, int(which), int(n_i), int(reps), ctypes.byref(v),
                                      ctypes.byref(ms)))
         return dict(ipl=v.ipl, unroll=v.unroll, target=v.target, kmax=v.kmax), ms.value
+
+    def nb_shared_step(self, dt, nsteps=1):
+        self._check(self.lib.nb_shared_step(self.h, float(dt), int(nsteps)))
+
+    def nb_force_vjp(self, abar, kbar, xbar, vbar, mbar):
+        """Adds the force VJP at the predicted stream to xbar, vbar (3, n) and mbar (n,)."""
+        self._check(self.lib.nb_force_vjp(self.h, _ptr(abar), _ptr(kbar), _ptr(xbar), _ptr(vbar),
+                                          _ptr(mbar)))
+
+    def nb_step_vjp(self, dt, xbar, vbar, abar, kbar, mbar):
+        """In place: output adjoints of one shared step from the bound state -> input adjoints."""
+        self._check(self.lib.nb_step_vjp(self.h, float(dt), _ptr(xbar), _ptr(vbar), _ptr(abar),
+                                         _ptr(kbar), _ptr(mbar)))
 
     def nb_profile(self, enable=True):
         self._check(self.lib.nb_profile(self.h, int(bool(enable))))

@@ -373,3 +373,29 @@ def test_plummer_ic_properties():
     assert abs(r[n // 2] / (a / math.sqrt(2 ** (2 / 3) - 1)) - 1) < 0.05
     cdf = lambda rr: np.minimum(1.0, (rr ** 3 / (rr ** 2 + a * a) ** 1.5) / 0.999)
     assert stats.kstest(r, cdf).pvalue > 1e-3
+
+
+# ------------------------------------------------------------------ derivatives of shared runs
+def test_fd_gradient_free_particle_closed_form():
+    """One free particle moves as x0 + v0 T, so L = |x0 + v0 T - target|^2 has
+    dL/dx0 = 2 (x(T) - target), dL/dv0 = 2 T (x(T) - target)."""
+    x0 = np.array([[0.3, -0.1, 0.2]]); v0 = np.array([[0.5, 0.25, -1.0]]); m = np.array([1.0])
+    T, dt = 0.5, 2.0 ** -4
+    target = np.array([[0.1, 0.1, 0.1]])
+    coords = [("x", 0, c) for c in range(3)] + [("v", 0, c) for c in range(3)]
+    g = oracle.fd_gradient(x0, v0, m, 0.0, dt, int(T / dt), target, coords)
+    r = (x0 + v0 * T - target)[0]
+    np.testing.assert_allclose(g[:3], 2 * r, rtol=1e-8)
+    np.testing.assert_allclose(g[3:], 2 * T * r, rtol=1e-8)
+
+
+def test_fd_gradient_mass_of_a_pulling_particle():
+    """Two particles at rest a distance 2 apart (eps = 0): over a short time T the first moves
+    by m2 T^2 / (2 r^2) toward the second, so d x1 / d m2 = T^2 / 8 + O(T^4); the loss
+    L = mean |x - target|^2 with target = initial positions gives dL/dm2 = (T^2/8)^2 m2."""
+    x0 = np.array([[0.0, 0, 0], [2.0, 0, 0]]); v0 = np.zeros((2, 3)); m = np.array([1.0, 1.0])
+    T, dt = 2.0 ** -4, 2.0 ** -10
+    g = oracle.fd_gradient(x0, v0, m, 0.0, dt, int(T / dt), x0, [("m", 1, 0)])
+    # L(m2) = (1/2) [ (m2 T^2/8)^2 + (m1 T^2/8)^2 ] to leading order
+    expect = (T * T / 8) ** 2 * m[1]
+    assert abs(g[0] - expect) < 2e-3 * expect
