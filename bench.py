@@ -136,6 +136,249 @@ def bench_ensemble(args):
     print(json.dumps(result), flush=True)
 
 
+RUNS = {
+    # Plummer N = 1024, eps = 1/256, nu = 0.01, dt <= 1/64, to t = 1/8
+    "n1024_t0.125": dict(n=1024, seed=1, eps=1 / 256, nu=0.01, lmin=6, t_end=0.125),
+    # Plummer N = 65536, eps = 1e-3, nu = 0.01, dt <= 1/8, to t = 1
+    "n65536_t1": dict(n=65536, seed=2, eps=1e-3, nu=0.01, lmin=3, t_end=1.0),
+}
+
+
+def bench_run(args):
+    """Block-step run workload: a Plummer sphere integrated from t = 0 to t_end by the
+    device-resident loop (nb_init + nb_run, graph replay).  `value` = force interactions per
+    second over the whole run (sum over block steps of N times the block size, plus the N^2 of
+    the initial force), wall clock around nb_init + nb_run.  The block-step force kernel's
+    launch time comes from an eager replay of the same run with timing events on (graph replay
+    records no events); both replays must take the same number of block steps."""
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_astro_ph_0702058_amd import nbody
+    from paper_astro_ph_0702058_amd.plummer import plummer
+    p = RUNS[args.run]
+    n, eps, nu, lmin, t_end = p["n"], p["eps"], p["nu"], p["lmin"], p["t_end"]
+    x0, v0, m = plummer(n, p["seed"])
+
+    def one(prec, graph, profile=False):
+        st = nbody.DeviceState(x0, v0, m)
+        ctx = nbody.Context(n, eps, lmin=lmin, lmax=26, precision=prec)
+        ctx.nb_bind(st)
+        if profile:
+            ctx.nb_profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.nb_init(nu)
+        ctx.nb_run(nu, t_end, chunk=256, use_graph=graph)
+        ctx.nb_sync()
+        wall = time.perf_counter() - t0
+        c = ctx.nb_read_control()
+        ek1, ep1 = ctx.nb_energy()
+        prof = ctx.nb_profile_read(1) if profile else None
+        ctx.close()
+        return dict(wall=wall, n_steps=c.n_steps, n_active_sum=c.n_active_sum,
+                    e1=ek1 + ep1, prof=prof)
+
+    # E0 from the same energy routine, before the run
+    st = nbody.DeviceState(x0, v0, m)
+    with nbody.Context(n, eps, lmin=lmin, lmax=26, precision="fp64") as ctx:
+        ctx.nb_bind(st)
+        ctx.nb_init(nu)
+        ek0, ep0 = ctx.nb_energy()
+    e0 = ek0 + ep0
+    for _ in range(args.warmup):
+        one(args.precision, True)
+    runs = [one(args.precision, True) for _ in range(max(1, args.steps))]
+    wall = min(r["wall"] for r in runs)
+    r = runs[0]
+    inter = n * n + n * r["n_active_sum"]
+    log(f"[bench] {args.run} {args.precision}: {r['n_steps']} block steps, mean block "
+        f"{r['n_active_sum'] / r['n_steps']:.1f}, {wall:.3f} s")
+    eager = one(args.precision, False, profile=True)
+    assert eager["n_steps"] == r["n_steps"], (eager["n_steps"], r["n_steps"])
+    ms, launches = eager["prof"]
+    per_launch = n * r["n_active_sum"] / launches
+    peak = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
+    tflops = FLOP_PER_INTERACTION * per_launch / (ms / launches * 1e-3) / 1e12
+    result = {
+        "metric": "interactions/s over a block-step run (force interactions incl. the initial "
+                  "full force / wall clock)",
+        "value": inter / wall, "unit": "interactions/s", "n_gpus": 1, "steps": len(runs),
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "ds": "f32x2", "fp64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"Plummer N={n} (eps={eps:g}, eta={nu}, dt_max=2^-{lmin}) "
+                               f"block-step run t=0 -> {t_end}", "n": n, "eps": eps, "eta": nu,
+                   "lmin": lmin, "t_end": t_end, "precision": args.precision,
+                   "n_steps": r["n_steps"], "mean_block": r["n_active_sum"] / r["n_steps"],
+                   "de_rel": (r["e1"] - e0) / e0, "wall_s": wall},
+        "roofline": {"bound": "alu", "kernel": "force_kernel (block-step launch class)",
+                     "achieved": round(tflops, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(tflops / peak, 4), "traffic": None, "launches": launches,
+                     "avg_launch_ms": round(ms / launches, 4),
+                     "interactions_per_launch": per_launch,
+                     "flop_per_interaction": FLOP_PER_INTERACTION,
+                     "source": "eager replay of the same run with timing events"},
+    }
+    variants = {}
+    for prec in [q for q in args.variants.split(",") if q and q != "none" and q != args.precision]:
+        vr = one(prec, True)
+        variants[prec] = {"wall_s": vr["wall"], "n_steps": vr["n_steps"],
+                          "mean_block": vr["n_active_sum"] / vr["n_steps"],
+                          "de_rel": (vr["e1"] - e0) / e0}
+        log(f"[bench] {prec}: {vr['n_steps']} steps, {vr['wall']:.3f} s, dE/E {variants[prec]['de_rel']:.3e}")
+    result["variants"] = variants
+    gold = os.path.join(ROOT, "tests", "golden", "plummer_runs.json")
+    if os.path.exists(gold):
+        g = json.load(open(gold)).get(args.run)
+        if g:
+            result["oracle_reference_run"] = {
+                "de_rel": g["de_rel"], "n_steps": g["n_steps"], "mean_block": g["mean_block"],
+                "seconds": g["seconds"], "threads": g["threads"],
+                "note": "committed FP64 oracle run of the same initial conditions"}
+    if not args.no_cpu_baseline:
+        import oracle
+        it = oracle.BlockIntegrator(x0, v0, m, eps=eps, nu=nu, lmin=lmin)
+        t_a = time.perf_counter()
+        while time.perf_counter() - t_a < args.cpu_seconds and it.time < t_end:
+            it.step()
+        el = time.perf_counter() - t_a
+        result["cpu_baseline"] = {
+            "value": (n * n + n * it.n_active_total) / el, "unit": "interactions/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"oracle init + its first {it.n_steps} block steps of the same run "
+                      f"(t = 0 -> {it.time:.4g}), {el:.1f} s"}
+    print(json.dumps(result), flush=True)
+
+
+def bench_accuracy(args):
+    """Energy conservation against the accuracy parameter (Sec. Results, accuracy
+    measurements): Plummer N = 1024 (seed 1) and 16384 (seed 7), eps = 1/256, dt <= 1/8,
+    nu = 0.1 / 2^k for k = 0 .. 8; each run goes from t = 0 to 1/4 and on to 1/2 and reports
+    |E(1/2) - E(1/4)| / |E(1/4)| for the four interaction arithmetics (all-single as in the
+    paper's kernel, FP32 with double separations, double-single, FP64).  `value` = force
+    interactions per second over all the runs; the committed oracle curves are attached."""
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_astro_ph_0702058_amd import nbody
+    from paper_astro_ph_0702058_amd.plummer import plummer
+    sizes = {1024: 1, 16384: 7}
+    nus = [0.1 / 2 ** k for k in range(9)]
+    precs = ["fp32all", "fp32", "ds", "fp64"]
+    curves, inter, wall = {}, 0.0, 0.0
+    for n, seed in sizes.items():
+        x, v, m = plummer(n, seed)
+        for prec in precs:
+            rows = []
+            for nu in nus:
+                st = nbody.DeviceState(x, v, m)
+                with nbody.Context(n, 1 / 256, lmin=3, lmax=26, precision=prec,
+                                   allow_dtmin=True) as ctx:
+                    ctx.nb_bind(st)
+                    torch.cuda.synchronize()
+                    t_a = time.perf_counter()
+                    ctx.nb_init(nu)
+                    ctx.nb_run(nu, 0.25, chunk=256)
+                    ek, ep = ctx.nb_energy()
+                    c0 = ctx.nb_read_control()
+                    ctx.nb_run(nu, 0.5, chunk=256)
+                    ek1, ep1 = ctx.nb_energy()
+                    c1 = ctx.nb_read_control()
+                    el = time.perf_counter() - t_a
+                e0, e1 = ek + ep, ek1 + ep1
+                steps = c1.n_steps - c0.n_steps
+                rows.append({"nu": nu, "de_rel": abs((e1 - e0) / e0), "n_steps": steps,
+                             "dtmin_clamped": ctx.dtmin_clamped,
+                             "mean_block": (c1.n_active_sum - c0.n_active_sum) / max(steps, 1),
+                             "seconds": el})
+                inter += n * n + n * c1.n_active_sum
+                wall += el
+            curves[f"{n}/{prec}"] = rows
+            log(f"[bench] N={n} {prec}: " + " ".join(f"{r['de_rel']:.1e}" for r in rows))
+    result = {
+        "metric": "|dE/E| over t = 1/4 .. 1/2 against nu (energy conservation experiment); value = "
+                  "force interactions/s over all runs",
+        "value": inter / wall, "unit": "interactions/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * wall, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32,f32,f32x2,f64", "data": "synthetic",
+        "config": {"workload": "Plummer N=1024 (seed 1) and N=16384 (seed 7), eps=1/256, "
+                               "dt_max=1/8, nu=0.1/2^k (k=0..8), t=0 -> 1/4 -> 1/2",
+                   "precisions": precs},
+        "curves": curves,
+    }
+    gold = os.path.join(ROOT, "tests", "golden", "accuracy_sweep.json")
+    if os.path.exists(gold):
+        g = json.load(open(gold))
+        result["oracle_curves"] = {k: [{"nu": r["nu"], "de_rel": r["de_rel"],
+                                        "n_steps": r["n_steps"]} for r in g[k]["rows"]]
+                                   for k in g if k != "params"}
+    print(json.dumps(result), flush=True)
+
+
+def bench_adjoint(args):
+    """Differentiable run: Plummer N = 16384, eps = 1/128, 64 shared steps of 1/1024, FP32
+    force; loss = mean squared distance of the final positions to a target (the end of a run
+    from initial conditions perturbed by N(0, 1e-3^2)); gradient with respect to x0, v0, m
+    through the hand-written adjoint with checkpoints every 8 steps.  One bench step = forward
+    + backward."""
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_astro_ph_0702058_amd.adjoint import HermiteRun, SharedRunner
+    from paper_astro_ph_0702058_amd.plummer import perturb, plummer
+    n, eps, dt, nsteps, ce = 16384, 1.0 / 128, 2.0 ** -10, 64, 8
+    prec = args.precision if args.precision != "ds" else "fp32"
+    x0, v0, m = plummer(n, 5)
+    xp_, vp_ = perturb(x0, v0, 1e-3, 6)
+    soa = lambda a: torch.tensor(np.ascontiguousarray(np.asarray(a).T), dtype=torch.float64,
+                                 device="cuda")
+    runner = SharedRunner(n, eps, dt, nsteps, checkpoint_every=ce, precision=prec)
+    with torch.no_grad():  # target: the perturbed run, on the same engine
+        tx, _ = HermiteRun.apply(soa(xp_), soa(vp_), torch.tensor(m, device="cuda"), runner)
+        target = tx.clone()
+
+    def step():
+        X0 = soa(x0).requires_grad_(True); V0 = soa(v0).requires_grad_(True)
+        M = torch.tensor(m, dtype=torch.float64, device="cuda").requires_grad_(True)
+        x, _ = HermiteRun.apply(X0, V0, M, runner)
+        loss = ((x - target) ** 2).sum(0).mean()
+        loss.backward()
+        return loss.detach(), X0.grad, V0.grad, M.grad
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        loss, gx, gv, gm = step()
+    torch.cuda.synchronize()
+    elapsed = (time.perf_counter() - t0) / args.steps
+    nseg = nsteps // ce
+    forces = (nsteps + 1) + nseg * (ce - 1)    # forward + recomputation
+    vjps = nsteps + 1
+    result = {
+        "metric": "gradient of a 64-step trajectory loss: interactions/s (forces + force VJPs)",
+        "value": (forces + vjps) * n * n / elapsed, "unit": "interactions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * elapsed,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64"}[prec], "data": "synthetic",
+        "config": {"workload": "Plummer N=16384, eps=1/128, 64 shared steps dt=1/1024, "
+                               "checkpoints every 8, loss = mean |x - x_target|^2",
+                   "n": n, "force_evaluations": forces, "force_vjps": vjps,
+                   "loss": float(loss), "grad_norms": {"x0": float(gx.norm()),
+                                                       "v0": float(gv.norm()),
+                                                       "m": float(gm.norm())}},
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,10 +395,13 @@ def main():
                     help="other interaction arithmetics to time once (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="full", choices=["full", "ensemble"],
+    ap.add_argument("--workload", default="full", choices=["full", "ensemble", "adjoint", "run", "accuracy"],
                     help="full: N-body force + block steps at N (default); ensemble: 512 "
                          "Plummer clusters, N_c log-uniform in [64, 4096], eps = 1/N_c, "
-                         "eta = 0.02, to t = 1")
+                         "eta = 0.02, to t = 1; adjoint: gradient of a trajectory loss over "
+                         "64 shared steps at N = 16384; run: a block-step run (--run); "
+                         "accuracy: energy error against nu for every arithmetic")
+    ap.add_argument("--run", default="n65536_t1", choices=sorted(RUNS))
     ap.add_argument("--clusters", type=int, default=512)
     ap.add_argument("--t-end", type=float, default=1.0)
     ap.add_argument("--tune", action="store_true",
@@ -165,6 +411,12 @@ def main():
 
     if args.workload == "ensemble":
         return bench_ensemble(args)
+    if args.workload == "adjoint":
+        return bench_adjoint(args)
+    if args.workload == "run":
+        return bench_run(args)
+    if args.workload == "accuracy":
+        return bench_accuracy(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -296,10 +548,12 @@ def main():
     # CPU oracle on a bounded sample of i (all j): timing and the accuracy reference
     if not args.no_cpu_baseline:
         import oracle
-        cal = sample_indices(n, 8, 101)
+        # calibrate on enough i to occupy every oracle thread (the oracle splits over i)
+        ncal = 8 * oracle.num_threads()
+        cal = sample_indices(n, ncal, 101)
         t_a = time.perf_counter(); oracle.force(x, v, m, args.eps ** 2, idx=cal); t_b = time.perf_counter()
-        per_i = (t_b - t_a) / 8
-        count = int(max(16, min(16384, args.cpu_seconds / max(per_i, 1e-9))))
+        per_i = (t_b - t_a) / ncal
+        count = int(max(16, min(65536, args.cpu_seconds / max(per_i, 1e-9))))
         idx = sample_indices(n, count, 7)
         log(f"[bench] oracle on {count} sampled i x {n} j")
         t_a = time.perf_counter()

@@ -51,8 +51,12 @@ typedef enum {
  *  NB_FP32: single-precision VALU arithmetic; separations formed from double positions and
  *           then rounded once; sums over j-tiles accumulated in float and folded into double.
  *  NB_DS:   double-single (float-float) arithmetic throughout the interaction and its sums.
- *  NB_FP64: IEEE double arithmetic throughout. */
-typedef enum { NB_FP32 = 0, NB_DS = 1, NB_FP64 = 2 } nb_precision;
+ *  NB_FP64: IEEE double arithmetic throughout.
+ *  NB_FP32_ALL: the arithmetic of the paper's GPU kernel (Sec. Mapping, Appendix A):
+ *           predicted positions, velocities and masses rounded to float, separations formed
+ *           in float, sums over all j in float.  Single contexts only (not ensembles, not the
+ *           shared-step and adjoint calls); a reference point for accuracy studies. */
+typedef enum { NB_FP32 = 0, NB_DS = 1, NB_FP64 = 2, NB_FP32_ALL = 3 } nb_precision;
 
 /* FP64 master state of n particles, caller-owned device memory (structure of arrays). */
 typedef struct {

@@ -195,6 +195,94 @@ struct ModeF32 {
 };
 
 // ------------------------------------------------------------------------------------------
+// All-single interaction, the arithmetic of the paper's GPU kernel (Sec. Mapping and the
+// force routine of Appendix A): predicted positions, velocities and masses are rounded to
+// float, separations are differences of float positions, and the sums over all j stay in
+// float.  Prediction and correction remain FP64.  Kept as the paper-style accuracy reference;
+// separations cancel digits here that the FP32 mode keeps.
+// ------------------------------------------------------------------------------------------
+struct ModeF32All {
+    struct Args {
+        const float4 *pm;  // x, y, z, m
+        const float4 *vv;  // vx, vy, vz, 0
+        float eps2;
+    };
+    struct I {
+        float x, y, z, vx, vy, vz, m;
+    };
+    struct Smem {
+        float4 pm[TJ], vv[TJ];
+    };
+    struct Tile {
+        float ax, ay, az, jx, jy, jz, p;
+    };
+    using Sum = Tile;
+
+    __device__ static I load_i(const Args &a, int g) {
+        const float4 q = a.pm[g], w = a.vv[g];
+        return I{q.x, q.y, q.z, w.x, w.y, w.z, q.w};
+    }
+    __device__ static void stage(const Args &a, Smem &s, int t, int j, int n) {
+        if (j < n) {
+            s.pm[t] = a.pm[j]; s.vv[t] = a.vv[j];
+        } else {  // padding: zero mass contributes nothing
+            s.pm[t] = make_float4(0.f, 0.f, 0.f, 0.f); s.vv[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+    }
+    __device__ static Tile tile_zero() { return Tile{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}; }
+    __device__ static Sum sum_zero() { return tile_zero(); }
+    __device__ static I make_i(const double xp[3], const double vp[3], double m) {
+        return I{(float)xp[0], (float)xp[1], (float)xp[2], (float)vp[0], (float)vp[1],
+                 (float)vp[2], (float)m};
+    }
+    __device__ static void put(Smem &s, int t, const double xp[3], const double vp[3], double m) {
+        s.pm[t] = make_float4((float)xp[0], (float)xp[1], (float)xp[2], (float)m);
+        s.vv[t] = make_float4((float)vp[0], (float)vp[1], (float)vp[2], 0.f);
+    }
+
+    template <bool SOFT>
+    __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, float eps2,
+                                                    Tile &T) {
+        const float4 q = s.pm[jj], w = s.vv[jj];
+        const float dx = q.x - i.x, dy = q.y - i.y, dz = q.z - i.z;
+        const float ux = w.x - i.vx, uy = w.y - i.vy, uz = w.z - i.vz;
+        const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
+        const float rv = __builtin_fmaf(dz, uz, __builtin_fmaf(dy, uy, dx * ux));
+        float rinv = __builtin_amdgcn_rsqf(r2);
+        if (!SOFT) rinv = r2 > 0.0f ? rinv : 0.0f;
+        const float rinv2 = rinv * rinv;
+        const float mr = q.w * rinv;
+        const float mr3 = mr * rinv2;
+        const float t = -3.0f * (rv * rinv2);
+        T.p += mr;
+        T.ax = __builtin_fmaf(mr3, dx, T.ax);
+        T.ay = __builtin_fmaf(mr3, dy, T.ay);
+        T.az = __builtin_fmaf(mr3, dz, T.az);
+        T.jx = __builtin_fmaf(mr3, __builtin_fmaf(t, dx, ux), T.jx);
+        T.jy = __builtin_fmaf(mr3, __builtin_fmaf(t, dy, uy), T.jy);
+        T.jz = __builtin_fmaf(mr3, __builtin_fmaf(t, dz, uz), T.jz);
+    }
+    __device__ static void fold(Sum &S, const Tile &T) {
+        S.ax += T.ax; S.ay += T.ay; S.az += T.az;
+        S.jx += T.jx; S.jy += T.jy; S.jz += T.jz;
+        S.p += T.p;
+    }
+    __device__ static void remove_self(Sum &S, const I &i, float eps2) {
+        S.p -= i.m * __builtin_amdgcn_rsqf(eps2);
+    }
+    __device__ static Out7 out(const Sum &S) {
+        return Out7{{(double)S.ax, (double)S.ay, (double)S.az, (double)S.jx, (double)S.jy,
+                     (double)S.jz, (double)S.p}};
+    }
+    __device__ static void shfl_add(Sum &S, int off) {
+        S.ax += __shfl_xor(S.ax, off, 64); S.ay += __shfl_xor(S.ay, off, 64);
+        S.az += __shfl_xor(S.az, off, 64); S.jx += __shfl_xor(S.jx, off, 64);
+        S.jy += __shfl_xor(S.jy, off, 64); S.jz += __shfl_xor(S.jz, off, 64);
+        S.p += __shfl_xor(S.p, off, 64);
+    }
+};
+
+// ------------------------------------------------------------------------------------------
 // Double-single interaction: every operation in float-float arithmetic; tile sums folded into
 // outer sums with the accurate addition.
 // ------------------------------------------------------------------------------------------
@@ -405,6 +493,7 @@ template <class M> struct EpsOf;
 template <> struct EpsOf<ModeF32> { using T = float; };
 template <> struct EpsOf<ModeDS> { using T = ds; };
 template <> struct EpsOf<ModeF64> { using T = double; };
+template <> struct EpsOf<ModeF32All> { using T = float; };
 
 // Final sums of row q of a work item's j-range ks: straight to the outputs when K == 1,
 // else to partial plane ks.  The potential sum is negated here.
@@ -527,7 +616,14 @@ __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCom
 }
 
 // Fixed-order sum over the K partial planes (deterministic; no atomics).
-__global__ void __launch_bounds__(WG) force_reduce(ForceCommon fc, int32_t ib) {
+// One workgroup per (64 consecutive i-rows, one of the 7 sums): wave w adds the planes
+// k = w, w + RW, w + 2 RW, ... and the RW wave sums are then added in wave order, so the result
+// depends only on K, never on timing.  Consecutive lanes read consecutive rows of a plane.
+constexpr int RW = 16;               // waves per reduce workgroup
+constexpr int WG_REDUCE = 64 * RW;
+
+__global__ void __launch_bounds__(WG_REDUCE) force_reduce(ForceCommon fc, int32_t ib) {
+    __shared__ double part[RW][64];
     int32_t n_i = fc.n_i_max;
     if (fc.n_i_dev) {
         const int32_t d = *fc.n_i_dev;
@@ -536,18 +632,28 @@ __global__ void __launch_bounds__(WG) force_reduce(ForceCommon fc, int32_t ib) {
     if (n_i <= 0) return;
     const ForcePlan pl = make_plan(n_i, fc.n, ib, fc.target, fc.kmax);
     if (pl.K == 1) return;
-    for (int32_t q = blockIdx.x * WG + threadIdx.x; q < n_i; q += gridDim.x * WG) {
-        Out7 o;
-#pragma unroll
-        for (int c = 0; c < 7; ++c) {
-            double s = 0.0;
-            for (int32_t k = 0; k < pl.K; ++k) s += fc.partial[((int64_t)k * 7 + c) * pl.P + q];
-            o.v[c] = s;
+    const int32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t units = ((n_i + 63) >> 6) * 7;
+    for (int32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const int32_t rb = u / 7, c = u - rb * 7;
+        const int32_t q = rb * 64 + lane;
+        double s = 0.0;
+        if (q < n_i) {
+            const double *src = fc.partial + (int64_t)c * pl.P + q;
+            for (int32_t k = w; k < pl.K; k += RW) s += src[(int64_t)k * 7 * pl.P];
         }
-        if (fc.ctl && !finite7(o)) fc.ctl->flag_nonfinite = 1;
-        for (int c = 0; c < 3; ++c) fc.acc[c * (int64_t)fc.ld + q] = o.v[c];
-        for (int c = 0; c < 3; ++c) fc.jerk[c * (int64_t)fc.ld + q] = o.v[3 + c];
-        fc.pot[q] = o.v[6];
+        part[w][lane] = s;
+        __syncthreads();
+        if (w == 0 && q < n_i) {
+            double t = part[0][lane];
+#pragma unroll
+            for (int r = 1; r < RW; ++r) t += part[r][lane];
+            if (fc.ctl && !__builtin_isfinite(t)) fc.ctl->flag_nonfinite = 1;
+            double *dst = c < 3 ? fc.acc + c * (int64_t)fc.ld
+                        : c < 6 ? fc.jerk + (c - 3) * (int64_t)fc.ld : fc.pot;
+            dst[q] = t;
+        }
+        __syncthreads();
     }
 }
 
@@ -595,6 +701,9 @@ __global__ void __launch_bounds__(WG) predict_kernel(StateView s, JStreamView js
         if (MODE == 0) {
             js.px[i] = xp[0]; js.py[i] = xp[1]; js.pz[i] = xp[2];
             js.vm[i] = make_float4((float)vp[0], (float)vp[1], (float)vp[2], (float)m);
+        } else if (MODE == 3) {
+            js.q0[i] = make_float4((float)xp[0], (float)xp[1], (float)xp[2], (float)m);
+            js.q1[i] = make_float4((float)vp[0], (float)vp[1], (float)vp[2], 0.f);
         } else if (MODE == 1) {
             const ds X = ds_from_double(xp[0]), Y = ds_from_double(xp[1]), Z = ds_from_double(xp[2]);
             const ds VX = ds_from_double(vp[0]), VY = ds_from_double(vp[1]), VZ = ds_from_double(vp[2]);

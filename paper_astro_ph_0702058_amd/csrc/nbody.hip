@@ -29,6 +29,7 @@ using Variant = nb_variant;
 bool variant_compiled(int prec, const Variant &v) {
     const bool unr_ok = v.unroll == 1 || v.unroll == 2 || v.unroll == 4;
     if (prec == NB_FP32) return unr_ok && (v.ipl == 1 || v.ipl == 2);
+    // NB_FP32_ALL, NB_DS, NB_FP64
     return v.ipl == 1 && (v.unroll == 1 || v.unroll == 2);
 }
 
@@ -193,6 +194,7 @@ nb_status enqueue_predict(nb_ctx *c, const int64_t *t, int guard, hipStream_t s)
     switch (c->prec) {
         case NB_FP32: predict_kernel<0><<<grid, WG, 0, s>>>(sv, c->js, t, c->ctl, guard); break;
         case NB_DS: predict_kernel<1><<<grid, WG, 0, s>>>(sv, c->js, t, c->ctl, guard); break;
+        case NB_FP32_ALL: predict_kernel<3><<<grid, WG, 0, s>>>(sv, c->js, t, c->ctl, guard); break;
         default: predict_kernel<2><<<grid, WG, 0, s>>>(sv, c->js, t, c->ctl, guard); break;
     }
     LAUNCH_OK(c);
@@ -272,6 +274,11 @@ nb_status enqueue_force(nb_ctx *c, const Variant &v, int cls, const int32_t *ili
             launch_f32(pa, fc, v, soft, cls, grid, s);
             break;
         }
+        case NB_FP32_ALL: {
+            ModeF32All::Args pa{c->js.q0, c->js.q1, (float)(c->eps * c->eps)};
+            launch_ipl1<ModeF32All>(pa, fc, v, soft, cls, grid, s);
+            break;
+        }
         case NB_DS: {
             const double e2 = c->eps * c->eps;
             const float h = (float)e2;
@@ -292,8 +299,8 @@ nb_status enqueue_force(nb_ctx *c, const Variant &v, int cls, const int32_t *ili
         c->ev.push_back(nb_ctx::Timed{e0, e1, cls});
     }
     // second pass: a no-op when the plan has K == 1
-    const int32_t rgrid = grid_for(n_i_max, 4096);
-    force_reduce<<<rgrid, WG, 0, s>>>(fc, ib);
+    const int32_t units = ((n_i_max + 63) / 64) * 7;
+    force_reduce<<<std::max(1, std::min(units, c->num_cu * 8)), WG_REDUCE, 0, s>>>(fc, ib);
     LAUNCH_OK(c);
     return NB_OK;
 }
@@ -368,7 +375,7 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
     if (!out) return NB_EINVAL;
     *out = nullptr;
     if (n < 1 || n > (1 << 28) || !(eps >= 0.0) || !std::isfinite(eps) || lmin < 0 ||
-        lmax < lmin || lmax > 52 || precision < NB_FP32 || precision > NB_FP64)
+        lmax < lmin || lmax > 52 || precision < NB_FP32 || precision > NB_FP32_ALL)
         return NB_EINVAL;
     nb_ctx *c = new nb_ctx();
     c->n = n; c->eps = eps; c->lmin = lmin; c->lmax = lmax; c->prec = precision;
@@ -391,6 +398,8 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
         } else if (precision == NB_DS) {
             c->js.q0 = (float4 *)b; c->js.q1 = c->js.q0 + N; c->js.q2 = c->js.q1 + N;
             c->js.q3 = c->js.q2 + N;
+        } else if (precision == NB_FP32_ALL) {
+            c->js.q0 = (float4 *)b; c->js.q1 = c->js.q0 + N;
         } else {
             c->js.px = (double *)b; c->js.py = c->js.px + N; c->js.pz = c->js.py + N;
             c->js.pm = c->js.pz + N; c->js.vx = c->js.pm + N; c->js.vy = c->js.vx + N;
@@ -679,7 +688,8 @@ static nb_status enqueue_shared_predict(nb_ctx *c, double dt, hipStream_t s) {
 nb_status nb_shared_step(nb_ctx *c, double dt, int32_t nsteps) {
     nb_status r;
     if ((r = need(c)) != NB_OK) return r;
-    if (c->prec == NB_DS) return fail(c, NB_EINVAL, "shared steps: fp32 or fp64 contexts only");
+    if (c->prec != NB_FP32 && c->prec != NB_FP64)
+        return fail(c, NB_EINVAL, "shared steps: fp32 or fp64 contexts only");
     int64_t dt_ticks = 0;
     if ((r = check_shared_dt(c, dt, &dt_ticks)) != NB_OK) return r;
     if (nsteps < 0) return fail(c, NB_EINVAL, "nsteps < 0");
@@ -701,7 +711,8 @@ nb_status nb_force_vjp(nb_ctx *c, const double *abar, const double *kbar, double
                        double *vbar, double *mbar) {
     nb_status r;
     if ((r = need(c)) != NB_OK) return r;
-    if (c->prec == NB_DS) return fail(c, NB_EINVAL, "force VJP: fp32 or fp64 contexts only");
+    if (c->prec != NB_FP32 && c->prec != NB_FP64)
+        return fail(c, NB_EINVAL, "force VJP: fp32 or fp64 contexts only");
     if (!c->predicted) return fail(c, NB_ESTATE, "nb_force_vjp before nb_predict");
     if (!abar || !kbar || !xbar || !vbar || !mbar) return fail(c, NB_EINVAL, "nb_force_vjp: arrays required");
     return enqueue_force_vjp(c, abar, kbar, xbar, vbar, mbar, 1, c->stream);
@@ -711,7 +722,8 @@ nb_status nb_step_vjp(nb_ctx *c, double dt, double *xbar, double *vbar, double *
                       double *kbar, double *mbar) {
     nb_status r;
     if ((r = need(c)) != NB_OK) return r;
-    if (c->prec == NB_DS) return fail(c, NB_EINVAL, "step VJP: fp32 or fp64 contexts only");
+    if (c->prec != NB_FP32 && c->prec != NB_FP64)
+        return fail(c, NB_EINVAL, "step VJP: fp32 or fp64 contexts only");
     int64_t dt_ticks = 0;
     if ((r = check_shared_dt(c, dt, &dt_ticks)) != NB_OK) return r;
     if (!xbar || !vbar || !abar || !kbar || !mbar) return fail(c, NB_EINVAL, "nb_step_vjp: arrays required");

@@ -16,7 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "lib", "libnbody.so")
 
 NB_OK, NB_EINVAL, NB_EDEVICE, NB_ENOMEM, NB_ESTATE, NB_ENONFINITE, NB_EDTMIN = 0, -1, -2, -3, -4, -5, -6
-PRECISIONS = {"fp32": 0, "ds": 1, "fp64": 2}
+PRECISIONS = {"fp32": 0, "ds": 1, "fp64": 2, "fp32all": 3}
 _STATUS_NAMES = {0: "NB_OK", -1: "NB_EINVAL", -2: "NB_EDEVICE", -3: "NB_ENOMEM", -4: "NB_ESTATE",
                  -5: "NB_ENONFINITE", -6: "NB_EDTMIN"}
 
@@ -188,7 +188,11 @@ class Control:
 class Context:
     """One libnbody context: n particles, softening eps, steps in [2^-lmax, 2^-lmin]."""
 
-    def __init__(self, n, eps, lmin=3, lmax=26, precision="fp32", stream=None):
+    def __init__(self, n, eps, lmin=3, lmax=26, precision="fp32", stream=None, allow_dtmin=False):
+        """allow_dtmin: do not raise NB_EDTMIN (a step request below 2^-lmax, clamped; the call
+        itself completed); `dtmin_clamped` records that it was seen."""
+        self.allow_dtmin = bool(allow_dtmin)
+        self.dtmin_clamped = False
         self.lib = load_library()
         self.n = int(n)
         self.eps = float(eps)
@@ -205,6 +209,9 @@ class Context:
 
     # -- plumbing
     def _check(self, status, ctx="self"):
+        if status == NB_EDTMIN and self.allow_dtmin:
+            self.dtmin_clamped = True
+            return
         if status != NB_OK:
             msg = ""
             if ctx is not None and getattr(self, "h", None):

@@ -1,0 +1,162 @@
+"""Block-step runs of the N = 65536 workload: Plummer sphere (seed 2), eps = 1e-3, nu = 0.01,
+dt <= 1/8, integrated to t = 1 by the device-resident loop.
+
+1. Force parity inside a run.  At sampled block steps of a device run, the block's forces from
+   nb_force are compared with the FP64 oracle evaluated at the same predicted state: the oracle
+   predicts every particle from the device's FP64 master state (x, v, a, k, tick) to the block
+   time, then sums over all j.  Blocks are not a uniform sample: the first ones hold the
+   particles with the smallest steps, e.g. one near the centre whose pulls cancel to a tiny
+   |a| (dt = nu |a|/|k|), where rounding of size u * sum_j |a_ij| is large against |a|.  So
+   every sampled block must meet the force tolerances on the error measured against the sum of
+   the magnitudes of the terms, e = sqrt(mean_i |a_i - a_i^ref|^2 / (sum_j |a_ij|)^2) (jerk
+   alike; the potential terms share one sign, so its relative error is that already), and the
+   blocks at t = 1/64 and 1/16, which hold every particle of level <= 6 or <= 4, must also meet
+   them on the plain rms relative error.
+2. The first 300 block steps in FP64 follow the oracle step for step (same block times, same
+   levels and ticks, positions to 1e-10): the trajectories have not yet parted.
+3. The whole run to t = 1 against the committed FP64 oracle run of the same initial conditions
+   (tests/golden/plummer_runs.json, written by make_plummer_reference.py from the oracle only).
+   Over t = 1 the trajectories of a 65536-body system part, and the block-step count is set
+   by the few tightest pairs (a single close pair at level l adds 2^l / 8 block times), so
+   what is compared is what the bulk fixes: the total number of particle steps within 5 %, the
+   block-step count within 25 %, and the energy error within a factor 10 of the oracle's (at
+   eps = 1e-3 it is the integrator's, from close encounters, not the arithmetic's).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_astro_ph_0702058_amd import nbody
+from paper_astro_ph_0702058_amd.plummer import plummer, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+N, SEED, EPS, NU, LMIN, LMAX, T_END = 65536, 2, 1e-3, 0.01, 3, 26, 1.0
+TOL = {"fp32": (2e-6, 1e-5, 2e-6), "ds": (1e-11, 1e-10, 1e-11), "fp64": (1e-13, 1e-13, 1e-13)}
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plummer_runs.json")
+
+
+def term_magnitude_sums(xp, vp, m, rows):
+    """sum_j |a_ij| and sum_j |k_ij| over j != i for the listed i (FP64, chunks of rows)."""
+    sa = np.empty(len(rows)); sk = np.empty(len(rows))
+    for c0 in range(0, len(rows), 32):
+        r = rows[c0:c0 + 32]
+        d = xp[None, :, :] - xp[r][:, None, :]
+        u = vp[None, :, :] - vp[r][:, None, :]
+        s = np.sum(d * d, axis=2) + EPS * EPS
+        s[np.arange(len(r)), r] = np.inf          # drop j = i
+        w3 = m[None, :] * s ** -1.5
+        rv = np.sum(d * u, axis=2)
+        sa[c0:c0 + 32] = np.sum(w3 * np.linalg.norm(d, axis=2), axis=1)
+        kv = w3[:, :, None] * (u - 3.0 * (rv / s)[:, :, None] * d)
+        sk[c0:c0 + 32] = np.sum(np.linalg.norm(kv, axis=2), axis=1)
+    return sa, sk
+
+
+def rms_rel(got, ref):
+    if got.ndim == 1:
+        return float(np.sqrt(np.mean(((got - ref) / ref) ** 2)))
+    return float(np.sqrt(np.mean(np.sum((got - ref) ** 2, 1) / np.sum(ref ** 2, 1))))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "ds", "fp64"])
+def test_block_forces_inside_run(prec):
+    import torch
+    x, v, m = plummer(N, SEED)
+    st = nbody.DeviceState(x, v, m)
+    acc = torch.zeros((3, N), dtype=torch.float64, device="cuda")
+    jerk = torch.zeros_like(acc)
+    pot = torch.zeros(N, dtype=torch.float64, device="cuda")
+    done = 0
+    with nbody.Context(N, EPS, lmin=LMIN, lmax=LMAX, precision=prec) as ctx:
+        ctx.nb_bind(st)
+        ctx.nb_init(NU)
+        for kind, where in (("steps", 1), ("steps", 200), ("time", 1 / 64), ("time", 1 / 16)):
+            if kind == "steps":
+                ctx.nb_step(NU, where - done, use_graph=True)
+                done = where
+            else:   # run up to one tick before the time, then select the block there
+                ctx.nb_run(NU, where - 2.0 ** -LMAX, chunk=256)
+            ctx.nb_schedule_block(NU)
+            c = ctx.nb_read_control()
+            if kind == "time":
+                assert c.t_next == int(where * 2 ** LMAX)
+            g = st.numpy()
+            idx_addr, cnt_addr = ctx.nb_active()
+            blk = nbody.read_device_int32(idx_addr, c.n_act).astype(np.int64)
+            ctx.nb_predict()
+            ctx.nb_force(acc, jerk, pot, i_idx=idx_addr, n_i=cnt_addr, n_i_max=N)
+            ctx.nb_correct(acc, jerk, pot)
+            ctx.nb_sync()
+            rows = np.sort(sample_indices(c.n_act, min(512, c.n_act), 40 + c.n_act))
+            ga = acc[:, :c.n_act].cpu().numpy().T[rows]
+            gk = jerk[:, :c.n_act].cpu().numpy().T[rows]
+            gp = pot[:c.n_act].cpu().numpy()[rows]
+            xp, vp = oracle.predict(g["x"], g["v"], g["a"], g["k"], g["tick"], c.t_next, LMAX)
+            ra, rk, rp = oracle.force(xp, vp, m, EPS * EPS, idx=blk[rows])
+            sa, sk = term_magnitude_sums(xp, vp, m, blk[rows])
+            ea_s = float(np.sqrt(np.mean(np.sum((ga - ra) ** 2, 1) / sa ** 2)))
+            ek_s = float(np.sqrt(np.mean(np.sum((gk - rk) ** 2, 1) / sk ** 2)))
+            ea, ek, ep = rms_rel(ga, ra), rms_rel(gk, rk), rms_rel(gp, rp)
+            cond = float(np.median(sa / np.linalg.norm(ra, axis=1)))
+            print(f"{prec} {kind} {where:g}: n_act={c.n_act} t={c.t_next / 2.0 ** LMAX:.6f} "
+                  f"scaled e_acc={ea_s:.3e} e_jerk={ek_s:.3e}; e_acc={ea:.3e} e_jerk={ek:.3e} "
+                  f"e_pot={ep:.3e}; median sum|a_ij|/|a| {cond:.1f}", flush=True)
+            ta, tk, tp = TOL[prec]
+            assert ea_s <= ta and ek_s <= tk and ep <= tp, (kind, where, ea_s, ek_s, ep)
+            if kind == "time":
+                assert ea <= ta and ek <= tk, (where, ea, ek)
+
+
+def golden_run():
+    if not os.path.exists(GOLDEN):
+        return None
+    return json.load(open(GOLDEN)).get("n65536_t1")
+
+
+def test_fp64_block_steps_follow_oracle():
+    x, v, m = plummer(N, SEED)
+    st = nbody.DeviceState(x, v, m)
+    ref = oracle.BlockIntegrator(x, v, m, eps=EPS, nu=NU, lmin=LMIN)
+    with nbody.Context(N, EPS, lmin=LMIN, lmax=LMAX, precision="fp64") as ctx:
+        ctx.nb_bind(st)
+        ctx.nb_init(NU)
+        for s in range(300):
+            ctx.nb_step(NU, 1, use_graph=True)
+            t, blk = ref.step()
+            c = ctx.nb_read_control()
+            assert c.t_cur == t and c.n_steps == s + 1, (s, c.t_cur, t)
+        g = st.numpy()
+    assert np.array_equal(g["tick"], ref.tick) and np.array_equal(g["level"], ref.level)
+    print(f"300 steps to t={ref.time:.6f}, {ref.n_active_total} particle steps", flush=True)
+    assert np.max(np.abs(g["x"] - ref.x)) < 1e-10
+    assert np.max(np.abs(g["v"] - ref.v)) < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp64", "ds", "fp32"])
+def test_run_to_t1_against_oracle_run(prec):
+    ref = golden_run()
+    if ref is None:
+        pytest.skip("the oracle reference run n65536_t1 has not been written")
+    x, v, m = plummer(N, SEED)
+    st = nbody.DeviceState(x, v, m)
+    with nbody.Context(N, EPS, lmin=LMIN, lmax=LMAX, precision=prec) as ctx:
+        ctx.nb_bind(st)
+        ctx.nb_init(NU)
+        ek0, ep0 = ctx.nb_energy()
+        ctx.nb_run(NU, T_END, chunk=256, use_graph=True)
+        c = ctx.nb_read_control()
+        ek1, ep1 = ctx.nb_energy()
+        g = st.numpy()
+    e0 = ek0 + ep0
+    assert abs(e0 - ref["energy0"]) <= 1e-12 * abs(e0)
+    de = (ek1 + ep1 - e0) / e0
+    print(f"{prec}: steps {c.n_steps} vs {ref['n_steps']}; particle steps {c.n_active_sum} vs "
+          f"{ref['n_active_sum']}; dE/E {de:.3e} vs {ref['de_rel']:.3e}", flush=True)
+    assert c.t_cur == int(T_END * 2 ** LMAX) and np.all(g["tick"] == c.t_cur)
+    assert abs(c.n_active_sum - ref["n_active_sum"]) <= 0.05 * ref["n_active_sum"]
+    assert abs(c.n_steps - ref["n_steps"]) <= 0.25 * ref["n_steps"]
+    assert abs(de) <= 10 * abs(ref["de_rel"])
