@@ -51,21 +51,21 @@ struct ForcePlan {
 };
 
 // Lanes per i-particle for a list of n_i with one i per work-item: the whole workgroup is
-// spread over the list, up to 64 lanes (one wave) per i.
-__host__ __device__ inline int32_t lane_split(int32_t n_i, bool allowed) {
+// spread over the list, up to smax lanes (at most one wave) per i.
+__host__ __device__ inline int32_t lane_split(int32_t n_i, bool allowed, int32_t smax = 64) {
     if (!allowed || n_i >= WG) return 1;
     int32_t p2 = 1;
     while (p2 < n_i) p2 <<= 1;
     const int32_t S = WG / p2;
-    return S > 64 ? 64 : S;
+    return S > smax ? smax : S;
 }
 
 // ib_max: WG * (i-particles per work-item); the lane split applies when that is WG.
 __host__ __device__ inline ForcePlan make_plan(int32_t n_i, int32_t n, int32_t ib_max,
-                                               int32_t target, int32_t kmax) {
+                                               int32_t target, int32_t kmax, int32_t smax = 64) {
     ForcePlan p;
     p.n_i = n_i;
-    p.S = lane_split(n_i, ib_max == WG);
+    p.S = lane_split(n_i, ib_max == WG, smax);
     const int32_t ib = ib_max / p.S;
     p.ib = ib;
     p.n_iblk = (n_i + ib - 1) / ib;
@@ -92,6 +92,7 @@ struct ForceCommon {
     int32_t ld;              // leading dimension of acc/jerk/pot
     double *partial;         // K > 1: [K][7][P]
     DevControl *ctl;         // latched flags (may be NULL)
+    int32_t smax;            // largest lane split of the arithmetic mode
 };
 
 // Sum record written per i-particle: acc (3), jerk (3), accumulated m/r (1).
@@ -279,6 +280,75 @@ struct ModeF32All {
         S.az += __shfl_xor(S.az, off, 64); S.jx += __shfl_xor(S.jx, off, 64);
         S.jy += __shfl_xor(S.jy, off, 64); S.jz += __shfl_xor(S.jz, off, 64);
         S.p += __shfl_xor(S.p, off, 64);
+    }
+};
+
+// ------------------------------------------------------------------------------------------
+// Order-independent single precision, in the spirit of the 64-bit fixed-point accumulation of
+// the GRAPE-6 pipelines the paper compares against (Sec. Results, accuracy measurements).  The
+// interaction is the FP32 mode's; float sums run over aligned sub-blocks of FOLD = 64 j, and
+// each sub-block sum is added into int64 accumulators in fixed point (scale 2^F per quantity).
+// Integer addition is exact and associative, and a sub-block's float sum depends only on which
+// j it holds, so the result is bitwise the same for any j-split, i-per-lane, unroll, work-item
+// count or lane split.  Fixed-point steps: acc 2^-40 (range +-2^23), jerk 2^-32 (+-2^31),
+// pot 2^-40.  A sub-block sum outside the range or an overflowing accumulator poisons the
+// record, which comes out as NaN (reported as a non-finite force).
+// ------------------------------------------------------------------------------------------
+struct ModeF32Fixed : ModeF32 {
+    static constexpr int F_ACC = 40, F_JERK = 32, F_POT = 40;
+    struct Sum {
+        int64_t ax, ay, az, jx, jy, jz, p;
+        int32_t bad;
+    };
+    __device__ static Sum sum_zero() { return Sum{0, 0, 0, 0, 0, 0, 0, 0}; }
+    __device__ static __forceinline__ int64_t fix(float x, int F, int32_t &bad) {
+        const double d = __builtin_ldexp((double)x, F);  // exact
+        const bool ok = __builtin_fabs(d) < 0x1p62;      // false for NaN too
+        bad |= !ok;
+        return ok ? (int64_t)__builtin_rint(d) : 0;
+    }
+    __device__ static __forceinline__ void add(int64_t &s, int64_t v, int32_t &bad) {
+        const int64_t r = (int64_t)((uint64_t)s + (uint64_t)v);
+        bad |= (int32_t)((uint64_t)((s ^ r) & (v ^ r)) >> 63);
+        s = r;
+    }
+    __device__ static void fold(Sum &S, const Tile &T) {
+        add(S.ax, fix(T.ax, F_ACC, S.bad), S.bad);
+        add(S.ay, fix(T.ay, F_ACC, S.bad), S.bad);
+        add(S.az, fix(T.az, F_ACC, S.bad), S.bad);
+        add(S.jx, fix(T.jx, F_JERK, S.bad), S.bad);
+        add(S.jy, fix(T.jy, F_JERK, S.bad), S.bad);
+        add(S.jz, fix(T.jz, F_JERK, S.bad), S.bad);
+        add(S.p, fix(T.p, F_POT, S.bad), S.bad);
+    }
+    // the self pair added m_i rsq(eps2) to the potential inside its sub-block; remove the
+    // same float value in fixed point
+    __device__ static void remove_self(Sum &S, const I &i, float eps2) {
+        add(S.p, -fix(i.m * __builtin_amdgcn_rsqf(eps2), F_POT, S.bad), S.bad);
+    }
+    __device__ static Out7 out(const Sum &S) {
+        if (S.bad) {
+            const double nan = __builtin_nan("");
+            return Out7{{nan, nan, nan, nan, nan, nan, nan}};
+        }
+        return Out7{{__builtin_ldexp((double)S.ax, -F_ACC), __builtin_ldexp((double)S.ay, -F_ACC),
+                     __builtin_ldexp((double)S.az, -F_ACC), __builtin_ldexp((double)S.jx, -F_JERK),
+                     __builtin_ldexp((double)S.jy, -F_JERK), __builtin_ldexp((double)S.jz, -F_JERK),
+                     __builtin_ldexp((double)S.p, -F_POT)}};
+    }
+    // K > 1: the raw integers go to the partial planes (INT64_MIN marks a poisoned record)
+    __device__ static void store_raw(double *base, int64_t P, const Sum &S) {
+        const int64_t v[7] = {S.ax, S.ay, S.az, S.jx, S.jy, S.jz, S.p};
+#pragma unroll
+        for (int c = 0; c < 7; ++c)
+            base[(int64_t)c * P] = __longlong_as_double(S.bad ? INT64_MIN : (long long)v[c]);
+    }
+    __device__ static void shfl_add(Sum &S, int off) {
+        add(S.ax, __shfl_xor(S.ax, off, 64), S.bad); add(S.ay, __shfl_xor(S.ay, off, 64), S.bad);
+        add(S.az, __shfl_xor(S.az, off, 64), S.bad); add(S.jx, __shfl_xor(S.jx, off, 64), S.bad);
+        add(S.jy, __shfl_xor(S.jy, off, 64), S.bad); add(S.jz, __shfl_xor(S.jz, off, 64), S.bad);
+        add(S.p, __shfl_xor(S.p, off, 64), S.bad);
+        S.bad |= __shfl_xor(S.bad, off, 64);
     }
 };
 
@@ -494,11 +564,33 @@ template <> struct EpsOf<ModeF32> { using T = float; };
 template <> struct EpsOf<ModeDS> { using T = ds; };
 template <> struct EpsOf<ModeF64> { using T = double; };
 template <> struct EpsOf<ModeF32All> { using T = float; };
+template <> struct EpsOf<ModeF32Fixed> { using T = float; };
+
+// How a mode folds its sums: every FOLD j of a tile (TJ: once per tile), and whether the sums
+// are fixed-point integers (then at most TJ / FOLD lanes may share an i-particle).
+template <class M> struct ModeTraits {
+    static constexpr int FOLD = TJ;
+    static constexpr bool FIXED = false;
+};
+template <> struct ModeTraits<ModeF32Fixed> {
+    static constexpr int FOLD = 64;
+    static constexpr bool FIXED = true;
+};
 
 // Final sums of row q of a work item's j-range ks: straight to the outputs when K == 1,
-// else to partial plane ks.  The potential sum is negated here.
+// else to partial plane ks.  The potential sum is negated here (for fixed-point sums, whose
+// partial planes hold the raw integers, in the reduction).
+template <class M>
 __device__ __forceinline__ void store_result(const ForceCommon &fc, const ForcePlan &pl,
-                                             int32_t ks, int32_t q, Out7 o) {
+                                             int32_t ks, int32_t q, const typename M::Sum &S) {
+    double *base = fc.partial + (int64_t)ks * 7 * pl.P + q;
+    if constexpr (ModeTraits<M>::FIXED) {
+        if (pl.K > 1) {
+            M::store_raw(base, pl.P, S);
+            return;
+        }
+    }
+    Out7 o = M::out(S);
     o.v[6] = -o.v[6];
     if (pl.K == 1) {
         if (fc.ctl && !finite7(o)) fc.ctl->flag_nonfinite = 1;
@@ -510,7 +602,6 @@ __device__ __forceinline__ void store_result(const ForceCommon &fc, const ForceP
         fc.jerk[2 * (int64_t)fc.ld + q] = o.v[5];
         fc.pot[q] = o.v[6];
     } else {
-        double *base = fc.partial + (int64_t)ks * 7 * pl.P + q;
 #pragma unroll
         for (int c = 0; c < 7; ++c) base[(int64_t)c * pl.P] = o.v[c];
     }
@@ -537,16 +628,27 @@ __device__ void force_items_split(const typename M::Args &pa, const ForceCommon 
             __syncthreads();
             M::stage(pa, sm, threadIdx.x, t * TJ + (int32_t)threadIdx.x, fc.n);
             __syncthreads();
-            typename M::Tile T = M::tile_zero();
+            if constexpr (ModeTraits<M>::FOLD == TJ) {
+                typename M::Tile T = M::tile_zero();
 #pragma unroll UNR
-            for (int jj = slice; jj < TJ; jj += Sl) M::template interact<SOFT>(ii, sm, jj, eps2, T);
-            M::fold(S, T);
+                for (int jj = slice; jj < TJ; jj += Sl) M::template interact<SOFT>(ii, sm, jj, eps2, T);
+                M::fold(S, T);
+            } else {  // lanes take whole sub-blocks of FOLD j (Sl <= TJ / FOLD)
+                constexpr int FOLD = ModeTraits<M>::FOLD;
+                for (int b = slice; b < TJ / FOLD; b += Sl) {
+                    typename M::Tile T = M::tile_zero();
+#pragma unroll UNR
+                    for (int jj = b * FOLD; jj < (b + 1) * FOLD; ++jj)
+                        M::template interact<SOFT>(ii, sm, jj, eps2, T);
+                    M::fold(S, T);
+                }
+            }
         }
         for (int off = Sl >> 1; off > 0; off >>= 1) M::shfl_add(S, off);
         const int32_t jlo = t0 * TJ, jhi = t1 * TJ;
         if (slice == 0 && q < n_i) {
             if (SOFT && g >= jlo && g < jhi) M::remove_self(S, ii, eps2);
-            store_result(fc, pl, ks, q, M::out(S));
+            store_result<M>(fc, pl, ks, q, S);
         }
     }
 }
@@ -570,7 +672,7 @@ __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCom
         n_i = d < n_i ? d : n_i;
     }
     if (n_i <= 0) return;
-    const ForcePlan pl = make_plan(n_i, fc.n, WG * IPL, fc.target, fc.kmax);
+    const ForcePlan pl = make_plan(n_i, fc.n, WG * IPL, fc.target, fc.kmax, fc.smax);
     const auto eps2 = pa.eps2;
     if (IPL == 1 && pl.S > 1) {
         force_items_split<M, UNR, SOFT>(pa, fc, pl, sm, n_i, eps2);
@@ -594,23 +696,39 @@ __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCom
             __syncthreads();
             M::stage(pa, sm, threadIdx.x, t * TJ + (int32_t)threadIdx.x, fc.n);
             __syncthreads();
-            typename M::Tile T[IPL];
+            if constexpr (ModeTraits<M>::FOLD == TJ) {
+                typename M::Tile T[IPL];
 #pragma unroll
-            for (int p = 0; p < IPL; ++p) T[p] = M::tile_zero();
+                for (int p = 0; p < IPL; ++p) T[p] = M::tile_zero();
 #pragma unroll UNR
-            for (int jj = 0; jj < TJ; ++jj) {
+                for (int jj = 0; jj < TJ; ++jj) {
 #pragma unroll
-                for (int p = 0; p < IPL; ++p) M::template interact<SOFT>(ii[p], sm, jj, eps2, T[p]);
+                    for (int p = 0; p < IPL; ++p) M::template interact<SOFT>(ii[p], sm, jj, eps2, T[p]);
+                }
+#pragma unroll
+                for (int p = 0; p < IPL; ++p) M::fold(S[p], T[p]);
+            } else {  // sums folded every FOLD j (canonical sub-blocks)
+                constexpr int FOLD = ModeTraits<M>::FOLD;
+                for (int jb = 0; jb < TJ; jb += FOLD) {
+                    typename M::Tile T[IPL];
+#pragma unroll
+                    for (int p = 0; p < IPL; ++p) T[p] = M::tile_zero();
+#pragma unroll UNR
+                    for (int jj = jb; jj < jb + FOLD; ++jj) {
+#pragma unroll
+                        for (int p = 0; p < IPL; ++p) M::template interact<SOFT>(ii[p], sm, jj, eps2, T[p]);
+                    }
+#pragma unroll
+                    for (int p = 0; p < IPL; ++p) M::fold(S[p], T[p]);
+                }
             }
-#pragma unroll
-            for (int p = 0; p < IPL; ++p) M::fold(S[p], T[p]);
         }
         const int32_t jlo = t0 * TJ, jhi = t1 * TJ;
 #pragma unroll
         for (int p = 0; p < IPL; ++p) {
             if (q[p] >= n_i) continue;
             if (SOFT && g[p] >= jlo && g[p] < jhi) M::remove_self(S[p], ii[p], eps2);
-            store_result(fc, pl, ks, q[p], M::out(S[p]));
+            store_result<M>(fc, pl, ks, q[p], S[p]);
         }
     }
 }
@@ -622,32 +740,65 @@ __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCom
 constexpr int RW = 16;               // waves per reduce workgroup
 constexpr int WG_REDUCE = 64 * RW;
 
+// FIXED: the planes hold the raw int64 fixed-point sums of ModeF32Fixed; they are added as
+// integers (exact), converted with the mode's scales and the potential negated.
+template <bool FIXED>
 __global__ void __launch_bounds__(WG_REDUCE) force_reduce(ForceCommon fc, int32_t ib) {
     __shared__ double part[RW][64];
+    __shared__ int64_t ipart[FIXED ? RW : 1][64];
+    __shared__ int32_t ibad[FIXED ? RW : 1][64];
     int32_t n_i = fc.n_i_max;
     if (fc.n_i_dev) {
         const int32_t d = *fc.n_i_dev;
         n_i = d < n_i ? d : n_i;
     }
     if (n_i <= 0) return;
-    const ForcePlan pl = make_plan(n_i, fc.n, ib, fc.target, fc.kmax);
+    const ForcePlan pl = make_plan(n_i, fc.n, ib, fc.target, fc.kmax, fc.smax);
     if (pl.K == 1) return;
     const int32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int32_t units = ((n_i + 63) >> 6) * 7;
     for (int32_t u = blockIdx.x; u < units; u += gridDim.x) {
         const int32_t rb = u / 7, c = u - rb * 7;
         const int32_t q = rb * 64 + lane;
-        double s = 0.0;
-        if (q < n_i) {
-            const double *src = fc.partial + (int64_t)c * pl.P + q;
-            for (int32_t k = w; k < pl.K; k += RW) s += src[(int64_t)k * 7 * pl.P];
+        const double *src = fc.partial + (int64_t)c * pl.P + q;
+        if constexpr (FIXED) {
+            int64_t s = 0;
+            int32_t bad = 0;
+            if (q < n_i) {
+                for (int32_t k = w; k < pl.K; k += RW) {
+                    const int64_t v = (int64_t)__double_as_longlong(src[(int64_t)k * 7 * pl.P]);
+                    bad |= v == INT64_MIN;
+                    ModeF32Fixed::add(s, v, bad);
+                }
+            }
+            ipart[w][lane] = s;
+            ibad[w][lane] = bad;
+        } else {
+            double s = 0.0;
+            if (q < n_i)
+                for (int32_t k = w; k < pl.K; k += RW) s += src[(int64_t)k * 7 * pl.P];
+            part[w][lane] = s;
         }
-        part[w][lane] = s;
         __syncthreads();
         if (w == 0 && q < n_i) {
-            double t = part[0][lane];
+            double t;
+            if constexpr (FIXED) {
+                int64_t s = ipart[0][lane];
+                int32_t bad = ibad[0][lane];
 #pragma unroll
-            for (int r = 1; r < RW; ++r) t += part[r][lane];
+                for (int r = 1; r < RW; ++r) {
+                    bad |= ibad[r][lane];
+                    ModeF32Fixed::add(s, ipart[r][lane], bad);
+                }
+                const int F = c < 3 ? ModeF32Fixed::F_ACC : c < 6 ? ModeF32Fixed::F_JERK
+                                                                  : ModeF32Fixed::F_POT;
+                t = bad ? __builtin_nan("") : __builtin_ldexp((double)s, -F);
+                if (c == 6) t = -t;
+            } else {
+                t = part[0][lane];
+#pragma unroll
+                for (int r = 1; r < RW; ++r) t += part[r][lane];
+            }
             if (fc.ctl && !__builtin_isfinite(t)) fc.ctl->flag_nonfinite = 1;
             double *dst = c < 3 ? fc.acc + c * (int64_t)fc.ld
                         : c < 6 ? fc.jerk + (c - 3) * (int64_t)fc.ld : fc.pot;

@@ -29,6 +29,7 @@ using Variant = nb_variant;
 bool variant_compiled(int prec, const Variant &v) {
     const bool unr_ok = v.unroll == 1 || v.unroll == 2 || v.unroll == 4;
     if (prec == NB_FP32) return unr_ok && (v.ipl == 1 || v.ipl == 2);
+    if (prec == NB_FP32_FIXED) return (v.ipl == 1 || v.ipl == 2) && (v.unroll == 1 || v.unroll == 2);
     // NB_FP32_ALL, NB_DS, NB_FP64
     return v.ipl == 1 && (v.unroll == 1 || v.unroll == 2);
 }
@@ -175,8 +176,9 @@ Variant default_variant(int32_t n, int prec, int num_cu, bool block) {
     Variant v;
     // measured on MI355X at N = 2^20: two i per work-item, unroll 1 for full-force calls and
     // 2 for block steps; 16 work items per compute unit (full) and 8 (blocks)
-    v.ipl = (prec == NB_FP32 && n >= 16384) ? 2 : 1;
-    v.unroll = (prec == NB_FP32 && !block) ? 1 : 2;
+    const bool f32 = prec == NB_FP32 || prec == NB_FP32_FIXED;
+    v.ipl = (f32 && n >= 16384) ? 2 : 1;
+    v.unroll = (f32 && !block) ? 1 : 2;
     v.target = num_cu * (block ? 8 : 16);
     v.kmax = 1 << 16;  // K is bounded by the tile count and by target / i-blocks anyway
     return v;
@@ -192,7 +194,8 @@ nb_status enqueue_predict(nb_ctx *c, const int64_t *t, int guard, hipStream_t s)
     const StateView sv = state_view(c);
     const int32_t grid = grid_for(c->n, 8192);
     switch (c->prec) {
-        case NB_FP32: predict_kernel<0><<<grid, WG, 0, s>>>(sv, c->js, t, c->ctl, guard); break;
+        case NB_FP32:
+        case NB_FP32_FIXED: predict_kernel<0><<<grid, WG, 0, s>>>(sv, c->js, t, c->ctl, guard); break;
         case NB_DS: predict_kernel<1><<<grid, WG, 0, s>>>(sv, c->js, t, c->ctl, guard); break;
         case NB_FP32_ALL: predict_kernel<3><<<grid, WG, 0, s>>>(sv, c->js, t, c->ctl, guard); break;
         default: predict_kernel<2><<<grid, WG, 0, s>>>(sv, c->js, t, c->ctl, guard); break;
@@ -233,13 +236,27 @@ void launch_f32(const ModeF32::Args &pa, const ForceCommon &fc, const Variant &v
     }
 }
 
+void launch_fixed(const ModeF32Fixed::Args &pa, const ForceCommon &fc, const Variant &v,
+                  bool soft, int cls, int32_t grid, hipStream_t s) {
+    if (v.ipl == 2) {
+        if (v.unroll == 1) launch_soft<ModeF32Fixed, 2, 1>(pa, fc, soft, cls, grid, s);
+        else launch_soft<ModeF32Fixed, 2, 2>(pa, fc, soft, cls, grid, s);
+    } else {
+        if (v.unroll == 1) launch_soft<ModeF32Fixed, 1, 1>(pa, fc, soft, cls, grid, s);
+        else launch_soft<ModeF32Fixed, 1, 2>(pa, fc, soft, cls, grid, s);
+    }
+}
+
+// Largest lane split of a precision's force kernel (fixed-point sums: whole 64-j sub-blocks).
+int32_t smax_of(int prec) { return prec == NB_FP32_FIXED ? TJ / ModeTraits<ModeF32Fixed>::FOLD : 64; }
+
 // Largest K * P over every i-count up to n, for one variant.
-int64_t partial_rows_for(int32_t n, const Variant &v) {
+int64_t partial_rows_for(int32_t n, const Variant &v, int32_t smax) {
     const int32_t ib = WG * v.ipl;
     int64_t rows = 0;
     for (int32_t nb = 1; nb <= (n + ib - 1) / ib; ++nb) {
         const ForcePlan pl = make_plan((int32_t)std::min<int64_t>((int64_t)nb * ib, n), n, ib,
-                                       v.target, v.kmax);
+                                       v.target, v.kmax, smax);
         if (pl.K > 1) rows = std::max<int64_t>(rows, (int64_t)pl.K * pl.P);
         if (pl.K == 1) break;  // K only falls as the number of i-blocks grows
     }
@@ -250,15 +267,16 @@ nb_status enqueue_force(nb_ctx *c, const Variant &v, int cls, const int32_t *ili
                         const int32_t *n_i_dev, int32_t n_i_max, double *acc, double *jerk,
                         double *pot, int32_t ld, hipStream_t s) {
     const int32_t ib = WG * v.ipl;
+    const int32_t smax = smax_of(c->prec);
     ForceCommon fc{c->n, ilist, n_i_dev, n_i_max, v.target, v.kmax, acc, jerk, pot, ld,
-                   c->partial, c->ctl};
+                   c->partial, c->ctl, smax};
     int32_t grid;
     if (n_i_dev) {
         // the count is known only on the device: enough workgroups for any count up to n_i_max
-        const ForcePlan full = make_plan(n_i_max, c->n, ib, v.target, v.kmax);
+        const ForcePlan full = make_plan(n_i_max, c->n, ib, v.target, v.kmax, smax);
         grid = std::max(std::max(1, v.target), std::min(full.items, 65535));
     } else {
-        const ForcePlan p = make_plan(n_i_max, c->n, ib, v.target, v.kmax);
+        const ForcePlan p = make_plan(n_i_max, c->n, ib, v.target, v.kmax, smax);
         grid = std::min(p.items, 1 << 20);
     }
     const bool soft = c->eps > 0.0;
@@ -272,6 +290,11 @@ nb_status enqueue_force(nb_ctx *c, const Variant &v, int cls, const int32_t *ili
         case NB_FP32: {
             ModeF32::Args pa{c->js.px, c->js.py, c->js.pz, c->js.vm, (float)(c->eps * c->eps)};
             launch_f32(pa, fc, v, soft, cls, grid, s);
+            break;
+        }
+        case NB_FP32_FIXED: {
+            ModeF32Fixed::Args pa{c->js.px, c->js.py, c->js.pz, c->js.vm, (float)(c->eps * c->eps)};
+            launch_fixed(pa, fc, v, soft, cls, grid, s);
             break;
         }
         case NB_FP32_ALL: {
@@ -300,7 +323,9 @@ nb_status enqueue_force(nb_ctx *c, const Variant &v, int cls, const int32_t *ili
     }
     // second pass: a no-op when the plan has K == 1
     const int32_t units = ((n_i_max + 63) / 64) * 7;
-    force_reduce<<<std::max(1, std::min(units, c->num_cu * 8)), WG_REDUCE, 0, s>>>(fc, ib);
+    const int32_t rgrid = std::max(1, std::min(units, c->num_cu * 8));
+    if (c->prec == NB_FP32_FIXED) force_reduce<true><<<rgrid, WG_REDUCE, 0, s>>>(fc, ib);
+    else force_reduce<false><<<rgrid, WG_REDUCE, 0, s>>>(fc, ib);
     LAUNCH_OK(c);
     return NB_OK;
 }
@@ -375,7 +400,7 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
     if (!out) return NB_EINVAL;
     *out = nullptr;
     if (n < 1 || n > (1 << 28) || !(eps >= 0.0) || !std::isfinite(eps) || lmin < 0 ||
-        lmax < lmin || lmax > 52 || precision < NB_FP32 || precision > NB_FP32_ALL)
+        lmax < lmin || lmax > 52 || precision < NB_FP32 || precision > NB_FP32_FIXED)
         return NB_EINVAL;
     nb_ctx *c = new nb_ctx();
     c->n = n; c->eps = eps; c->lmin = lmin; c->lmax = lmax; c->prec = precision;
@@ -392,7 +417,7 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
     if ((r = alloc(c, &c->jbuf, 64 * N)) != NB_OK) { nb_destroy(c); return r; }
     {
         char *b = (char *)c->jbuf;
-        if (precision == NB_FP32) {
+        if (precision == NB_FP32 || precision == NB_FP32_FIXED) {
             c->js.px = (double *)b; c->js.py = c->js.px + N; c->js.pz = c->js.py + N;
             c->js.vm = (float4 *)(c->js.pz + N);
         } else if (precision == NB_DS) {
@@ -414,7 +439,8 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
     {
         int64_t rows = 0;
         for (int ipl = 1; ipl <= 2; ++ipl)
-            rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->max_target, 1 << 16}));
+            rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->max_target, 1 << 16},
+                                                   smax_of(precision)));
         c->partial_rows = rows;
         if ((r = alloc(c, &p, (size_t)std::max<int64_t>(rows, 1) * 7 * sizeof(double))) != NB_OK) {
             nb_destroy(c); return r;
@@ -744,7 +770,7 @@ nb_status nb_step_vjp(nb_ctx *c, double dt, double *xbar, double *vbar, double *
 static bool variant_valid(const nb_ctx *c, const nb_variant &v) {
     if (!variant_compiled(c->prec, v)) return false;
     if (v.target < 1 || v.target > c->max_target || v.kmax < 1 || v.kmax > (1 << 16)) return false;
-    return partial_rows_for(c->n, v) <= c->partial_rows;
+    return partial_rows_for(c->n, v, smax_of(c->prec)) <= c->partial_rows;
 }
 
 nb_status nb_get_variant(nb_ctx *c, int32_t which, nb_variant *out) {

@@ -16,7 +16,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "lib", "libnbody.so")
 
 NB_OK, NB_EINVAL, NB_EDEVICE, NB_ENOMEM, NB_ESTATE, NB_ENONFINITE, NB_EDTMIN = 0, -1, -2, -3, -4, -5, -6
-PRECISIONS = {"fp32": 0, "ds": 1, "fp64": 2, "fp32all": 3}
+PRECISIONS = {"fp32": 0, "ds": 1, "fp64": 2, "fp32all": 3, "fp32fixed": 4}
 _STATUS_NAMES = {0: "NB_OK", -1: "NB_EINVAL", -2: "NB_EDEVICE", -3: "NB_ENOMEM", -4: "NB_ESTATE",
                  -5: "NB_ENONFINITE", -6: "NB_EDTMIN"}
 

@@ -1,0 +1,118 @@
+"""Order-independent single precision (fp32fixed): float sums over aligned 64-j sub-blocks added
+into int64 fixed point.  Its forces must be bitwise identical for every launch variant (i per
+lane 1 or 2, unroll 1 or 2), every work-item target (which changes the j-split K and, for short
+lists, the lane split), and between the full-force and block-step launch classes; they must
+meet the single-precision tolerances against the oracle (the fixed-point steps, 2^-40 for acc and
+pot and 2^-32 for the jerk, add at most N/64 half-steps: below 1e-8 absolute at N = 2^20); and
+sums outside the fixed-point range must be reported, not wrapped.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_astro_ph_0702058_amd import nbody
+from paper_astro_ph_0702058_amd.plummer import plummer, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = [dict(ipl=i, unroll=u, target=t, kmax=65536)
+            for i in (1, 2) for u in (1, 2) for t in (8, 256, 4096)]
+
+
+def rms_rel(got, ref):
+    if got.ndim == 1:
+        return float(np.sqrt(np.mean(((got - ref) / ref) ** 2)))
+    return float(np.sqrt(np.mean(np.sum((got - ref) ** 2, 1) / np.sum(ref ** 2, 1))))
+
+
+def forces(ctx, n, idx, which):
+    """Force on the listed i through the block-step class (device count) or the full class."""
+    acc = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+    jerk = torch.zeros_like(acc)
+    pot = torch.zeros(n, dtype=torch.float64, device="cuda")
+    if which == 1:
+        ii = torch.as_tensor(idx.astype(np.int32), device="cuda")
+        cnt = torch.tensor([idx.size], dtype=torch.int32, device="cuda")
+        ctx.nb_force(acc, jerk, pot, i_idx=ii, n_i=cnt)
+    else:
+        ii = torch.as_tensor(idx.astype(np.int32), device="cuda")
+        a2 = torch.zeros((3, idx.size), dtype=torch.float64, device="cuda")
+        k2 = torch.zeros_like(a2)
+        p2 = torch.zeros(idx.size, dtype=torch.float64, device="cuda")
+        ctx.nb_force(a2, k2, p2, i_idx=ii)
+        acc[:, :idx.size] = a2; jerk[:, :idx.size] = k2; pot[:idx.size] = p2
+    ctx.nb_sync()
+    return (acc[:, :idx.size].cpu().numpy().T.copy(), jerk[:, :idx.size].cpu().numpy().T.copy(),
+            pot[:idx.size].cpu().numpy().copy())
+
+
+@pytest.mark.parametrize("eps", [1 / 256, 0.0])
+@pytest.mark.parametrize("count", [3, 37, 200, 700, 5001])
+def test_bitwise_identical_across_variants(eps, count):
+    n = 5001
+    x, v, m = plummer(n, 41)
+    idx = np.arange(n) if count == n else sample_indices(n, count, 7 + count)
+    st = nbody.DeviceState(x, v, m)
+    results = []
+    with nbody.Context(n, eps, precision="fp32fixed") as ctx:
+        ctx.nb_bind(st)
+        ctx.nb_predict(torch.zeros(1, dtype=torch.int64, device="cuda"))
+        for var in VARIANTS:
+            for which in (0, 1):
+                ctx.nb_set_variant(which, var)
+                results.append((var, which, forces(ctx, n, idx, which)))
+    ref = oracle.force(x, v, m, eps * eps, idx=idx)
+    first = results[0][2]
+    e = [rms_rel(first[c], ref[c]) for c in range(3)]
+    print(f"count={count} eps={eps}: e_acc={e[0]:.3e} e_jerk={e[1]:.3e} e_pot={e[2]:.3e}",
+          flush=True)
+    assert e[0] <= 2e-6 and e[1] <= 1e-5 and e[2] <= 2e-6
+    for var, which, got in results[1:]:
+        for c in range(3):
+            assert np.array_equal(got[c], first[c]), (var, which, c)
+
+
+def test_full_size_sampled_and_same_as_block_class():
+    """N = 2^20, eps = 1/256: the all-i launch (j-split K = 2 at the default 16 items per CU)
+    and a 128-particle list through the block class (K up to the tile count, lane split)
+    give bitwise the same rows; both meet the tolerances against the oracle."""
+    n = 1 << 20
+    x, v, m = plummer(n, 3)
+    idx = np.sort(sample_indices(n, 128, 21))
+    st = nbody.DeviceState(x, v, m)
+    with nbody.Context(n, 1 / 256, precision="fp32fixed") as ctx:
+        ctx.nb_bind(st)
+        ctx.nb_predict(torch.zeros(1, dtype=torch.int64, device="cuda"))
+        acc = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        jerk = torch.zeros_like(acc); pot = torch.zeros(n, dtype=torch.float64, device="cuda")
+        ctx.nb_force(acc, jerk, pot)
+        ctx.nb_sync()
+        ii = torch.as_tensor(idx, device="cuda")
+        full = (acc[:, ii].cpu().numpy().T, jerk[:, ii].cpu().numpy().T, pot[ii].cpu().numpy())
+        blk = forces(ctx, n, idx, 1)
+    ref = oracle.force(x, v, m, (1 / 256) ** 2, idx=idx)
+    e = [rms_rel(full[c], ref[c]) for c in range(3)]
+    print(f"N=2^20: e_acc={e[0]:.3e} e_jerk={e[1]:.3e} e_pot={e[2]:.3e}", flush=True)
+    assert e[0] <= 2e-6 and e[1] <= 1e-5 and e[2] <= 2e-6
+    for c in range(3):
+        assert np.array_equal(full[c], blk[c]), c
+
+
+def test_range_overflow_is_reported():
+    """Unsoftened pair at separation 1e-4 with unit masses: |acc| = 1e8 > 2^23, outside the
+    fixed-point range; the result is poisoned and the next synchronising call reports it."""
+    x = np.array([[0.0, 0.0, 0.0], [1e-4, 0.0, 0.0], [1.0, 1.0, 1.0]])
+    v = np.zeros((3, 3)); m = np.ones(3)
+    st = nbody.DeviceState(x, v, m)
+    with nbody.Context(3, 0.0, precision="fp32fixed") as ctx:
+        ctx.nb_bind(st)
+        ctx.nb_predict(torch.zeros(1, dtype=torch.int64, device="cuda"))
+        acc = torch.zeros((3, 3), dtype=torch.float64, device="cuda")
+        jerk = torch.zeros_like(acc); pot = torch.zeros(3, dtype=torch.float64, device="cuda")
+        ctx.nb_force(acc, jerk, pot)
+        with pytest.raises(nbody.NBodyError) as e:
+            ctx.nb_sync()
+        assert e.value.status == nbody.NB_ENONFINITE
+        a = acc.cpu().numpy()
+    assert np.all(np.isnan(a[:, :2])) and np.all(np.isfinite(a[:, 2]))
