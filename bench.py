@@ -119,7 +119,7 @@ def bench_ensemble(args):
         "metric": "interactions/s, batched ensemble", "value": inter / elapsed,
         "unit": "interactions/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * elapsed, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"fp32": "f32", "ds": "f32x2", "fp64": "f64"}[args.precision],
+        "vs_baseline": None, "dtype": {"fp32": "f32", "ds": "f32x2", "fp64": "f64", "fp32all": "f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.clusters} Plummer clusters, N_c log-uniform [64, 4096] "
                                f"(total {int(sizes.sum())}), eps=1/N_c, eta=0.02, t -> {args.t_end}",
@@ -208,7 +208,7 @@ def bench_run(args):
         "value": inter / wall, "unit": "interactions/s", "n_gpus": 1, "steps": len(runs),
         "warmup": args.warmup, "ms_per_step": 1e3 * wall, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32", "ds": "f32x2", "fp64": "f64"}[args.precision],
+        "dtype": {"fp32": "f32", "ds": "f32x2", "fp64": "f64", "fp32all": "f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"Plummer N={n} (eps={eps:g}, eta={nu}, dt_max=2^-{lmin}) "
                                f"block-step run t=0 -> {t_end}", "n": n, "eps": eps, "eta": nu,
@@ -259,8 +259,15 @@ def bench_accuracy(args):
     measurements): Plummer N = 1024 (seed 1) and 16384 (seed 7), eps = 1/256, dt <= 1/8,
     nu = 0.1 / 2^k for k = 0 .. 8; each run goes from t = 0 to 1/4 and on to 1/2 and reports
     |E(1/2) - E(1/4)| / |E(1/4)| for the four interaction arithmetics (all-single as in the
-    paper's kernel, FP32 with double separations, double-single, FP64).  `value` = force
-    interactions per second over all the runs; the committed oracle curves are attached."""
+    paper's kernel, FP32 with double separations, double-single, FP64).  E comes from the FP64
+    energy diagnostic; E' = kinetic + (1/2) sum_i m_i phi_i uses the force kernel's own
+    potentials instead (at t = 1/4 and 1/2 every particle has just been evaluated), which is
+    how an energy check reads when the potential comes from the force pass (taken at the
+    predicted positions, and in the paper's kernel from single-precision sums).  A run whose
+    block steps exceed 4 times the oracle's count at that nu (over t = 0 .. 1/2) is stopped and
+    marked collapsed: rounding noise in a and k, divided by dt^2 and dt^3 in the corrector's
+    derivative estimates, drives the step criterion down towards the 2^-26 floor.  `value` = force interactions per
+    second over all the runs; the committed oracle curves are attached."""
     if args.gpus != 1:
         print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
@@ -270,12 +277,16 @@ def bench_accuracy(args):
     sizes = {1024: 1, 16384: 7}
     nus = [0.1 / 2 ** k for k in range(9)]
     precs = ["fp32all", "fp32", "ds", "fp64"]
+    gold = os.path.join(ROOT, "tests", "golden", "accuracy_sweep.json")
+    g = json.load(open(gold)) if os.path.exists(gold) else {}
     curves, inter, wall = {}, 0.0, 0.0
     for n, seed in sizes.items():
         x, v, m = plummer(n, seed)
+        ref_steps = {round(r["nu"], 12): r["n_steps"] for r in g.get(str(n), {}).get("rows", [])}
         for prec in precs:
             rows = []
             for nu in nus:
+                budget = 4 * 2 * ref_steps.get(round(nu, 12), 20000)   # both halves
                 st = nbody.DeviceState(x, v, m)
                 with nbody.Context(n, 1 / 256, lmin=3, lmax=26, precision=prec,
                                    allow_dtmin=True) as ctx:
@@ -283,23 +294,36 @@ def bench_accuracy(args):
                     torch.cuda.synchronize()
                     t_a = time.perf_counter()
                     ctx.nb_init(nu)
-                    ctx.nb_run(nu, 0.25, chunk=256)
+                    ctx.nb_run(nu, 0.25, max_steps=budget, chunk=256)
                     ek, ep = ctx.nb_energy()
                     c0 = ctx.nb_read_control()
-                    ctx.nb_run(nu, 0.5, chunk=256)
+                    mp0 = float((st.m * st.pot).sum()) / 2
+                    ok = c0.t_cur == 1 << 24
+                    if ok:
+                        ctx.nb_run(nu, 0.5, max_steps=budget - c0.n_steps, chunk=256)
                     ek1, ep1 = ctx.nb_energy()
                     c1 = ctx.nb_read_control()
+                    mp1 = float((st.m * st.pot).sum()) / 2
+                    ok = ok and c1.t_cur == 1 << 25
                     el = time.perf_counter() - t_a
                 e0, e1 = ek + ep, ek1 + ep1
                 steps = c1.n_steps - c0.n_steps
-                rows.append({"nu": nu, "de_rel": abs((e1 - e0) / e0), "n_steps": steps,
-                             "dtmin_clamped": ctx.dtmin_clamped,
-                             "mean_block": (c1.n_active_sum - c0.n_active_sum) / max(steps, 1),
-                             "seconds": el})
+                row = {"nu": nu, "collapsed": not ok, "dtmin_clamped": ctx.dtmin_clamped,
+                       "t_reached": c1.t_cur / 2.0 ** 26, "seconds": el}
+                if ok:
+                    row.update({"steps_vs_oracle": steps / ref_steps.get(round(nu, 12), steps),
+                                "de_rel": abs((e1 - e0) / e0),
+                                "de_rel_kernel_pot": abs((ek1 + mp1 - ek - mp0) / (ek + mp0)),
+                                "n_steps": steps,
+                                "mean_block": (c1.n_active_sum - c0.n_active_sum) / max(steps, 1)})
+                rows.append(row)
                 inter += n * n + n * c1.n_active_sum
                 wall += el
+                log(f"[bench] N={n} {prec} nu={nu:.5g}: " + (
+                    f"dE/E {row['de_rel']:.2e} (kernel phi {row['de_rel_kernel_pot']:.2e}), "
+                    f"{steps} steps, {el:.2f} s" if ok else
+                    f"collapsed at t={row['t_reached']:.6f} after {c1.n_steps} steps, {el:.2f} s"))
             curves[f"{n}/{prec}"] = rows
-            log(f"[bench] N={n} {prec}: " + " ".join(f"{r['de_rel']:.1e}" for r in rows))
     result = {
         "metric": "|dE/E| over t = 1/4 .. 1/2 against nu (energy conservation experiment); value = "
                   "force interactions/s over all runs",
@@ -311,12 +335,125 @@ def bench_accuracy(args):
                    "precisions": precs},
         "curves": curves,
     }
-    gold = os.path.join(ROOT, "tests", "golden", "accuracy_sweep.json")
-    if os.path.exists(gold):
-        g = json.load(open(gold))
+    if g:
         result["oracle_curves"] = {k: [{"nu": r["nu"], "de_rel": r["de_rel"],
                                         "n_steps": r["n_steps"]} for r in g[k]["rows"]]
                                    for k in g if k != "params"}
+    print(json.dumps(result), flush=True)
+
+
+# Wall-clock seconds over t = 1/4 .. 1/2 printed in the paper's results table (Sec. Results):
+# GRAPE-6Af, GeForce 8800GTX, Quadro FX1400, Xeon host; None where not measured.
+PAPER_TIMED_RUNS = {
+    256: (0.07098, 2.708, 3.423, 0.1325), 512: (0.1410, 8.777, 10.59, 0.5941),
+    1024: (0.3327, 17.46, 20.20, 2.584), 2048: (0.7652, 45.27, 54.16, 10.59),
+    4096: (1.991, 128.3, 157.8, 50.40), 8192: (5.552, 342.7, 617.3, 224.7),
+    16384: (16.32, 924.4, 3398, 994.0), 32768: (51.68, 1907, 13180, 4328),
+    65536: (178.2, 3973, 40560, 19290), 131072: (None, 8844, None, None),
+    262144: (None, 22330, None, None), 524288: (None, 63960, None, None),
+}
+
+
+def bench_timed(args):
+    """The timed runs of the paper's results table: Plummer spheres of N = 256 .. 2^19 (seed
+    100 + log2 N), eps = 1/256, nu = 0.01, dt in [2^-26, 1/8], integrated from t = 0 to 1/2 by
+    the device-resident loop and timed over t = 1/4 .. 1/2.  Reported per N: wall seconds,
+    block steps and mean block size over the window, with the paper's fits n_block = a N^b and
+    n_steps = c N^d refitted, and the block-step time fitted to
+    t_step = tau_0 + tau_pred N + tau_corr n_block + tau_fe N n_block (non-negative least
+    squares over all N; the paper's model with the host and bus terms replaced by device work).
+    `value` = force interactions per second over the window at the largest N."""
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from scipy.optimize import nnls
+    from paper_astro_ph_0702058_amd import nbody
+    from paper_astro_ph_0702058_amd.plummer import plummer
+    ns = [n for n in sorted(PAPER_TIMED_RUNS) if n <= args.max_n]
+    n = 2 * ns[-1]
+    while n <= args.max_n:      # beyond the paper's largest N
+        ns.append(n)
+        n *= 2
+    eps, nu, lmin = 1 / 256, 0.01, 3
+    rows = []
+    for n in ns:
+        x, v, m = plummer(n, 100 + int(math.log2(n)))
+        st = nbody.DeviceState(x, v, m)
+        with nbody.Context(n, eps, lmin=lmin, lmax=26, precision=args.precision) as ctx:
+            ctx.nb_bind(st)
+            ctx.nb_init(nu)
+            ctx.nb_run(nu, 0.25, chunk=256)
+            c0 = ctx.nb_read_control()
+            torch.cuda.synchronize()
+            t_a = time.perf_counter()
+            ctx.nb_run(nu, 0.5, chunk=256)
+            ctx.nb_sync()
+            wall = time.perf_counter() - t_a
+            c1 = ctx.nb_read_control()
+        steps = c1.n_steps - c0.n_steps
+        act = c1.n_active_sum - c0.n_active_sum
+        paper = PAPER_TIMED_RUNS.get(n, (None,) * 4)
+        rows.append({"n": n, "seconds": wall, "n_steps": steps, "mean_block": act / steps,
+                     "interactions_per_s": n * act / wall, "us_per_step": 1e6 * wall / steps,
+                     "paper_s": {"grape6af": paper[0], "gf8800gtx": paper[1], "fx1400": paper[2],
+                                 "xeon": paper[3]}})
+        log(f"[bench] N={n}: {wall:.3f} s over the window, {steps} steps, mean block "
+            f"{act / steps:.1f}, {n * act / wall:.3e} interactions/s")
+    big = [r for r in rows if r["n"] >= 1024]
+    lb = np.polyfit(np.log([r["n"] for r in big]), np.log([r["mean_block"] for r in big]), 1)
+    ls = np.polyfit(np.log([r["n"] for r in big]), np.log([4 * r["n_steps"] for r in big]), 1)
+    A = np.array([[r["n_steps"], r["n_steps"] * r["n"], r["n_steps"] * r["mean_block"],
+                   r["n_steps"] * r["mean_block"] * r["n"]] for r in rows])
+    tau, _ = nnls(A / np.array([r["seconds"] for r in rows])[:, None], np.ones(len(rows)))
+    last = rows[-1]
+    result = {
+        "metric": "wall seconds over t = 1/4 .. 1/2 per N (the paper's timed runs); value = force "
+                  "interactions/s over the window at the largest N",
+        "value": last["interactions_per_s"], "unit": "interactions/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": 1e3 * last["seconds"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp32": "f32", "ds": "f32x2", "fp64": "f64", "fp32all": "f32"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"Plummer N=256..{ns[-1]} (seed 100+log2 N), eps=1/256, eta=0.01, "
+                               "dt_max=1/8, run t=0 -> 1/2, timed t=1/4 -> 1/2",
+                   "precision": args.precision},
+        "rows": rows,
+        "fits": {"n_block": {"a": float(np.exp(lb[1])), "b": float(lb[0]),
+                             "paper": {"a": 0.20, "b": 0.81}},
+                 "n_steps_per_time_unit": {"c": float(np.exp(ls[1])), "d": float(ls[0]),
+                                           "paper": {"c": 247, "d": 0.35}},
+                 "t_step_s": {"tau_0": tau[0], "tau_pred_per_particle": tau[1],
+                              "tau_corr_per_block_member": tau[2],
+                              "tau_fe_per_interaction": tau[3],
+                              "paper_gf8800gtx": {"t_host_per_particle": 3.82e-7,
+                                                  "tau_fe_per_interaction": 8.15e-10,
+                                                  "send_per_particle": 1.76e-5,
+                                                  "receive_per_particle": 5.97e-6}}},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        spent, best = 0.0, None
+        for n in ns:
+            x, v, m = plummer(n, 100 + int(math.log2(n)))
+            it = oracle.BlockIntegrator(x, v, m, eps=eps, nu=nu, lmin=lmin)
+            t_a = time.perf_counter()
+            it.run_until(0.25)
+            s0, a0 = it.n_steps, it.n_active_total
+            t_b = time.perf_counter()
+            it.run_until(0.5)
+            t_c = time.perf_counter()
+            spent += t_c - t_a
+            best = (n, t_c - t_b, it.n_active_total - a0)
+            if spent * 4 > args.cpu_seconds:   # the next N costs about 4x more
+                break
+        n, el, act = best
+        result["cpu_baseline"] = {
+            "value": n * act / el, "unit": "interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"oracle timed over t = 1/4 .. 1/2 at N = {n}: {el:.2f} s (GPU: "
+                      f"{next(r['seconds'] for r in rows if r['n'] == n):.3f} s)"}
     print(json.dumps(result), flush=True)
 
 
@@ -390,17 +527,19 @@ def main():
     ap.add_argument("--eps", type=float, default=1.0 / 256)
     ap.add_argument("--lmin", type=int, default=3)
     ap.add_argument("--seed", type=int, default=3)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "ds", "fp64"])
-    ap.add_argument("--variants", default="ds,fp64",
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "ds", "fp64", "fp32all"])
+    ap.add_argument("--variants", default="ds,fp64,fp32fixed",
                     help="other interaction arithmetics to time once (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="full", choices=["full", "ensemble", "adjoint", "run", "accuracy"],
+    ap.add_argument("--workload", default="full", choices=["full", "ensemble", "adjoint", "run", "accuracy", "timed"],
                     help="full: N-body force + block steps at N (default); ensemble: 512 "
                          "Plummer clusters, N_c log-uniform in [64, 4096], eps = 1/N_c, "
                          "eta = 0.02, to t = 1; adjoint: gradient of a trajectory loss over "
                          "64 shared steps at N = 16384; run: a block-step run (--run); "
-                         "accuracy: energy error against nu for every arithmetic")
+                         "accuracy: energy error against nu for every arithmetic; timed: the "
+                         "paper's timed runs over N")
+    ap.add_argument("--max-n", type=int, default=1 << 19)
     ap.add_argument("--run", default="n65536_t1", choices=sorted(RUNS))
     ap.add_argument("--clusters", type=int, default=512)
     ap.add_argument("--t-end", type=float, default=1.0)
@@ -417,6 +556,8 @@ def main():
         return bench_run(args)
     if args.workload == "accuracy":
         return bench_accuracy(args)
+    if args.workload == "timed":
+        return bench_timed(args)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -514,7 +655,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32", "ds": "f32x2",
-                                                           "fp64": "f64"}[args.precision],
+                                                           "fp64": "f64", "fp32all": "f32"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"Plummer N={n} (eps={args.eps:g}, eta={args.eta:g}, "
                                f"dt_max=2^-{args.lmin}): full force + {args.block_steps} "
