@@ -57,11 +57,11 @@ typedef enum {
  *           in float, sums over all j in float.  Single contexts only (not ensembles, not the
  *           shared-step and adjoint calls); a reference point for accuracy studies.
  *  NB_FP32_FIXED: the NB_FP32 interaction with order-independent sums: float sums over aligned
- *           64-j sub-blocks added into int64 fixed point (acc and pot 2^-40, jerk 2^-32; the
+ *           64-j sub-blocks added into int64 fixed point (acc and pot 2^-44, jerk 2^-42; the
  *           idea of the GRAPE-6 accumulators the paper compares with), so forces are bitwise
  *           identical for every launch variant and j-split.  Sums beyond the fixed-point range
- *           (|acc|, |pot| >= 2^23, |jerk| >= 2^31) are reported as NB_ENONFINITE.  Single
- *           contexts only, as NB_FP32_ALL. */
+ *           (|acc|, |pot| >= 2^19, |jerk| >= 2^21; enough for total mass 1 and eps >= 1e-3)
+ *           are reported as NB_ENONFINITE.  Single contexts only, as NB_FP32_ALL. */
 typedef enum {
     NB_FP32 = 0, NB_DS = 1, NB_FP64 = 2, NB_FP32_ALL = 3, NB_FP32_FIXED = 4
 } nb_precision;

@@ -290,12 +290,16 @@ struct ModeF32All {
 // each sub-block sum is added into int64 accumulators in fixed point (scale 2^F per quantity).
 // Integer addition is exact and associative, and a sub-block's float sum depends only on which
 // j it holds, so the result is bitwise the same for any j-split, i-per-lane, unroll, work-item
-// count or lane split.  Fixed-point steps: acc 2^-40 (range +-2^23), jerk 2^-32 (+-2^31),
-// pot 2^-40.  A sub-block sum outside the range or an overflowing accumulator poisons the
-// record, which comes out as NaN (reported as a non-finite force).
+// count or lane split.  Fixed-point steps: acc and pot 2^-44 (range +-2^19), jerk 2^-42
+// (+-2^21).  With total mass 1 a softened pull is at most 0.385/eps^2 and a potential 1/eps,
+// inside the range for eps >= 1e-3; the steps keep the rounding of N/64 sub-block conversions
+// (about 2^-44 sqrt(N/64) absolute) far below single-precision error also for the small
+// accelerations and jerks of halo particles.  A sub-block sum outside the range or an
+// overflowing accumulator poisons the record, which comes out as NaN (reported as a
+// non-finite force).
 // ------------------------------------------------------------------------------------------
 struct ModeF32Fixed : ModeF32 {
-    static constexpr int F_ACC = 40, F_JERK = 32, F_POT = 40;
+    static constexpr int F_ACC = 44, F_JERK = 42, F_POT = 44;
     struct Sum {
         int64_t ax, ay, az, jx, jy, jz, p;
         int32_t bad;
