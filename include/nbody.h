@@ -210,9 +210,10 @@ nb_status nb_step_vjp(nb_ctx *ctx, double dt, double *xbar, double *vbar, double
 
 /* Force-kernel launch variant: i-particles held per work-item (ipl), unroll of the j-loop,
  * desired number of equal work items per launch (target; the j-range is split K ways when the
- * i-blocks alone are fewer) and the largest split (kmax).  Compiled: fp32 ipl in {1, 2} and
- * unroll in {1, 2, 4}; ds and fp64 ipl = 1 and unroll in {1, 2}.  Any choice computes the same
- * sums up to rounding order. */
+ * i-blocks alone are fewer) and the largest split (kmax).  Compiled: fp32 ipl in {1, 2} with
+ * unroll in {1, 2, 4}, and ipl = 4 with unroll in {1, 2}; fixed-point ipl in {1, 2} with unroll
+ * in {1, 2}; ds, fp64 and all-single ipl = 1 and unroll in {1, 2}.  Any choice computes the
+ * same sums up to rounding order (fixed-point: bitwise the same). */
 typedef struct {
     int32_t ipl, unroll, target, kmax;
 } nb_variant;
@@ -222,9 +223,10 @@ typedef struct {
  * (which = 1). */
 nb_status nb_get_variant(nb_ctx *ctx, int32_t which, nb_variant *out);
 
-/* Replace that variant (HOST struct).  NB_EINVAL if it is not compiled, or if its j-split
- * would need more partial-sum storage than the context holds (targets up to 16 per compute
- * unit, kmax <= 65536). */
+/* Replace that variant (HOST struct).  NB_EINVAL if it is not compiled, if its target exceeds
+ * 128 work items per compute unit, or if its j-split would need more partial-sum storage than
+ * the context holds (sized for one or two i per work-item with up to 16 items per compute unit
+ * and any split, or up to 128 items per compute unit and at most 64 j-ranges). */
 nb_status nb_set_variant(nb_ctx *ctx, int32_t which, const nb_variant *v);
 
 /* Autotuner: launch every available variant on the first n_i particles against the

@@ -28,7 +28,8 @@ using Variant = nb_variant;
 // Compiled force-kernel variants: i-particles per work-item x j-loop unroll.
 bool variant_compiled(int prec, const Variant &v) {
     const bool unr_ok = v.unroll == 1 || v.unroll == 2 || v.unroll == 4;
-    if (prec == NB_FP32) return unr_ok && (v.ipl == 1 || v.ipl == 2);
+    if (prec == NB_FP32)
+        return unr_ok && (v.ipl == 1 || v.ipl == 2 || (v.ipl == 4 && v.unroll <= 2));
     if (prec == NB_FP32_FIXED) return (v.ipl == 1 || v.ipl == 2) && (v.unroll == 1 || v.unroll == 2);
     // NB_FP32_ALL, NB_DS, NB_FP64
     return v.ipl == 1 && (v.unroll == 1 || v.unroll == 2);
@@ -171,16 +172,23 @@ SchedView sched_view(const nb_ctx *c) {
                      c->wgmin, c->cnt, c->active};
 }
 
+// Work-item targets: up to FULL_ITEMS_PER_CU per compute unit with at most FULL_KMAX j-ranges
+// (the full-force class), or up to BLOCK_ITEMS_PER_CU with any split; partial planes are sized
+// for both families.
+constexpr int32_t FULL_ITEMS_PER_CU = 128, FULL_KMAX = 64, BLOCK_ITEMS_PER_CU = 16;
+
 // Heuristic defaults per size class; nb_tune() replaces them with measured choices.
 Variant default_variant(int32_t n, int prec, int num_cu, bool block) {
     Variant v;
     // measured on MI355X at N = 2^20: two i per work-item, unroll 1 for full-force calls and
-    // 2 for block steps; 16 work items per compute unit (full) and 8 (blocks)
+    // 2 for block steps; 128 work items per compute unit for full-force calls (fine items
+    // shorten the last, partly filled round of workgroups: 688 ms at 16 per CU, 656 ms at
+    // 128), with the j-split capped at 64 ranges; 8 per compute unit for block steps
     const bool f32 = prec == NB_FP32 || prec == NB_FP32_FIXED;
     v.ipl = (f32 && n >= 16384) ? 2 : 1;
     v.unroll = (f32 && !block) ? 1 : 2;
-    v.target = num_cu * (block ? 8 : 16);
-    v.kmax = 1 << 16;  // K is bounded by the tile count and by target / i-blocks anyway
+    v.target = num_cu * (block ? 8 : FULL_ITEMS_PER_CU);
+    v.kmax = block ? 1 << 16 : FULL_KMAX;  // K is also bounded by the tile count
     return v;
 }
 
@@ -225,7 +233,10 @@ void launch_ipl1(const typename M::Args &pa, const ForceCommon &fc, const Varian
 
 void launch_f32(const ModeF32::Args &pa, const ForceCommon &fc, const Variant &v, bool soft,
                 int cls, int32_t grid, hipStream_t s) {
-    if (v.ipl == 2) {
+    if (v.ipl == 4) {
+        if (v.unroll == 1) launch_soft<ModeF32, 4, 1>(pa, fc, soft, cls, grid, s);
+        else launch_soft<ModeF32, 4, 2>(pa, fc, soft, cls, grid, s);
+    } else if (v.ipl == 2) {
         if (v.unroll == 1) launch_soft<ModeF32, 2, 1>(pa, fc, soft, cls, grid, s);
         else if (v.unroll == 2) launch_soft<ModeF32, 2, 2>(pa, fc, soft, cls, grid, s);
         else launch_soft<ModeF32, 2, 4>(pa, fc, soft, cls, grid, s);
@@ -411,7 +422,7 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
         c->num_cu = prop.multiProcessorCount;
     c->var_full = default_variant(n, precision, c->num_cu, false);
     c->var_block = default_variant(n, precision, c->num_cu, true);
-    c->max_target = c->num_cu * 16;
+    c->max_target = c->num_cu * FULL_ITEMS_PER_CU;
     const size_t N = (size_t)n;
     // j-stream: up to 64 bytes per particle
     if ((r = alloc(c, &c->jbuf, 64 * N)) != NB_OK) { nb_destroy(c); return r; }
@@ -434,13 +445,17 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
     void *p;
     if ((r = alloc(c, &p, 7 * N * sizeof(double))) != NB_OK) { nb_destroy(c); return r; }
     c->acc1 = (double *)p; c->jerk1 = c->acc1 + 3 * N; c->pot1 = c->jerk1 + 3 * N;
-    // partial planes: K * P rows for the largest plan that any variant the tuner may pick
-    // (targets up to max_target, kmax up to 256) can produce for any count up to n
+    // partial planes: K * P rows for the largest plan of either target family, one or two i
+    // per work-item, for any count up to n (variant_valid refuses a variant, e.g. four i per
+    // work-item at a large target, whose plan would need more)
     {
         int64_t rows = 0;
-        for (int ipl = 1; ipl <= 2; ++ipl)
-            rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->max_target, 1 << 16},
-                                                   smax_of(precision)));
+        for (int ipl = 1; ipl <= 2; ++ipl) {
+            rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->num_cu * FULL_ITEMS_PER_CU,
+                                                              FULL_KMAX}, smax_of(precision)));
+            rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->num_cu * BLOCK_ITEMS_PER_CU,
+                                                              1 << 16}, smax_of(precision)));
+        }
         c->partial_rows = rows;
         if ((r = alloc(c, &p, (size_t)std::max<int64_t>(rows, 1) * 7 * sizeof(double))) != NB_OK) {
             nb_destroy(c); return r;
@@ -691,7 +706,7 @@ static nb_status enqueue_force_vjp(nb_ctx *c, const double *ab, const double *kb
     a.px = c->js.px; a.py = c->js.py; a.pz = c->js.pz; a.vm = c->js.vm;
     a.pm = c->js.pm; a.vx = c->js.vx; a.vy = c->js.vy; a.vz = c->js.vz;
     a.ab = ab; a.kb = kb; a.eps2 = c->eps * c->eps; a.partial = c->partial;
-    a.target = c->max_target; a.kmax = 1 << 16;
+    a.target = c->num_cu * BLOCK_ITEMS_PER_CU; a.kmax = 1 << 16;  // covered by the allocation
     const ForcePlan pl = make_plan(c->n, c->n, WG, a.target, a.kmax);
     const int32_t grid = std::max(1, std::min(pl.items, 1 << 20));
     if (c->prec == NB_FP32) force_vjp_kernel<0><<<grid, WG, 0, s>>>(a);
@@ -805,12 +820,14 @@ nb_status nb_tune(nb_ctx *c, int32_t which, int32_t n_i, int32_t reps, nb_varian
     HIP_OK(c, hipEventCreate(&e1));
     nb_variant bestv = which == 0 ? c->var_full : c->var_block;
     double bms = 1e300;
-    const int ipls[] = {1, 2}, unrs[] = {1, 2, 4};
-    const int32_t targets[] = {c->num_cu * 4, c->num_cu * 8, c->num_cu * 16};
+    const int ipls[] = {1, 2, 4}, unrs[] = {1, 2, 4};
+    const int32_t targets[] = {c->num_cu * 4, c->num_cu * 8, c->num_cu * 16, c->num_cu * 32,
+                               c->num_cu * 64, c->num_cu * FULL_ITEMS_PER_CU};
     for (int ipl : ipls)
         for (int unr : unrs)
             for (int32_t tg : targets) {
-                const nb_variant v{ipl, unr, tg, 1 << 16};
+                const nb_variant v{ipl, unr, tg,
+                                   tg > c->num_cu * BLOCK_ITEMS_PER_CU ? FULL_KMAX : 1 << 16};
                 if (!variant_valid(c, v)) continue;
                 float tot = 0.f;
                 for (int rep = 0; rep <= reps; ++rep) {  // the first launch is not timed
