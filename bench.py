@@ -131,8 +131,33 @@ def bench_ensemble(args):
         "roofline": {"bound": "alu", "achieved": round(60 * inter / elapsed / 1e12, 3),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(60 * inter / elapsed / 1e12 / PEAK_FP32_TFLOPS, 4),
-                     "traffic": None},
+                     "traffic": None,
+                     "basis": "60 flop per interaction over the whole run's wall clock (all "
+                              "kernels; the run is bound by the latency of its global steps)"},
     }
+    if not args.no_cpu_baseline:
+        # the oracle on the same clusters in index order, each for at most 2 s of its own block
+        # steps (or to t_end), until the time budget is spent
+        import oracle
+        spent, inter_c, done_c, desc = 0.0, 0, 0, []
+        for c, nc in enumerate(sizes):
+            nc = int(nc)
+            it = oracle.BlockIntegrator(parts[c][0], parts[c][1], parts[c][2], eps=1.0 / nc,
+                                        nu=eta, lmin=3)
+            t_a = time.perf_counter()
+            while time.perf_counter() - t_a < 2.0 and it.time < args.t_end:
+                it.step()
+            spent += time.perf_counter() - t_a
+            inter_c += nc * nc + nc * it.n_active_total
+            done_c += 1
+            desc.append(f"{nc}:{it.time:.3g}")
+            if spent > args.cpu_seconds:
+                break
+        result["cpu_baseline"] = {
+            "value": inter_c / spent, "unit": "interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"oracle on the first {done_c} clusters (N_c:time reached) "
+                      f"{' '.join(desc)}, {spent:.1f} s"}
     print(json.dumps(result), flush=True)
 
 
@@ -513,6 +538,22 @@ def bench_adjoint(args):
                                                        "v0": float(gv.norm()),
                                                        "m": float(gm.norm())}},
     }
+    if not args.no_cpu_baseline:
+        # the oracle's forward shared steps of the same run (the FP64 reference has no
+        # hand-written adjoint; its gradient checks use finite differences of this forward)
+        import oracle
+        t_a = time.perf_counter()
+        it = oracle.SharedStepIntegrator(x0, v0, m, eps, dt)
+        steps = 0
+        while time.perf_counter() - t_a < args.cpu_seconds and steps < nsteps:
+            it.step(1)
+            steps += 1
+        el = time.perf_counter() - t_a
+        result["cpu_baseline"] = {
+            "value": (steps + 1) * n * n / el, "unit": "interactions/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"oracle forward of the same run: initial force + {steps} shared steps, "
+                      f"{el:.1f} s (forward only)"}
     print(json.dumps(result), flush=True)
 
 

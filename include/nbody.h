@@ -86,7 +86,8 @@ typedef struct {
     int64_t n_steps;      /* block steps completed since nb_init()                          */
     int64_t n_active_sum; /* sum of block sizes over those steps                            */
     int32_t n_act;        /* size of the selected block                                     */
-    int32_t flags;        /* bit 0: non-finite value seen; bit 1: step clamped at 2^-lmax   */
+    int32_t flags;        /* bit 0: non-finite value seen; bit 1: step clamped at 2^-lmax;
+                             bit 2: block selection found a particle behind the block time   */
 } nb_control;
 
 /* Create a context for n particles (1 <= n <= 2^28) with Plummer softening eps >= 0, largest
@@ -149,9 +150,15 @@ nb_status nb_force(nb_ctx *ctx, const int32_t *i_idx, const int32_t *n_i, int32_
  * the time-step criterion inputs for the next nb_schedule_block(). */
 nb_status nb_correct(nb_ctx *ctx, const double *acc, const double *jerk, const double *pot);
 
-/* One whole block step, nsteps times: nb_schedule_block, nb_predict, nb_force on the block
- * (library-owned outputs), nb_correct.  With use_graph != 0 the step sequence is captured once
- * into a HIP graph and replayed. */
+/* One whole block step, nsteps times, with bitwise the result of nb_schedule_block, nb_predict,
+ * nb_force on the block (library-owned outputs) and nb_correct, in five launches: the block
+ * count fused with the predictor, the ordered block list, the force, its j-split reduction,
+ * and the corrector fused with the new levels.  Particles on one level share their time (the
+ * rules above keep t_i a multiple of dt_i), so the block time is the first multiple of the
+ * finest occupied step after the current time, read from a per-level count the step keeps on
+ * the device; a particle found behind it latches an error (NB_ESTATE at the next synchronising
+ * call).  Afterwards the block just corrected already has its new levels.  With use_graph != 0
+ * the step is captured once into a HIP graph and replayed. */
 nb_status nb_step(nb_ctx *ctx, double eta, int32_t nsteps, int32_t use_graph);
 
 /* Advance block steps until the block time would pass t_end (ticks): the scheduler selects no

@@ -36,6 +36,10 @@ struct DevControl {
     int32_t done;           // the last selection found no block at or before t_end
     int32_t flag_nonfinite; // latched: a force or corrected state was not finite
     int32_t flag_dtmin;     // latched: the criterion asked for a step below 2^-lmax
+    // fused block step
+    int32_t flag_sched;     // latched: a particle's next time preceded the block time
+    int32_t pad_;
+    int32_t hist[64];       // particles per level
 };
 
 // ------------------------------------------------------------------------------------------
@@ -838,40 +842,47 @@ __device__ __forceinline__ void predict_one(double D, double x, double v, double
     vp = __builtin_fma(D, __builtin_fma(h, k, a), v);
 }
 
+// Predict particle i to tick t and store it in the j-stream layout of MODE (0: FP32 and
+// fixed-point, 1: double-single, 2: FP64, 3: all-single).
+template <int MODE>
+__device__ __forceinline__ void predict_store(const StateView &s, const JStreamView &js, int32_t i,
+                                              int64_t t) {
+    const int32_t n = s.n;
+    const double D = (double)(t - s.tick[i]) * s.tick_len;
+    double xp[3], vp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        predict_one(D, s.x[c * (int64_t)n + i], s.v[c * (int64_t)n + i],
+                    s.a[c * (int64_t)n + i], s.k[c * (int64_t)n + i], xp[c], vp[c]);
+    const double m = s.m[i];
+    if (MODE == 0) {
+        js.px[i] = xp[0]; js.py[i] = xp[1]; js.pz[i] = xp[2];
+        js.vm[i] = make_float4((float)vp[0], (float)vp[1], (float)vp[2], (float)m);
+    } else if (MODE == 3) {
+        js.q0[i] = make_float4((float)xp[0], (float)xp[1], (float)xp[2], (float)m);
+        js.q1[i] = make_float4((float)vp[0], (float)vp[1], (float)vp[2], 0.f);
+    } else if (MODE == 1) {
+        const ds X = ds_from_double(xp[0]), Y = ds_from_double(xp[1]), Z = ds_from_double(xp[2]);
+        const ds VX = ds_from_double(vp[0]), VY = ds_from_double(vp[1]), VZ = ds_from_double(vp[2]);
+        const ds M = ds_from_double(m);
+        js.q0[i] = make_float4(X.hi, Y.hi, Z.hi, M.hi);
+        js.q1[i] = make_float4(X.lo, Y.lo, Z.lo, M.lo);
+        js.q2[i] = make_float4(VX.hi, VY.hi, VZ.hi, 0.f);
+        js.q3[i] = make_float4(VX.lo, VY.lo, VZ.lo, 0.f);
+    } else {
+        js.px[i] = xp[0]; js.py[i] = xp[1]; js.pz[i] = xp[2]; js.pm[i] = m;
+        js.vx[i] = vp[0]; js.vy[i] = vp[1]; js.vz[i] = vp[2];
+    }
+}
+
 template <int MODE>
 __global__ void __launch_bounds__(WG) predict_kernel(StateView s, JStreamView js,
                                                      const int64_t *t_ptr, const DevControl *ctl,
                                                      int32_t guard) {
     if (guard && ctl->n_act == 0) return;
     const int64_t t = t_ptr ? *t_ptr : ctl->t_next;
-    const int32_t n = s.n;
-    for (int32_t i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) {
-        const double D = (double)(t - s.tick[i]) * s.tick_len;
-        double xp[3], vp[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            predict_one(D, s.x[c * (int64_t)n + i], s.v[c * (int64_t)n + i],
-                        s.a[c * (int64_t)n + i], s.k[c * (int64_t)n + i], xp[c], vp[c]);
-        const double m = s.m[i];
-        if (MODE == 0) {
-            js.px[i] = xp[0]; js.py[i] = xp[1]; js.pz[i] = xp[2];
-            js.vm[i] = make_float4((float)vp[0], (float)vp[1], (float)vp[2], (float)m);
-        } else if (MODE == 3) {
-            js.q0[i] = make_float4((float)xp[0], (float)xp[1], (float)xp[2], (float)m);
-            js.q1[i] = make_float4((float)vp[0], (float)vp[1], (float)vp[2], 0.f);
-        } else if (MODE == 1) {
-            const ds X = ds_from_double(xp[0]), Y = ds_from_double(xp[1]), Z = ds_from_double(xp[2]);
-            const ds VX = ds_from_double(vp[0]), VY = ds_from_double(vp[1]), VZ = ds_from_double(vp[2]);
-            const ds M = ds_from_double(m);
-            js.q0[i] = make_float4(X.hi, Y.hi, Z.hi, M.hi);
-            js.q1[i] = make_float4(X.lo, Y.lo, Z.lo, M.lo);
-            js.q2[i] = make_float4(VX.hi, VY.hi, VZ.hi, 0.f);
-            js.q3[i] = make_float4(VX.lo, VY.lo, VZ.lo, 0.f);
-        } else {
-            js.px[i] = xp[0]; js.py[i] = xp[1]; js.pz[i] = xp[2]; js.pm[i] = m;
-            js.vx[i] = vp[0]; js.vy[i] = vp[1]; js.vz[i] = vp[2];
-        }
-    }
+    for (int32_t i = blockIdx.x * WG + threadIdx.x; i < s.n; i += gridDim.x * WG)
+        predict_store<MODE>(s, js, i, t);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -892,6 +903,7 @@ __global__ void __launch_bounds__(WG) reset_control(DevControl *ctl) {
         ctl->t_cur = 0; ctl->t_next = 0; ctl->t_end = INT64_MAX; ctl->n_steps = 0;
         ctl->n_active_sum = 0; ctl->n_act = 0; ctl->flags = 0; ctl->t_cand = 0;
         ctl->n_pending = 0; ctl->done = 0; ctl->flag_nonfinite = 0; ctl->flag_dtmin = 0;
+        ctl->flag_sched = 0;
     }
 }
 
@@ -1153,6 +1165,118 @@ __global__ void __launch_bounds__(WG) sched_scatter(SchedView v, DevControl *ctl
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->n_act = take ? (int32_t)total : 0;
         if (take) ctl->t_next = tc;
+        ctl->n_pending = 0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Fused block step (Sec. 2), the launch sequence of the composite step call: count + predict,
+// ordered scatter (sched_scatter), force, reduction, correct + new levels.  Particles on one
+// level share their time: the power-of-two rules keep each t_i a multiple of dt_i and every
+// particle is corrected at every multiple of its step, so t_i is the last multiple of dt_i not
+// after the current time.  The next block time is therefore the first multiple of the finest
+// occupied step after the current time, and the block is every particle with t_i + dt_i equal
+// to it.  A per-level histogram in the control record gives the finest level without a pass
+// over all particles, so one pass both counts the block members of each chunk and predicts
+// every particle; the corrector assigns the new levels at once and posts the level changes to
+// the histogram.  The block list is the same ascending list the separate calls build.
+// ------------------------------------------------------------------------------------------
+constexpr int NLEV = 64;   // levels 0 .. lmax <= 52
+
+__global__ void __launch_bounds__(WG) hist_clear(DevControl *ctl) {
+    if (blockIdx.x == 0 && threadIdx.x < NLEV) ctl->hist[threadIdx.x] = 0;
+}
+
+__global__ void __launch_bounds__(WG) hist_build(const int32_t *level, int32_t n, DevControl *ctl) {
+    __shared__ int32_t h[NLEV];
+    if (threadIdx.x < NLEV) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (int32_t i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG)
+        atomicAdd(&h[level[i] & (NLEV - 1)], 1);
+    __syncthreads();
+    if (threadIdx.x < NLEV && h[threadIdx.x] != 0) atomicAdd(&ctl->hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// One workgroup per chunk of v.chunk consecutive particles: block time from the histogram, the
+// chunk's count of block members (for sched_scatter), and the prediction of every particle.
+template <int MODE>
+__global__ void __launch_bounds__(WG) fused_count_predict(SchedView v, StateView s, JStreamView js,
+                                                          DevControl *ctl) {
+    __shared__ int64_t red[WG / 64];
+    int32_t lfine = -1;
+    for (int32_t l = v.lmax; l >= 0; --l)
+        if (ctl->hist[l] > 0) {
+            lfine = l;
+            break;
+        }
+    const int64_t dtf = lfine >= 0 ? (int64_t)1 << (v.lmax - lfine) : 1;
+    const int64_t t_next = (ctl->t_cur / dtf + 1) * dtf;
+    const bool take = lfine >= 0 && t_next <= ctl->t_end;
+    const int32_t lo = blockIdx.x * v.chunk;
+    const int32_t hi = lo + v.chunk < v.n ? lo + v.chunk : v.n;
+    int64_t c = 0;
+    if (take) {
+        for (int32_t i = lo + threadIdx.x; i < hi; i += WG) {
+            const int64_t tn = v.tick[i] + ((int64_t)1 << (v.lmax - v.level[i]));
+            if (tn < t_next) ctl->flag_sched = 1;
+            c += tn == t_next;
+            predict_store<MODE>(s, js, i, t_next);
+        }
+    }
+    c = wg_sum_i64(c, red);
+    if (threadIdx.x == 0) {
+        v.cnt[blockIdx.x] = (int32_t)c;
+        if (blockIdx.x == 0) {  // nothing else in this launch reads these two
+            ctl->t_cand = t_next;
+            ctl->done = take ? 0 : 1;
+        }
+    }
+}
+
+// Corrector of the block with the new level of each member (Eq. timestep, power-of-two
+// rules) assigned at once, and the level changes posted to the histogram.
+__global__ void __launch_bounds__(WG) fused_correct_level(StateRW s, const int32_t *active,
+                                                          const double *acc, const double *jerk,
+                                                          const double *pot, int32_t ld,
+                                                          double eta, int32_t lmin, int32_t lmax,
+                                                          DevControl *ctl) {
+    __shared__ int32_t dh[NLEV];
+    __shared__ int32_t any;
+    if (threadIdx.x < NLEV) dh[threadIdx.x] = 0;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    const int32_t n_act = ctl->n_act;
+    const int64_t t_next = ctl->t_next;
+    for (int32_t q = blockIdx.x * WG + threadIdx.x; q < n_act; q += gridDim.x * WG) {
+        const int32_t i = active[q];
+        const double dt = (double)(t_next - s.tick[i]) * s.tick_len;
+        double a1[3], k1[3], num, den;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            a1[c] = acc[c * (int64_t)ld + q];
+            k1[c] = jerk[c * (int64_t)ld + q];
+        }
+        if (!correct_particle(s, i, dt, a1, k1, pot[q], t_next, nullptr, &num, &den))
+            ctl->flag_nonfinite = 1;
+        const double dtn = den > 0.0 ? __builtin_sqrt(eta * num / den) : __builtin_inf();
+        if (__builtin_isnan(dtn)) ctl->flag_nonfinite = 1;
+        else if (dtn < s.tick_len) ctl->flag_dtmin = 1;
+        const int32_t l0 = s.level[i];
+        const int32_t l1 = next_level(dtn, l0, t_next, lmin, lmax);
+        if (l1 != l0) {
+            s.level[i] = l1;
+            atomicAdd(&dh[l0 & (NLEV - 1)], -1);
+            atomicAdd(&dh[l1 & (NLEV - 1)], 1);
+            any = 1;
+        }
+    }
+    __syncthreads();
+    if (any && threadIdx.x < NLEV && dh[threadIdx.x] != 0)
+        atomicAdd(&ctl->hist[threadIdx.x], dh[threadIdx.x]);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n_act > 0) {  // nothing in this launch reads these
+        ctl->t_cur = t_next;
+        ctl->n_steps += 1;
+        ctl->n_active_sum += n_act;
         ctl->n_pending = 0;
     }
 }

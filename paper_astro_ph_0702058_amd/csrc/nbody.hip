@@ -67,6 +67,7 @@ struct nb_ctx {
     int32_t *adj_flag = nullptr;
 
     int32_t sched_groups = 1, sched_chunk = 1;
+    int32_t fused_groups = 1, fused_chunk = 1;  // chunks of the fused step's count + predict
     Variant var_full{2, 2, 4096, 256};   // calls on (nearly) all particles
     Variant var_block{2, 2, 4096, 256};  // block-step calls (device-resident count)
     int32_t max_target = 4096;           // partial planes are sized for targets up to this
@@ -165,6 +166,11 @@ StateView state_view(const nb_ctx *c) {
 StateRW state_rw(const nb_ctx *c) {
     return StateRW{c->st.x, c->st.v, c->st.a, c->st.k, c->st.m, c->st.pot, c->st.tick,
                    c->st.level, c->n, std::ldexp(1.0, -c->lmax)};
+}
+
+SchedView fused_view(const nb_ctx *c) {
+    return SchedView{c->st.tick, c->st.level, c->n, c->lmax, c->fused_chunk, c->fused_groups,
+                     c->wgmin, c->cnt, c->active};
 }
 
 SchedView sched_view(const nb_ctx *c) {
@@ -364,14 +370,44 @@ nb_status enqueue_correct(nb_ctx *c, const double *acc, const double *jerk, cons
     return NB_OK;
 }
 
+// Before fused steps: new levels for a block left corrected by a separate nb_correct, then the
+// per-level histogram rebuilt from the bound state (levels may have been set by any call).
+nb_status enqueue_fused_prelude(nb_ctx *c, double eta, hipStream_t s) {
+    sched_newlevel<<<grid_for(c->n, 2048), WG, 0, s>>>(state_rw(c), c->active, c->crit, eta, c->lmin,
+                                                        c->lmax, c->ctl);
+    LAUNCH_OK(c);
+    hist_clear<<<1, WG, 0, s>>>(c->ctl);
+    LAUNCH_OK(c);
+    hist_build<<<grid_for(c->n, 2048), WG, 0, s>>>(c->st.level, c->n, c->ctl);
+    LAUNCH_OK(c);
+    return NB_OK;
+}
+
+// One block step as five launches: count + predict, ordered scatter, force, reduction,
+// correct + new levels.
 nb_status enqueue_step(nb_ctx *c, double eta, hipStream_t s) {
     nb_status r;
-    if ((r = enqueue_schedule(c, eta, s)) != NB_OK) return r;
-    if ((r = enqueue_predict(c, nullptr, 1, s)) != NB_OK) return r;
+    const StateView sv = state_view(c);
+    const SchedView fv = fused_view(c);
+    const int32_t g = c->fused_groups;
+    switch (c->prec) {
+        case NB_FP32:
+        case NB_FP32_FIXED: fused_count_predict<0><<<g, WG, 0, s>>>(fv, sv, c->js, c->ctl); break;
+        case NB_DS: fused_count_predict<1><<<g, WG, 0, s>>>(fv, sv, c->js, c->ctl); break;
+        case NB_FP32_ALL: fused_count_predict<3><<<g, WG, 0, s>>>(fv, sv, c->js, c->ctl); break;
+        default: fused_count_predict<2><<<g, WG, 0, s>>>(fv, sv, c->js, c->ctl); break;
+    }
+    LAUNCH_OK(c);
+    sched_scatter<<<g, WG, 0, s>>>(fv, c->ctl);
+    LAUNCH_OK(c);
     if ((r = enqueue_force(c, c->var_block, 1, c->active, &c->ctl->n_act, c->n, c->acc1, c->jerk1,
                            c->pot1, c->n, s)) != NB_OK)
         return r;
-    return enqueue_correct(c, c->acc1, c->jerk1, c->pot1, s);
+    fused_correct_level<<<grid_for(c->n, 2048), WG, 0, s>>>(state_rw(c), c->active, c->acc1, c->jerk1,
+                                                             c->pot1, c->n, eta, c->lmin, c->lmax,
+                                                             c->ctl);
+    LAUNCH_OK(c);
+    return NB_OK;
 }
 
 nb_status latched(nb_ctx *c) {
@@ -379,6 +415,8 @@ nb_status latched(nb_ctx *c) {
     HIP_OK(c, hipMemcpyAsync(&h, c->ctl, sizeof h, hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipStreamSynchronize(c->stream));
     if (h.flag_nonfinite) return fail(c, NB_ENONFINITE, "non-finite force or state on device");
+    if (h.flag_sched)
+        return fail(c, NB_ESTATE, "block selection: a particle's next time preceded the block time");
     if (h.flag_dtmin) return fail(c, NB_EDTMIN, "time step below 2^-%d requested (clamped)", c->lmax);
     return NB_OK;
 }
@@ -468,9 +506,13 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
     c->crit = (double *)p;
     c->sched_groups = (int32_t)std::min<int64_t>(std::max<int64_t>((N + 4095) / 4096, 1), 1024);
     c->sched_chunk = (int32_t)((N + c->sched_groups - 1) / c->sched_groups);
-    if ((r = alloc(c, &p, c->sched_groups * sizeof(int64_t))) != NB_OK) { nb_destroy(c); return r; }
+    // the fused step predicts while it counts: chunks of 1024 (more workgroups), up to 2048
+    c->fused_groups = (int32_t)std::min<int64_t>(std::max<int64_t>((N + 1023) / 1024, 1), 2048);
+    c->fused_chunk = (int32_t)((N + c->fused_groups - 1) / c->fused_groups);
+    const int32_t ngroups = std::max(c->sched_groups, c->fused_groups);
+    if ((r = alloc(c, &p, ngroups * sizeof(int64_t))) != NB_OK) { nb_destroy(c); return r; }
     c->wgmin = (int64_t *)p;
-    if ((r = alloc(c, &p, c->sched_groups * sizeof(int32_t))) != NB_OK) { nb_destroy(c); return r; }
+    if ((r = alloc(c, &p, ngroups * sizeof(int32_t))) != NB_OK) { nb_destroy(c); return r; }
     c->cnt = (int32_t *)p;
     if ((r = alloc(c, &p, sizeof(DevControl))) != NB_OK) { nb_destroy(c); return r; }
     c->ctl = (DevControl *)p;
@@ -604,6 +646,8 @@ nb_status nb_step(nb_ctx *c, double eta, int32_t nsteps, int32_t use_graph) {
     if ((r = need(c)) != NB_OK) return r;
     if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, NB_EINVAL, "eta must be > 0");
     if (nsteps < 0) return fail(c, NB_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return NB_OK;
+    if ((r = enqueue_fused_prelude(c, eta, c->stream)) != NB_OK) return r;
     if (!use_graph || c->profile) {  // timing events are recorded on eager launches only
         for (int32_t i = 0; i < nsteps; ++i)
             if ((r = enqueue_step(c, eta, c->stream)) != NB_OK) return r;
@@ -683,8 +727,10 @@ nb_status nb_read_control(nb_ctx *c, nb_control *out) {
     HIP_OK(c, hipStreamSynchronize(c->stream));
     out->t_cur = h.t_cur; out->t_next = h.t_next; out->t_end = h.t_end;
     out->n_steps = h.n_steps; out->n_active_sum = h.n_active_sum; out->n_act = h.n_act;
-    out->flags = (h.flag_nonfinite ? 1 : 0) | (h.flag_dtmin ? 2 : 0);
+    out->flags = (h.flag_nonfinite ? 1 : 0) | (h.flag_dtmin ? 2 : 0) | (h.flag_sched ? 4 : 0);
     if (h.flag_nonfinite) return fail(c, NB_ENONFINITE, "non-finite force or state on device");
+    if (h.flag_sched)
+        return fail(c, NB_ESTATE, "block selection: a particle's next time preceded the block time");
     if (h.flag_dtmin) return fail(c, NB_EDTMIN, "time step below 2^-%d requested (clamped)", c->lmax);
     return NB_OK;
 }

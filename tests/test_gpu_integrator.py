@@ -206,3 +206,68 @@ def test_plummer_1024_to_one_eighth(prec):
         assert c.n_steps == ref.n_steps
         assert np.sqrt(np.mean(np.sum((g["x"] - ref.x) ** 2, 1))) < 1e-8
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_fused_step_equals_separate_calls(prec):
+    """nb_step launches selection+prediction, force, reduction and correction+new levels; the
+    separate calls (nb_schedule_block, nb_predict, nb_force on nb_active's list, nb_correct)
+    select in ascending order through three passes and level in the next schedule call.  After
+    60 steps each way (and a final schedule call on the separate side to level its last block)
+    the states and the step counters are bitwise equal."""
+    import torch
+    n, eps, nu = 3000, 1 / 256, 0.01
+    states = []
+    for fused in (True, False):
+        x, v, m, st, ctx = make(n, 27, eps, prec, 3)
+        ctx.nb_init(nu)
+        if fused:
+            ctx.nb_step(nu, 60, use_graph=True)
+        else:
+            acc = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+            jerk = torch.zeros_like(acc); pot = torch.zeros(n, dtype=torch.float64, device="cuda")
+            for s in range(60):
+                if s > 0:
+                    ctx.nb_schedule_block(nu)
+                idx, cnt = ctx.nb_active()
+                ctx.nb_predict()
+                ctx.nb_force(acc, jerk, pot, i_idx=idx, n_i=cnt, n_i_max=n)
+                ctx.nb_correct(acc, jerk, pot)
+            ctx.nb_schedule_block(nu)   # levels the last block (and selects the next)
+        states.append((st.numpy(), ctx.nb_read_control()))
+        ctx.close()
+    (a, ca), (b, cb) = states
+    assert ca.n_steps == cb.n_steps == 60 and ca.t_cur == cb.t_cur
+    assert ca.n_active_sum == cb.n_active_sum
+    for key in ("x", "v", "a", "k", "pot", "tick", "level"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_fused_steps_mix_with_separate_calls():
+    """Separate calls between fused steps (a block corrected by nb_correct and not yet levelled)
+    are picked up by the next nb_step; the run follows the oracle step for step."""
+    import torch
+    n, eps, nu, lmin = 400, 1 / 64, 0.01, 4
+    x, v, m, st, ctx = make(n, 28, eps, "fp64", lmin)
+    ctx.nb_init(nu)
+    ref = oracle.BlockIntegrator(x, v, m, eps=eps, nu=nu, lmin=lmin)
+    acc = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+    jerk = torch.zeros_like(acc); pot = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for s in range(12):
+        if s % 3 == 1:     # one step through the separate calls
+            ctx.nb_schedule_block(nu)
+            idx, cnt = ctx.nb_active()
+            ctx.nb_predict()
+            ctx.nb_force(acc, jerk, pot, i_idx=idx, n_i=cnt, n_i_max=n)
+            ctx.nb_correct(acc, jerk, pot)
+        else:
+            ctx.nb_step(nu, 1, use_graph=(s % 2 == 0))
+        t, blk = ref.step()
+        c = ctx.nb_read_control()
+        assert c.t_cur == t and c.n_steps == s + 1, (s, c.t_cur, t)
+    ctx.nb_schedule_block(nu)
+    ref_level = ref.level.copy()
+    g = st.numpy()
+    assert np.array_equal(g["tick"], ref.tick) and np.array_equal(g["level"], ref_level)
+    assert np.max(np.abs(g["x"] - ref.x)) < 1e-11
+    ctx.close()
