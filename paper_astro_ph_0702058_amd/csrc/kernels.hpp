@@ -64,13 +64,15 @@ __host__ __device__ inline int32_t lane_split(int32_t n_i, bool allowed, int32_t
     return S > smax ? smax : S;
 }
 
-// ib_max: WG * (i-particles per work-item); the lane split applies when that is WG.
+// ib_max: WG * (i-particles per work-item).  Lists shorter than a workgroup take the lane
+// split whatever the variant (one i per group of S lanes), so that a short block costs work in
+// proportion to its length.
 __host__ __device__ inline ForcePlan make_plan(int32_t n_i, int32_t n, int32_t ib_max,
                                                int32_t target, int32_t kmax, int32_t smax = 64) {
     ForcePlan p;
     p.n_i = n_i;
-    p.S = lane_split(n_i, ib_max == WG, smax);
-    const int32_t ib = ib_max / p.S;
+    p.S = lane_split(n_i, true, smax);
+    const int32_t ib = p.S > 1 ? WG / p.S : ib_max;
     p.ib = ib;
     p.n_iblk = (n_i + ib - 1) / ib;
     p.ntiles = (n + TJ - 1) / TJ;
@@ -682,7 +684,7 @@ __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCom
     if (n_i <= 0) return;
     const ForcePlan pl = make_plan(n_i, fc.n, WG * IPL, fc.target, fc.kmax, fc.smax);
     const auto eps2 = pa.eps2;
-    if (IPL == 1 && pl.S > 1) {
+    if (pl.S > 1) {
         force_items_split<M, UNR, SOFT>(pa, fc, pl, sm, n_i, eps2);
         return;
     }
