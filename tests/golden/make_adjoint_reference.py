@@ -1,0 +1,57 @@
+"""Write tests/golden/adjoint_fd.json: central finite differences of the FP64 oracle for the
+differentiable shared-step workload at its full size, at 32 sampled coordinates.
+
+Workload: Plummer N = 16384 (seed 5), eps = 1/128, 64 shared Hermite steps of dt = 1/1024.
+Target: the final positions of the oracle's run from the same initial conditions with every
+coordinate of x and v perturbed by N(0, 1e-3^2) (seed 6).  Loss: mean over particles of
+|x_i(T) - target_i|^2.  Derivatives with respect to 12 initial position coordinates, 12 initial
+velocity coordinates and 8 masses (seeded samples), steps as in oracle.fd_gradient.  Calls only
+the oracle and the seeded input generator.
+
+    python tests/golden/make_adjoint_reference.py
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from paper_astro_ph_0702058_amd.plummer import perturb, plummer, sample_indices  # noqa: E402
+
+N, SEED, EPS, DT, NSTEPS = 16384, 5, 1.0 / 128, 2.0 ** -10, 64
+
+
+def coords():
+    out = []
+    for kind, count, seed in (("x", 12, 50), ("v", 12, 51), ("m", 8, 52)):
+        for k, i in enumerate(sample_indices(N, count, seed)):
+            out.append((kind, int(i), 0 if kind == "m" else k % 3))
+    return out
+
+
+def main():
+    t0 = time.time()
+    x0, v0, m = plummer(N, SEED)
+    xp, vp = perturb(x0, v0, 1e-3, 6)
+    target, _ = oracle.shared_run(xp, vp, m, EPS, DT, NSTEPS)
+    xf, _ = oracle.shared_run(x0, v0, m, EPS, DT, NSTEPS)
+    loss = oracle.mean_sq_distance(xf, target)
+    cs = coords()
+    fd = oracle.fd_gradient(x0, v0, m, EPS, DT, NSTEPS, target, cs)
+    out = dict(params=dict(n=N, seed=SEED, eps=EPS, dt=DT, nsteps=NSTEPS, target_seed=6,
+                           target_sigma=1e-3),
+               loss=loss, target_sum=float(np.sum(target)), coords=cs, fd=fd.tolist(),
+               seconds=time.time() - t0, threads=oracle.num_threads())
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "adjoint_fd.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print("loss", loss, "seconds", out["seconds"], flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -125,3 +125,37 @@ def test_run_gradient_against_oracle_finite_differences(prec, tol):
     err = np.abs(got - fd) / scale
     print(f"{prec}: max rel err {err.max():.2e}", flush=True)
     assert err.max() <= tol, (err.max(), coords[int(np.argmax(err))])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-4), ("fp32", 2e-3)])
+def test_full_size_gradient_against_committed_finite_differences(prec, tol):
+    """The differentiable workload at full size: Plummer N = 16384, eps = 1/128, 64 shared steps
+    of 1/1024, checkpoints every 8, loss = mean |x(T) - target|^2.  The GPU gradient at 32 sampled
+    coordinates against the oracle's central finite differences committed in
+    tests/golden/adjoint_fd.json (make_adjoint_reference.py).  The target is the GPU's FP64 run
+    from the same perturbed initial conditions; it matches the oracle's (the stored coordinate
+    sum to 1e-7, the loss to 1e-9 relative in FP64).  Tolerances as for the small case."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_fd.json")
+    if not os.path.exists(path):
+        pytest.skip("the oracle finite differences have not been written")
+    g = json.load(open(path))
+    p = g["params"]
+    n, eps, dt, nsteps = p["n"], p["eps"], p["dt"], p["nsteps"]
+    x0, v0, m = plummer(n, p["seed"])
+    xp_, vp_ = perturb(x0, v0, p["target_sigma"], p["target_seed"])
+    runner = SharedRunner(n, eps, dt, nsteps, checkpoint_every=8, precision="fp64")
+    with torch.no_grad():
+        tx, _ = HermiteRun.apply(soa(xp_), soa(vp_), torch.tensor(m, device="cuda"), runner)
+    target = tx.cpu().numpy().T.copy()
+    assert abs(float(target.sum()) - g["target_sum"]) <= 1e-7
+    loss, gx, gv, gm, xf = gpu_grad(x0, v0, m, target, eps, dt, nsteps, 8, prec)
+    assert abs(loss - g["loss"]) <= (1e-9 if prec == "fp64" else 1e-5) * g["loss"]
+    coords = [tuple(c) for c in g["coords"]]
+    fd = np.array(g["fd"])
+    got = np.array([{"x": gx, "v": gv}[k][i, c] if k != "m" else gm[i] for k, i, c in coords])
+    scale = np.maximum(np.abs(fd), 1e-3 * np.max(np.abs(fd)))
+    err = np.abs(got - fd) / scale
+    print(f"{prec} N={n}: max rel err {err.max():.2e} over {len(coords)} coordinates", flush=True)
+    assert err.max() <= tol, (err.max(), coords[int(np.argmax(err))])
