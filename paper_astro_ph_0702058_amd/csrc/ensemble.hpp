@@ -82,6 +82,7 @@ __device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t *red) {
 }
 
 constexpr int WGL = 1024;  // workgroup of the cluster-local kernel
+constexpr int TN_CACHE = 4096;  // clusters up to this size keep t_i + dt_i in LDS for selection
 
 // One workgroup of WGL per cluster.
 //   phase 0: start of run -- block = every particle, times 0, block time 0
@@ -95,6 +96,7 @@ __global__ void __launch_bounds__(WGL) ens_local(EnsView e, StateRW s, double et
                                                  int32_t phase) {
     __shared__ int64_t red[WGL / 64];
     __shared__ int32_t wsum[WGL / 64];
+    __shared__ int64_t tn_lds[TN_CACHE];
     const int32_t c = blockIdx.x;
     if (c >= e.C) return;
     const int32_t lo = e.off[c], hi = e.off[c + 1];
@@ -120,15 +122,14 @@ __global__ void __launch_bounds__(WGL) ens_local(EnsView e, StateRW s, double et
         double o[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         const double *src = pbase + q;
         int32_t j = 0;
-        for (; j + 2 <= K; j += 2) {
-            double v0[7], v1[7];
+        for (; j + 4 <= K; j += 4) {  // four planes' loads in flight, added in plane order
+            double v[4][7];
 #pragma unroll
-            for (int k = 0; k < 7; ++k) {
-                v0[k] = src[j * stride + (int64_t)k * P];
-                v1[k] = src[(j + 1) * stride + (int64_t)k * P];
-            }
+            for (int r = 0; r < 4; ++r)
 #pragma unroll
-            for (int k = 0; k < 7; ++k) o[k] = (o[k] + v0[k]) + v1[k];
+                for (int k = 0; k < 7; ++k) v[r][k] = src[(j + r) * stride + (int64_t)k * P];
+#pragma unroll
+            for (int k = 0; k < 7; ++k) o[k] = (((o[k] + v[0][k]) + v[1][k]) + v[2][k]) + v[3][k];
         }
         for (; j < K; ++j) {
 #pragma unroll
@@ -169,22 +170,41 @@ __global__ void __launch_bounds__(WGL) ens_local(EnsView e, StateRW s, double et
         cl->n_steps += 1;
         cl->n_active_sum += n_act;
     }
-    // next block of this cluster
+    // next block of this cluster; clusters of up to TN_CACHE particles keep t_i + dt_i in LDS
+    // for the compaction (the loads of four particles per work-item are issued together)
+    const int32_t lmax = e.lmax;
+    const bool cached = hi - lo <= TN_CACHE;
     int64_t m = INT64_MAX;
-    for (int32_t i = lo + threadIdx.x; i < hi; i += WGL) {
-        const int64_t tn = s.tick[i] + ((int64_t)1 << (e.lmax - s.level[i]));
-        m = tn < m ? tn : m;
+    if (cached) {
+        int64_t tn[TN_CACHE / WGL];
+#pragma unroll
+        for (int r = 0; r < TN_CACHE / WGL; ++r) {
+            const int32_t i = lo + threadIdx.x + r * WGL;
+            tn[r] = i < hi ? s.tick[i] + ((int64_t)1 << (lmax - s.level[i])) : INT64_MAX;
+        }
+#pragma unroll
+        for (int r = 0; r < TN_CACHE / WGL; ++r) {
+            tn_lds[threadIdx.x + r * WGL] = tn[r];
+            m = tn[r] < m ? tn[r] : m;
+        }
+    } else {
+        for (int32_t i = lo + threadIdx.x; i < hi; i += WGL) {
+            const int64_t tn = s.tick[i] + ((int64_t)1 << (lmax - s.level[i]));
+            m = tn < m ? tn : m;
+        }
     }
-    const int64_t tn_min = block_min_i64<WGL>(m, red);
+    const int64_t tn_min = block_min_i64<WGL>(m, red);  // its barriers also publish tn_lds
     if (tn_min > e.t_end) {
         if (threadIdx.x == 0) { cl->done = 1; cl->n_act = 0; }
         return;
     }
-    const int32_t lmax = e.lmax;
-    const int32_t na = wg_compact<WGL>(
-        lo, hi,
-        [&](int32_t i) { return s.tick[i] + ((int64_t)1 << (lmax - s.level[i])) == tn_min; },
-        e.active + lo, wsum);
+    const int32_t na = cached
+        ? wg_compact<WGL>(lo, hi, [&](int32_t i) { return tn_lds[i - lo] == tn_min; },
+                          e.active + lo, wsum)
+        : wg_compact<WGL>(
+              lo, hi,
+              [&](int32_t i) { return s.tick[i] + ((int64_t)1 << (lmax - s.level[i])) == tn_min; },
+              e.active + lo, wsum);
     if (threadIdx.x == 0) {
         cl->t_next = tn_min;
         cl->n_act = na;
