@@ -80,6 +80,9 @@ def main(argv=None):
     b.add_argument("--algorithmic-bytes", type=float, required=True)
     b.add_argument("--cmd-fetch", required=True); b.add_argument("--cmd-write", required=True)
     c = sub.add_parser("counters"); c.add_argument("csv"); c.add_argument("--kernel", required=True)
+    c.add_argument("--interactions", type=float,
+                   help="interactions per dispatch: also print per-interaction figures")
+    c.add_argument("--ms", type=float, help="dispatch duration (ms) for the rates")
     args = ap.parse_args(argv)
     if args.what == "stats":
         print(stats(args.csv, args.cmd))
@@ -101,8 +104,25 @@ def main(argv=None):
                 json.dump(doc, f, indent=1)
         print(json.dumps(doc, indent=1))
     else:
-        for k, v in sorted(counters(args.csv, args.kernel).items()):
+        m = counters(args.csv, args.kernel)
+        for k, v in sorted(m.items()):
             print(f"{k:32s} {v:.6g}")
+        if args.interactions:
+            n2 = args.interactions
+            per = lambda k: m.get(k, 0.0) * 64 / n2   # wave-level counts x 64 lanes
+            print("\n# derived (wave-level counts x 64 lanes / interactions):")
+            print(f"VALU instructions per interaction      {per('SQ_INSTS_VALU'):.2f}")
+            print(f"v_rsq_f32 per interaction              {per('SQ_INSTS_VALU_TRANS_F32'):.3f}")
+            print(f"hardware-counted FP32 flop/interaction {per('SQ_INSTS_VALU_FLOPS_FP32'):.2f}"
+                  "   (FMA = 2; the paper's convention counts 60)")
+            print(f"LDS instructions per interaction       {per('SQ_INSTS_LDS'):.3f}")
+            if args.ms:
+                t = args.ms * 1e-3
+                print(f"hardware-counted FP32 rate             "
+                      f"{per('SQ_INSTS_VALU_FLOPS_FP32') * n2 / t / 1e12:.1f} TFLOP/s at {args.ms:.2f} ms")
+                print(f"60-flop-convention rate                {60 * n2 / t / 1e12:.1f} TFLOP/s = "
+                      f"{100 * 60 * n2 / t / 157.3e12:.1f}% of 157.3")
+                print(f"VALU lane-instructions per second      {per('SQ_INSTS_VALU') * n2 / t:.3e}")
 
 
 if __name__ == "__main__":
