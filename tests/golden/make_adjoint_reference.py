@@ -5,10 +5,13 @@ Workload: Plummer N = 16384 (seed 5), eps = 1/128, 64 shared Hermite steps of dt
 Target: the final positions of the oracle's run from the same initial conditions with every
 coordinate of x and v perturbed by N(0, 1e-3^2) (seed 6).  Loss: mean over particles of
 |x_i(T) - target_i|^2.  Derivatives with respect to 12 initial position coordinates, 12 initial
-velocity coordinates and 8 masses (seeded samples), steps as in oracle.fd_gradient.  Calls only
-the oracle and the seeded input generator.
+velocity coordinates and 8 masses (seeded samples), steps as in oracle.fd_gradient.  With
+--refine-masses the mass derivatives are evaluated again at half the step and the Richardson
+value (4 D(h/2) - D(h)) / 3 is stored beside them: a mass is varied by a relative step of 1e-3,
+so the central difference's own truncation error can matter for the smallest mass derivatives.
+Calls only the oracle and the seeded input generator.
 
-    python tests/golden/make_adjoint_reference.py
+    python tests/golden/make_adjoint_reference.py [--refine-masses]
 """
 import json
 import os
@@ -34,7 +37,31 @@ def coords():
     return out
 
 
+def refine_masses(path):
+    g = json.load(open(path))
+    t0 = time.time()
+    x0, v0, m = plummer(N, SEED)
+    xp, vp = perturb(x0, v0, 1e-3, 6)
+    target, _ = oracle.shared_run(xp, vp, m, EPS, DT, NSTEPS)
+    cs = [tuple(c) for c in g["coords"]]
+    sel = [k for k, c in enumerate(cs) if c[0] == "m"]
+    half = oracle.fd_gradient(x0, v0, m, EPS, DT, NSTEPS, target, [cs[k] for k in sel],
+                              rel_h_mass=0.5e-3)
+    g["fd_half"] = [None] * len(cs)
+    g["fd_richardson"] = [None] * len(cs)
+    for k, d in zip(sel, half):
+        g["fd_half"][k] = float(d)
+        g["fd_richardson"][k] = (4.0 * float(d) - g["fd"][k]) / 3.0
+    g["seconds_refine"] = time.time() - t0
+    with open(path, "w") as f:
+        json.dump(g, f, indent=1)
+    print("refined", len(sel), "mass derivatives", g["seconds_refine"], flush=True)
+
+
 def main():
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "adjoint_fd.json")
+    if "--refine-masses" in sys.argv[1:]:
+        return refine_masses(path)
     t0 = time.time()
     x0, v0, m = plummer(N, SEED)
     xp, vp = perturb(x0, v0, 1e-3, 6)
@@ -47,7 +74,6 @@ def main():
                            target_sigma=1e-3),
                loss=loss, target_sum=float(np.sum(target)), coords=cs, fd=fd.tolist(),
                seconds=time.time() - t0, threads=oracle.num_threads())
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "adjoint_fd.json")
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print("loss", loss, "seconds", out["seconds"], flush=True)

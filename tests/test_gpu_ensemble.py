@@ -100,3 +100,51 @@ def test_ensemble_fp32_log_uniform_sizes():
           (np.median(de32), de32.max(), np.median(de64), de64.max()), flush=True)
     assert np.all(de32 <= 10 * de64 + 1e-6), np.max(de32 / (10 * de64 + 1e-6))
     assert np.all(np.abs(st32 - st64) <= 0.1 * st64)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_ensemble_against_committed_oracle_runs(prec):
+    """The batched workload at full size: 512 Plummer clusters, N_c log-uniform in [64, 4096]
+    (551629 particles), eps = 1/N_c, eta = 0.02, every cluster to t = 1, against the FP64 oracle
+    run of each cluster committed in tests/golden/ensemble_runs.json (make_ensemble_reference.py).
+    FP64 interaction: every cluster takes exactly the oracle's block steps (count and particle
+    steps) and its energy error agrees to 1e-12.  FP32: each cluster's block steps within 1 %,
+    the particle steps of the whole run within 0.1 %, and the energy error, set by the
+    integrator at this eta (median 1.2e-7), within a factor 4 of the oracle's plus 1e-8 for
+    every cluster, with the median ratio within 10 % of 1."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ensemble_runs.json")
+    if not os.path.exists(path):
+        pytest.skip("the oracle ensemble runs have not been written")
+    g = json.load(open(path))
+    p = g["params"]
+    sizes = ensemble_sizes(p["clusters"], p["size_seed"])
+    parts = [plummer(int(nc), p["seed0"] + c) for c, nc in enumerate(sizes)]
+    st = nbody.DeviceState(np.concatenate([q[0] for q in parts]), np.concatenate([q[1] for q in parts]),
+                           np.concatenate([q[2] for q in parts]))
+    ens = nbody.Ensemble(sizes, 1.0 / sizes, lmin=p["lmin"], lmax=LMAX, precision=prec)
+    ens.nb_ens_bind(st)
+    ens.nb_ens_init(p["eta"])
+    ek0, ep0 = ens.nb_ens_energy()
+    ens.nb_ens_run(p["eta"], p["t_end"], steps_per_launch=32)
+    ctl = ens.nb_ens_control()
+    ek1, ep1 = ens.nb_ens_energy()
+    ens.close()
+    ref = g["clusters"]
+    steps = np.array([c.n_steps for c in ctl]); rsteps = np.array([r["n_steps"] for r in ref])
+    act = np.array([c.n_active_sum for c in ctl]); ract = np.array([r["n_active_sum"] for r in ref])
+    de = (ek1 + ep1 - ek0 - ep0) / (ek0 + ep0)
+    rde = np.array([(r["energy1"] - r["energy0"]) / r["energy0"] for r in ref])
+    assert np.all([c.t_cur == 1 << LMAX for c in ctl]) and np.all([c.flags == 1 for c in ctl])
+    print(f"{prec}: {np.sum(steps == rsteps)} of {len(ref)} clusters with the oracle's step count; "
+          f"max |ddE/E| {np.max(np.abs(de - rde)):.2e}", flush=True)
+    if prec == "fp64":
+        assert np.array_equal(steps, rsteps) and np.array_equal(act, ract)
+        assert np.max(np.abs(de - rde)) <= 1e-12
+    else:
+        assert np.max(np.abs(steps - rsteps) / rsteps) <= 0.01
+        assert abs(act.sum() / ract.sum() - 1.0) <= 1e-3
+        assert np.all(np.abs(de) <= 4 * np.abs(rde) + 1e-8)
+        ratio = np.abs(de) / np.maximum(np.abs(rde), 1e-300)
+        assert abs(np.median(ratio) - 1.0) <= 0.1
