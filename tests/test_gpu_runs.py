@@ -39,20 +39,20 @@ TOL = {"fp32": (2e-6, 1e-5, 2e-6), "ds": (1e-11, 1e-10, 1e-11), "fp64": (1e-13, 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plummer_runs.json")
 
 
-def term_magnitude_sums(xp, vp, m, rows):
+def term_magnitude_sums(xp, vp, m, rows, eps=EPS, chunk=32):
     """sum_j |a_ij| and sum_j |k_ij| over j != i for the listed i (FP64, chunks of rows)."""
     sa = np.empty(len(rows)); sk = np.empty(len(rows))
-    for c0 in range(0, len(rows), 32):
-        r = rows[c0:c0 + 32]
+    for c0 in range(0, len(rows), chunk):
+        r = rows[c0:c0 + chunk]
         d = xp[None, :, :] - xp[r][:, None, :]
         u = vp[None, :, :] - vp[r][:, None, :]
-        s = np.sum(d * d, axis=2) + EPS * EPS
+        s = np.sum(d * d, axis=2) + eps * eps
         s[np.arange(len(r)), r] = np.inf          # drop j = i
         w3 = m[None, :] * s ** -1.5
         rv = np.sum(d * u, axis=2)
-        sa[c0:c0 + 32] = np.sum(w3 * np.linalg.norm(d, axis=2), axis=1)
+        sa[c0:c0 + chunk] = np.sum(w3 * np.linalg.norm(d, axis=2), axis=1)
         kv = w3[:, :, None] * (u - 3.0 * (rv / s)[:, :, None] * d)
-        sk[c0:c0 + 32] = np.sum(np.linalg.norm(kv, axis=2), axis=1)
+        sk[c0:c0 + chunk] = np.sum(np.linalg.norm(kv, axis=2), axis=1)
     return sa, sk
 
 
@@ -160,3 +160,52 @@ def test_run_to_t1_against_oracle_run(prec):
     assert abs(c.n_active_sum - ref["n_active_sum"]) <= 0.05 * ref["n_active_sum"]
     assert abs(c.n_steps - ref["n_steps"]) <= 0.25 * ref["n_steps"]
     assert abs(de) <= 10 * abs(ref["de_rel"])
+
+
+def test_block_forces_at_full_size():
+    """The headline workload (Plummer N = 2^20, seed 3, eps = 1/256, nu = 0.01, dt <= 1/8),
+    single precision: block forces at the 4th block step and at the block of t = 1/64 against
+    the oracle at the device's predicted state, on up to 256 sampled block members (the same
+    error measures and tolerances as above)."""
+    import torch
+    n, eps = 1 << 20, 1 / 256
+    x, v, m = plummer(n, 3)
+    st = nbody.DeviceState(x, v, m)
+    acc = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+    jerk = torch.zeros_like(acc)
+    pot = torch.zeros(n, dtype=torch.float64, device="cuda")
+    with nbody.Context(n, eps, lmin=LMIN, lmax=LMAX, precision="fp32") as ctx:
+        ctx.nb_bind(st)
+        ctx.nb_init(NU)
+        for kind, where in (("steps", 4), ("time", 1 / 64)):
+            if kind == "steps":
+                ctx.nb_step(NU, where, use_graph=True)
+            else:
+                ctx.nb_run(NU, where - 2.0 ** -LMAX, chunk=256)
+            ctx.nb_schedule_block(NU)
+            c = ctx.nb_read_control()
+            g = st.numpy()
+            idx_addr, cnt_addr = ctx.nb_active()
+            blk = nbody.read_device_int32(idx_addr, c.n_act).astype(np.int64)
+            ctx.nb_predict()
+            ctx.nb_force(acc, jerk, pot, i_idx=idx_addr, n_i=cnt_addr, n_i_max=n)
+            ctx.nb_correct(acc, jerk, pot)
+            ctx.nb_sync()
+            rows = np.sort(sample_indices(c.n_act, min(256, c.n_act), 60 + c.n_act))
+            ga = acc[:, :c.n_act].cpu().numpy().T[rows]
+            gk = jerk[:, :c.n_act].cpu().numpy().T[rows]
+            gp = pot[:c.n_act].cpu().numpy()[rows]
+            xp, vp = oracle.predict(g["x"], g["v"], g["a"], g["k"], g["tick"], c.t_next, LMAX)
+            ra, rk, rp = oracle.force(xp, vp, m, eps * eps, idx=blk[rows])
+            ea, ek, ep = rms_rel(ga, ra), rms_rel(gk, rk), rms_rel(gp, rp)
+            k64 = slice(0, min(64, len(rows)))
+            sa, sk = term_magnitude_sums(xp, vp, m, blk[rows][k64], eps=eps, chunk=4)
+            ea_s = float(np.sqrt(np.mean(np.sum((ga[k64] - ra[k64]) ** 2, 1) / sa ** 2)))
+            ek_s = float(np.sqrt(np.mean(np.sum((gk[k64] - rk[k64]) ** 2, 1) / sk ** 2)))
+            print(f"N=2^20 {kind} {where:g}: n_act={c.n_act} e_acc={ea:.3e} e_jerk={ek:.3e} "
+                  f"e_pot={ep:.3e}; scaled (64 rows) e_acc={ea_s:.3e} e_jerk={ek_s:.3e}", flush=True)
+            ta, tk, tp = TOL["fp32"]
+            assert ep <= tp and ea_s <= ta and ek_s <= tk
+            if kind == "time":
+                assert c.t_next == int(where * 2 ** LMAX)
+                assert ea <= ta and ek <= tk
