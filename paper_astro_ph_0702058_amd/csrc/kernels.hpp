@@ -745,8 +745,9 @@ __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCom
 
 // Fixed-order sum over the K partial planes (deterministic; no atomics).
 // One workgroup per (64 consecutive i-rows, one of the 7 sums): wave w adds the planes
-// k = w, w + RW, w + 2 RW, ... and the RW wave sums are then added in wave order, so the result
-// depends only on K, never on timing.  Consecutive lanes read consecutive rows of a plane.
+// k = w, w + RW, w + 2 RW, ... (in four interleaved partial sums, so that four loads are in
+// flight) and the RW wave sums are then added in wave order, so the result depends only on K,
+// never on timing.  Consecutive lanes read consecutive rows of a plane.
 constexpr int RW = 16;               // waves per reduce workgroup
 constexpr int WG_REDUCE = 64 * RW;
 
@@ -784,10 +785,19 @@ __global__ void __launch_bounds__(WG_REDUCE) force_reduce(ForceCommon fc, int32_
             ipart[w][lane] = s;
             ibad[w][lane] = bad;
         } else {
-            double s = 0.0;
-            if (q < n_i)
-                for (int32_t k = w; k < pl.K; k += RW) s += src[(int64_t)k * 7 * pl.P];
-            part[w][lane] = s;
+            // four planes in flight per lane: planes k = w + RW (4 m + r) go to sum r, and the
+            // four sums are added in the order 0..3 (the order depends only on K)
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            if (q < n_i) {
+                const int64_t st = (int64_t)RW * 7 * pl.P;
+                int32_t k = w;
+                for (; k + 3 * RW < pl.K; k += 4 * RW) {
+                    const double *b = src + (int64_t)k * 7 * pl.P;
+                    s0 += b[0]; s1 += b[st]; s2 += b[2 * st]; s3 += b[3 * st];
+                }
+                for (; k < pl.K; k += RW) s0 += src[(int64_t)k * 7 * pl.P];
+            }
+            part[w][lane] = ((s0 + s1) + s2) + s3;
         }
         __syncthreads();
         if (w == 0 && q < n_i) {
