@@ -271,3 +271,56 @@ def test_fused_steps_mix_with_separate_calls():
     assert np.array_equal(g["tick"], ref.tick) and np.array_equal(g["level"], ref_level)
     assert np.max(np.abs(g["x"] - ref.x)) < 1e-11
     ctx.close()
+
+
+def test_step_floor_is_clamped_reported_and_matches_oracle():
+    """Steps are confined to [2^-lmax, 2^-lmin]; with lmax = 9 the criterion asks for less
+    (the oracle counts 421 such requests in the first 40 block steps of this sphere).  The
+    library clamps (as the oracle does), keeps integrating, and reports
+    NB_EDTMIN at the next synchronising call; with allow_dtmin the call records it instead.
+    In FP64 the clamped run follows the oracle's clamped run step for step."""
+    n, eps, nu, lmin, lmax = 300, 1e-4, 0.01, 3, 9
+    x, v, m = plummer(n, 29)
+    st = nbody.DeviceState(x, v, m)
+    ref = oracle.BlockIntegrator(x, v, m, eps=eps, nu=nu, lmin=lmin, lmax=lmax)
+    with nbody.Context(n, eps, lmin=lmin, lmax=lmax, precision="fp64") as ctx:
+        ctx.nb_bind(st)
+        ctx.nb_init(nu)
+        for s in range(40):
+            ctx.nb_step(nu, 1, use_graph=False)
+            ref.step()
+        with pytest.raises(nbody.NBodyError) as e:
+            ctx.nb_read_control()
+        assert e.value.status == nbody.NB_EDTMIN
+    assert ref.n_dtmin > 0
+    g = st.numpy()
+    assert np.array_equal(g["tick"], ref.tick) and np.array_equal(g["level"], ref.level)
+    assert np.max(np.abs(g["x"] - ref.x)) < 1e-10
+    st2 = nbody.DeviceState(x, v, m)
+    with nbody.Context(n, eps, lmin=lmin, lmax=lmax, precision="fp64", allow_dtmin=True) as ctx:
+        ctx.nb_bind(st2)
+        ctx.nb_init(nu)
+        ctx.nb_step(nu, 40, use_graph=True)
+        c = ctx.nb_read_control()
+        assert ctx.dtmin_clamped and (c.flags & 2) and c.n_steps == 40
+
+
+def test_fused_step_reports_a_particle_behind_the_block_time():
+    """The fused step takes the block time from the per-level counts, which is right while every
+    particle's t_i is the last multiple of its step (the scheduling rules keep it so).  A state
+    edited from the host to break that (one particle moved back to t = 0 on the finest level)
+    is reported as NB_ESTATE; the kernels finish normally."""
+    import torch
+    n, eps, nu = 500, 1 / 256, 0.01
+    x, v, m, st, ctx = make(n, 30, eps, "fp64", 3)
+    ctx.nb_init(nu)
+    ctx.nb_step(nu, 5, use_graph=False)
+    c = ctx.nb_read_control()
+    assert c.t_cur > 1
+    st.tick[7] = 0
+    st.level[7] = LMAX           # next time 1 tick: behind the block time
+    ctx.nb_step(nu, 1, use_graph=False)
+    with pytest.raises(nbody.NBodyError) as e:
+        ctx.nb_sync()
+    assert e.value.status == nbody.NB_ESTATE
+    ctx.close()
