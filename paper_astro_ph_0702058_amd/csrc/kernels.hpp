@@ -19,7 +19,7 @@
 namespace nbody {
 
 constexpr int WG = 256;      // work-items per workgroup
-constexpr int TJ = 256;      // j-particles per LDS tile (one staged per work-item)
+constexpr int TJ = 256;      // j-particles per tile (LDS tile of the lane split; fold interval)
 
 // Device-side scheduler record.  The first 48 bytes mirror nb_control of the C ABI.
 struct DevControl {
@@ -106,6 +106,19 @@ struct Out7 {
     double v[7];
 };
 
+// Wave-uniform reads of j-records: on the whole-block path every lane of a wave takes the same
+// j at the same time, so the record is read once per wave through the scalar data cache into
+// scalar registers, which the vector instructions take as operands (the j-stream is read-only
+// while a force launch runs).
+typedef float f4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ double uload(const double *p, int j) {
+    return ((const __attribute__((address_space(4))) double *)p)[j];
+}
+__device__ __forceinline__ float4 uload(const float4 *p, int j) {
+    const f4v q = ((const __attribute__((address_space(4))) f4v *)p)[j];
+    return make_float4(q.x, q.y, q.z, q.w);
+}
+
 // ------------------------------------------------------------------------------------------
 // FP32 interaction: separations from FP64 positions (one rounding), float arithmetic, tile
 // sums in float folded into double sums once per tile.
@@ -153,13 +166,24 @@ struct ModeF32 {
         s.vm[t] = make_float4((float)vp[0], (float)vp[1], (float)vp[2], (float)m);
     }
 
+    struct J {  // one j-record
+        double x, y, z;
+        float4 q;
+    };
+    __device__ static __forceinline__ J load_j(const Args &a, int j) {
+        return J{uload(a.px, j), uload(a.py, j), uload(a.pz, j), uload(a.vm, j)};
+    }
     template <bool SOFT>
     __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, float eps2,
                                                     Tile &T) {
-        const float dx = (float)(s.x[jj] - i.x);
-        const float dy = (float)(s.y[jj] - i.y);
-        const float dz = (float)(s.z[jj] - i.z);
-        const float4 q = s.vm[jj];
+        pair<SOFT>(i, J{s.x[jj], s.y[jj], s.z[jj], s.vm[jj]}, eps2, T);
+    }
+    template <bool SOFT>
+    __device__ static __forceinline__ void pair(const I &i, const J &j, float eps2, Tile &T) {
+        const float dx = (float)(j.x - i.x);
+        const float dy = (float)(j.y - i.y);
+        const float dz = (float)(j.z - i.z);
+        const float4 q = j.q;
         const float ux = q.x - i.vx;
         const float uy = q.y - i.vy;
         const float uz = q.z - i.vz;
@@ -247,10 +271,20 @@ struct ModeF32All {
         s.vv[t] = make_float4((float)vp[0], (float)vp[1], (float)vp[2], 0.f);
     }
 
+    struct J {
+        float4 pm, vv;
+    };
+    __device__ static __forceinline__ J load_j(const Args &a, int j) {
+        return J{uload(a.pm, j), uload(a.vv, j)};
+    }
     template <bool SOFT>
     __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, float eps2,
                                                     Tile &T) {
-        const float4 q = s.pm[jj], w = s.vv[jj];
+        pair<SOFT>(i, J{s.pm[jj], s.vv[jj]}, eps2, T);
+    }
+    template <bool SOFT>
+    __device__ static __forceinline__ void pair(const I &i, const J &j, float eps2, Tile &T) {
+        const float4 q = j.pm, w = j.vv;
         const float dx = q.x - i.x, dy = q.y - i.y, dz = q.z - i.z;
         const float ux = w.x - i.vx, uy = w.y - i.vy, uz = w.z - i.vz;
         const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, eps2)));
@@ -418,10 +452,20 @@ struct ModeDS {
         s.q3[t] = make_float4(VX.lo, VY.lo, VZ.lo, 0.f);
     }
 
+    struct J {
+        float4 h, l, vh, vl;
+    };
+    __device__ static __forceinline__ J load_j(const Args &a, int j) {
+        return J{uload(a.q0, j), uload(a.q1, j), uload(a.q2, j), uload(a.q3, j)};
+    }
     template <bool SOFT>
     __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, ds eps2,
                                                     Tile &T) {
-        const float4 h = s.q0[jj], l = s.q1[jj], vh = s.q2[jj], vl = s.q3[jj];
+        pair<SOFT>(i, J{s.q0[jj], s.q1[jj], s.q2[jj], s.q3[jj]}, eps2, T);
+    }
+    template <bool SOFT>
+    __device__ static __forceinline__ void pair(const I &i, const J &j, ds eps2, Tile &T) {
+        const float4 h = j.h, l = j.l, vh = j.vh, vl = j.vl;
         const ds dx = ds_sub(ds{h.x, l.x}, i.x);
         const ds dy = ds_sub(ds{h.y, l.y}, i.y);
         const ds dz = ds_sub(ds{h.z, l.z}, i.z);
@@ -523,17 +567,28 @@ struct ModeF64 {
         s.vx[t] = vp[0]; s.vy[t] = vp[1]; s.vz[t] = vp[2];
     }
 
+    struct J {
+        double x, y, z, m, vx, vy, vz;
+    };
+    __device__ static __forceinline__ J load_j(const Args &a, int j) {
+        return J{uload(a.px, j), uload(a.py, j), uload(a.pz, j), uload(a.pm, j),
+                 uload(a.vx, j), uload(a.vy, j), uload(a.vz, j)};
+    }
     template <bool SOFT>
     __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, double eps2,
                                                     Tile &T) {
-        const double dx = s.x[jj] - i.x, dy = s.y[jj] - i.y, dz = s.z[jj] - i.z;
-        const double ux = s.vx[jj] - i.vx, uy = s.vy[jj] - i.vy, uz = s.vz[jj] - i.vz;
+        pair<SOFT>(i, J{s.x[jj], s.y[jj], s.z[jj], s.m[jj], s.vx[jj], s.vy[jj], s.vz[jj]}, eps2, T);
+    }
+    template <bool SOFT>
+    __device__ static __forceinline__ void pair(const I &i, const J &j, double eps2, Tile &T) {
+        const double dx = j.x - i.x, dy = j.y - i.y, dz = j.z - i.z;
+        const double ux = j.vx - i.vx, uy = j.vy - i.vy, uz = j.vz - i.vz;
         const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, __builtin_fma(dx, dx, eps2)));
         const double rv = __builtin_fma(dz, uz, __builtin_fma(dy, uy, dx * ux));
         double rinv = rsqrt_f64(r2);
         if (!SOFT) rinv = r2 > 0.0 ? rinv : 0.0;
         const double rinv2 = rinv * rinv;
-        const double mr = s.m[jj] * rinv;
+        const double mr = j.m * rinv;
         const double mr3 = mr * rinv2;
         const double t = -3.0 * (rv * rinv2);
         T.p += mr;
@@ -578,13 +633,23 @@ template <> struct EpsOf<ModeF32Fixed> { using T = float; };
 
 // How a mode folds its sums: every FOLD j of a tile (TJ: once per tile), and whether the sums
 // are fixed-point integers (then at most TJ / FOLD lanes may share an i-particle).
+// SCALAR_J: whole blocks read the j-records with scalar loads (measured faster for the float
+// modes: 611 against 664 ms for the FP32 full force at N = 2^20) or from LDS tiles (FP64,
+// whose 56-byte record made the scalar path slower: 1.71 against 1.34 s).
 template <class M> struct ModeTraits {
     static constexpr int FOLD = TJ;
     static constexpr bool FIXED = false;
+    static constexpr bool SCALAR_J = true;
 };
 template <> struct ModeTraits<ModeF32Fixed> {
     static constexpr int FOLD = 64;
     static constexpr bool FIXED = true;
+    static constexpr bool SCALAR_J = true;
+};
+template <> struct ModeTraits<ModeF64> {
+    static constexpr int FOLD = TJ;
+    static constexpr bool FIXED = false;
+    static constexpr bool SCALAR_J = false;
 };
 
 // Final sums of row q of a work item's j-range ks: straight to the outputs when K == 1,
@@ -663,11 +728,78 @@ __device__ void force_items_split(const typename M::Args &pa, const ForceCommon 
     }
 }
 
+// Sums of the IPL i-particles of a work-item over the j-tiles [t0, t1): the j-records read
+// once per wave with scalar loads (every lane takes the same j).  The latency of each load is
+// exposed to its wave, so this pays only on long j-ranges (SCALAR_MIN_TILES tiles or more).
+constexpr int32_t SCALAR_MIN_TILES = 16;
+
+template <class M, int IPL, int UNR, bool SOFT>
+__device__ __forceinline__ void block_sums_scalar(const typename M::Args &pa, int32_t n, int32_t t0,
+                                                  int32_t t1, const typename M::I (&ii)[IPL],
+                                                  typename M::Sum (&S)[IPL],
+                                                  typename EpsOf<M>::T eps2) {
+    constexpr int FOLD = ModeTraits<M>::FOLD;
+    for (int32_t t = t0; t < t1; ++t) {
+        const int32_t j0 = t * TJ;
+        const int32_t jn = n - j0 < TJ ? n - j0 : TJ;
+        for (int32_t jb = 0; jb < jn; jb += FOLD) {
+            // wave-uniform bounds kept in scalar registers
+            const int32_t ja = __builtin_amdgcn_readfirstlane(j0 + jb);
+            const int32_t je = __builtin_amdgcn_readfirstlane(j0 + (jb + FOLD < jn ? jb + FOLD : jn));
+            typename M::Tile T[IPL];
+#pragma unroll
+            for (int p = 0; p < IPL; ++p) T[p] = M::tile_zero();
+#pragma unroll UNR
+            for (int32_t j = ja; j < je; ++j) {
+                const typename M::J jr = M::load_j(pa, j);
+#pragma unroll
+                for (int p = 0; p < IPL; ++p) M::template pair<SOFT>(ii[p], jr, eps2, T[p]);
+            }
+#pragma unroll
+            for (int p = 0; p < IPL; ++p) M::fold(S[p], T[p]);
+        }
+    }
+}
+
+// The same sums from LDS tiles staged by the whole workgroup (one j per work-item, loads
+// coalesced); every lane then reads each staged j (a broadcast).  Padding j past n has zero
+// mass and adds exact zeros, so both paths give bitwise the same sums.
+template <class M, int IPL, int UNR, bool SOFT>
+__device__ __forceinline__ void block_sums_lds(const typename M::Args &pa, int32_t n,
+                                               typename M::Smem &sm, int32_t t0, int32_t t1,
+                                               const typename M::I (&ii)[IPL],
+                                               typename M::Sum (&S)[IPL],
+                                               typename EpsOf<M>::T eps2) {
+    constexpr int FOLD = ModeTraits<M>::FOLD;
+    for (int32_t t = t0; t < t1; ++t) {
+        __syncthreads();
+        M::stage(pa, sm, threadIdx.x, t * TJ + (int32_t)threadIdx.x, n);
+        __syncthreads();
+        for (int jb = 0; jb < TJ; jb += FOLD) {
+            typename M::Tile T[IPL];
+#pragma unroll
+            for (int p = 0; p < IPL; ++p) T[p] = M::tile_zero();
+#pragma unroll UNR
+            for (int jj = jb; jj < jb + FOLD; ++jj) {
+#pragma unroll
+                for (int p = 0; p < IPL; ++p) M::template interact<SOFT>(ii[p], sm, jj, eps2, T[p]);
+            }
+#pragma unroll
+            for (int p = 0; p < IPL; ++p) M::fold(S[p], T[p]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // The force kernel.  Each workgroup takes work items (i-block, j-range); each work-item holds
-// IPL i-particles in registers; the workgroup stages TJ j-particles at a time in LDS, and
-// every work-item reads each staged j (an LDS broadcast) and interacts it with its i's; the
-// j-loop is unrolled UNR times.
+// IPL i-particles in registers.  On the whole-block path every lane of a wave takes the same j
+// at the same time: on long j-ranges the float modes read each j-record once per wave with
+// scalar loads (no LDS, no barriers); FP64, and every mode on short j-ranges, stage TJ
+// j-particles at a time in LDS and every lane reads each staged j (a broadcast).  The j-loop
+// is unrolled UNR times.  The tile sums are folded into the outer sums every FOLD j counted
+// from the start of each TJ-tile (the same j-indices on every path, so the path never changes
+// a result).  Short lists take the lane split, which stages TJ j-particles at a time in LDS
+// (force_items_split).
 // K == 1: results go straight to acc/jerk/pot; K > 1: to the partial planes for
 // force_reduce.  The potential sum is negated on output.
 // ------------------------------------------------------------------------------------------
@@ -688,8 +820,18 @@ __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCom
         force_items_split<M, UNR, SOFT>(pa, fc, pl, sm, n_i, eps2);
         return;
     }
-    for (int32_t w = blockIdx.x; w < pl.items; w += gridDim.x) {
-        const int32_t iblk = w / pl.K, ks = w - (w / pl.K) * pl.K;
+    // XCD-aware order: workgroups are dealt to the chip's 8 XCDs round-robin, so with a grid
+    // that is a multiple of 8, XCD x runs the workgroups x, x + 8, ...; they take the x-th
+    // eighth of the items in (j-range major, i-block minor) order, and the workgroups resident
+    // on one XCD at a time share few j-ranges, which its own L2 then holds.  Any other grid
+    // takes the items in plain order.  Items are independent: the order never changes a result.
+    const int32_t nx = (gridDim.x & 7) == 0 ? 8 : 1;
+    const int32_t xcd = (int32_t)blockIdx.x % nx;
+    const int32_t v_end = (int32_t)(((int64_t)pl.items * (xcd + 1)) / nx);
+    const int32_t v_step = (int32_t)gridDim.x / nx;
+    for (int32_t v = (int32_t)(((int64_t)pl.items * xcd) / nx) + (int32_t)blockIdx.x / nx;
+         v < v_end; v += v_step) {
+        const int32_t ks = v / pl.n_iblk, iblk = v - ks * pl.n_iblk;
         int32_t q[IPL], g[IPL];
         typename M::I ii[IPL];
         typename M::Sum S[IPL];
@@ -702,36 +844,13 @@ __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCom
         }
         const int32_t t0 = ks * pl.tps;
         const int32_t t1 = t0 + pl.tps < pl.ntiles ? t0 + pl.tps : pl.ntiles;
-        for (int32_t t = t0; t < t1; ++t) {
-            __syncthreads();
-            M::stage(pa, sm, threadIdx.x, t * TJ + (int32_t)threadIdx.x, fc.n);
-            __syncthreads();
-            if constexpr (ModeTraits<M>::FOLD == TJ) {
-                typename M::Tile T[IPL];
-#pragma unroll
-                for (int p = 0; p < IPL; ++p) T[p] = M::tile_zero();
-#pragma unroll UNR
-                for (int jj = 0; jj < TJ; ++jj) {
-#pragma unroll
-                    for (int p = 0; p < IPL; ++p) M::template interact<SOFT>(ii[p], sm, jj, eps2, T[p]);
-                }
-#pragma unroll
-                for (int p = 0; p < IPL; ++p) M::fold(S[p], T[p]);
-            } else {  // sums folded every FOLD j (canonical sub-blocks)
-                constexpr int FOLD = ModeTraits<M>::FOLD;
-                for (int jb = 0; jb < TJ; jb += FOLD) {
-                    typename M::Tile T[IPL];
-#pragma unroll
-                    for (int p = 0; p < IPL; ++p) T[p] = M::tile_zero();
-#pragma unroll UNR
-                    for (int jj = jb; jj < jb + FOLD; ++jj) {
-#pragma unroll
-                        for (int p = 0; p < IPL; ++p) M::template interact<SOFT>(ii[p], sm, jj, eps2, T[p]);
-                    }
-#pragma unroll
-                    for (int p = 0; p < IPL; ++p) M::fold(S[p], T[p]);
-                }
-            }
+        if constexpr (ModeTraits<M>::SCALAR_J) {
+            if (pl.tps >= SCALAR_MIN_TILES)
+                block_sums_scalar<M, IPL, UNR, SOFT>(pa, fc.n, t0, t1, ii, S, eps2);
+            else
+                block_sums_lds<M, IPL, UNR, SOFT>(pa, fc.n, sm, t0, t1, ii, S, eps2);
+        } else {
+            block_sums_lds<M, IPL, UNR, SOFT>(pa, fc.n, sm, t0, t1, ii, S, eps2);
         }
         const int32_t jlo = t0 * TJ, jhi = t1 * TJ;
 #pragma unroll

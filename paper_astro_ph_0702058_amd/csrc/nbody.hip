@@ -186,15 +186,15 @@ constexpr int32_t FULL_ITEMS_PER_CU = 128, FULL_KMAX = 64, BLOCK_ITEMS_PER_CU = 
 // Heuristic defaults per size class; nb_tune() replaces them with measured choices.
 Variant default_variant(int32_t n, int prec, int num_cu, bool block) {
     Variant v;
-    // measured on MI355X: full-force calls at N = 2^20 take two i per work-item, unroll 1 and
-    // 128 work items per compute unit (fine items shorten the last, partly filled round of
-    // workgroups: 688 ms at 16 per CU, 656 ms at 128), with the j-split capped at 64 ranges;
-    // block steps (N = 65536 run, every block size from 1 to N) take one i per work-item,
-    // unroll 2 and 16 items per compute unit (2.17 s of force time against 2.42 s with two i
-    // per work-item and 8 items per CU: more, shorter items at every block size)
-    const bool f32 = prec == NB_FP32 || prec == NB_FP32_FIXED;
-    v.ipl = (f32 && n >= 16384 && !block) ? 2 : 1;
-    v.unroll = (f32 && !block) ? 1 : 2;
+    // measured on MI355X: full-force calls at N = 2^20 take one i per work-item, unroll 2 and
+    // 128 work items per compute unit (FP32 with scalar j-loads: 611 ms, against 616 ms with
+    // two i per work-item and unroll 1, 622 ms at 64 items per CU; fine items shorten the
+    // last, partly filled round of workgroups), with the j-split capped at 64 ranges; block
+    // steps (N = 65536 run, every block size from 1 to N) take one i per work-item, unroll 2
+    // and 16 items per compute unit (more, shorter items at every block size)
+    (void)n; (void)prec;
+    v.ipl = 1;
+    v.unroll = 2;
     v.target = num_cu * (block ? BLOCK_ITEMS_PER_CU : FULL_ITEMS_PER_CU);
     v.kmax = block ? 1 << 16 : FULL_KMAX;  // K is also bounded by the tile count
     return v;
@@ -298,6 +298,7 @@ nb_status enqueue_force(nb_ctx *c, const Variant &v, int cls, const int32_t *ili
         const ForcePlan p = make_plan(n_i_max, c->n, ib, v.target, v.kmax, smax);
         grid = std::min(p.items, 1 << 20);
     }
+    grid = (grid + 7) & ~7;  // a multiple of 8: the force kernel's XCD-aware item order
     const bool soft = c->eps > 0.0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->profile) {
