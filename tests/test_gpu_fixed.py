@@ -1,7 +1,9 @@
 """Order-independent single precision (fp32fixed): float sums over aligned 64-j sub-blocks added
 into int64 fixed point.  Its forces must be bitwise identical for every launch variant (i per
-lane 1 or 2, unroll 1 or 2), every work-item target (which changes the j-split K and, for short
-lists, the lane split), and between the full-force and block-step launch classes; they must
+lane 1 or 2, unroll 1 or 2), every work-item target (which changes the j-split K, for short
+lists the lane split, and whether an item of 16 or more j-tiles reads its j-records with scalar
+loads or an item of fewer stages them in LDS), and between the full-force and block-step launch
+classes; they must
 meet the single-precision tolerances against the oracle, also on a sample that reaches the
 halo, where accelerations and jerks are small (the fixed-point steps, 2^-44 for acc and pot and
 2^-42 for the jerk, add rounding of about one step times sqrt(N/64): near 1e-11 absolute at
