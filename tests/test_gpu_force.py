@@ -188,3 +188,43 @@ def test_force_all_single_matches_rounded_inputs(eps):
         check("fp32all", got, ref, f"N={n} eps={eps}")
         exact = oracle.force(x, v, m, eps * eps, idx=idx)
         print(f"  against unrounded inputs: e_acc={rms_rel(got[0], exact[0]):.3e}", flush=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "ds", "fp64", "fp32fixed", "fp32all"])
+def test_force_scalar_load_and_lds_paths(prec):
+    """All i at N = 4999 (19 full j-tiles and a ragged tail of 135), once with 8 work items
+    (one j-range of 20 tiles per item: the float modes read the j-records with scalar loads)
+    and once with 4096 (20 j-ranges of one tile: LDS tiles).  Both meet the tolerances against
+    the oracle (fp32all: against the oracle on float-rounded inputs); they differ only in how
+    the per-tile sums are grouped, so they agree to 1e-11 relative (fp32all, whose sums stay
+    in float: 1e-6; fp32fixed: bitwise)."""
+    import torch
+    n, eps = 4999, 1 / 256
+    x, v, m = plummer(n, 34)
+    st = nbody.DeviceState(x, v, m)
+    res = []
+    with nbody.Context(n, eps, precision=prec) as ctx:
+        ctx.nb_bind(st)
+        ctx.nb_predict(torch.zeros(1, dtype=torch.int64, device="cuda"))
+        for target in (8, 4096):
+            ctx.nb_set_variant(0, dict(ipl=1, unroll=2, target=target, kmax=64))
+            acc = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+            jerk = torch.zeros_like(acc)
+            pot = torch.zeros(n, dtype=torch.float64, device="cuda")
+            ctx.nb_force(acc, jerk, pot)
+            ctx.nb_sync()
+            res.append((acc.cpu().numpy().T.copy(), jerk.cpu().numpy().T.copy(), pot.cpu().numpy()))
+    if prec == "fp32all":
+        xr, vr, mr = (np.asarray(a, np.float32).astype(np.float64) for a in (x, v, m))
+        ref = oracle.force(xr, vr, mr, eps * eps)
+    else:
+        ref = oracle.force(x, v, m, eps * eps)
+    tol_key = "fp32" if prec == "fp32fixed" else prec
+    for r, label in zip(res, ("scalar-load path", "LDS path")):
+        check(tol_key, r, ref, f"N={n} {label}")
+    for c in range(3):
+        if prec == "fp32fixed":
+            assert np.array_equal(res[0][c], res[1][c]), c
+        else:
+            lim = 1e-6 if prec == "fp32all" else 1e-11
+            assert rms_rel(res[0][c], res[1][c]) <= lim, (c, rms_rel(res[0][c], res[1][c]))
