@@ -89,51 +89,54 @@ __global__ void __launch_bounds__(WG) vjp_post(int32_t n, double dt, double *xb,
     }
 }
 
+template <class T> __device__ __forceinline__ T fma_t(T a, T b, T c);
+template <> __device__ __forceinline__ float fma_t<float>(float a, float b, float c) {
+    return __builtin_fmaf(a, b, c);
+}
+template <> __device__ __forceinline__ double fma_t<double>(double a, double b, double c) {
+    return __builtin_fma(a, b, c);
+}
+
 // Pair terms of the force VJP for particle p against q, arithmetic type T.  d = x_q - x_p,
 // u = v_q - v_p; (A, B) adjoints of p, (Aq, Bq) adjoints of q; rinv = s^-1/2 or 0 (self).
-// Adds the i-side -m_q dphi/d(d,u) and the j-side +m_p dphi/d(d,u) with q's adjoints (the
-// derivatives are even in (d, u)) to gx, gu, and phi at (-d, -u) with q's adjoints to gm.
+// With r3 = rinv^3, r5, r7 and du = d.u, the derivative of m_q (A.a + B.k) with respect to d
+// is m_q [A r3 + c1 d + c2 u + c3 B] and with respect to u is m_q [B r3 + c2 d], where
+// c1 = -3 r5 (A.d + B.u) + 15 r7 du B.d, c2 = -3 r5 B.d, c3 = -3 r5 du (even in (d, u)).
+// p gains the i-side term with -m_q and its own (A, B), and the j-side term with +m_p and
+// q's (Aq, Bq); both are added at once, the shared factors formed once:
+//   gx += r3 (m_p Aq - m_q A) + (m_p c1q - m_q c1) d + (m_p c2q - m_q c2) u + c3 (m_p Bq - m_q B)
+//   gu += r3 (m_p Bq - m_q B) + (m_p c2q - m_q c2) d
+// and gm gains phi at (-d, -u) with q's adjoints: -(Aq.d + Bq.u) r3 - c3 Bq.d.
 template <class T>
 __device__ __forceinline__ void vjp_pair(T dx, T dy, T dz, T ux, T uy, T uz, T rinv, T mp, T mq,
                                          const T A[3], const T B[3], const T Aq[3],
                                          const T Bq[3], T gx[3], T gu[3], T &gm) {
     const T r2 = rinv * rinv, r3 = rinv * r2, r5 = r3 * r2, r7 = r5 * r2;
-    const T du = dx * ux + dy * uy + dz * uz;
+    const T du = fma_t(dz, uz, fma_t(dy, uy, dx * ux));
+    const T m3r5 = T(-3) * r5;
+    const T c3 = m3r5 * du;
+    const T f15 = (T(15) * r7) * du;
+    const T Ad = fma_t(A[2], dz, fma_t(A[1], dy, A[0] * dx));
+    const T Bd = fma_t(B[2], dz, fma_t(B[1], dy, B[0] * dx));
+    const T Bu = fma_t(B[2], uz, fma_t(B[1], uy, B[0] * ux));
+    const T c1 = fma_t(f15, Bd, m3r5 * (Ad + Bu));
+    const T c2 = m3r5 * Bd;
+    const T Adq = fma_t(Aq[2], dz, fma_t(Aq[1], dy, Aq[0] * dx));
+    const T Bdq = fma_t(Bq[2], dz, fma_t(Bq[1], dy, Bq[0] * dx));
+    const T Buq = fma_t(Bq[2], uz, fma_t(Bq[1], uy, Bq[0] * ux));
+    const T c1q = fma_t(f15, Bdq, m3r5 * (Adq + Buq));
+    const T c2q = m3r5 * Bdq;
+    const T C1 = fma_t(mp, c1q, -(mq * c1));
+    const T C2 = fma_t(mp, c2q, -(mq * c2));
     const T d[3] = {dx, dy, dz}, u[3] = {ux, uy, uz};
-    // i-side, (A, B) of p
-    {
-        const T Ad = A[0] * dx + A[1] * dy + A[2] * dz;
-        const T Bd = B[0] * dx + B[1] * dy + B[2] * dz;
-        const T Bu = B[0] * ux + B[1] * uy + B[2] * uz;
-        const T c1 = -T(3) * r5 * (Ad + Bu) + T(15) * r7 * du * Bd;
-        const T c2 = -T(3) * r5 * Bd;
-        const T c3 = -T(3) * r5 * du;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const T gd = A[k] * r3 + c1 * d[k] + c2 * u[k] + c3 * B[k];
-            const T gv = B[k] * r3 + c2 * d[k];
-            gx[k] -= mq * gd;
-            gu[k] -= mq * gv;
-        }
+    for (int k = 0; k < 3; ++k) {
+        const T Ab = fma_t(mp, Aq[k], -(mq * A[k]));
+        const T Bb = fma_t(mp, Bq[k], -(mq * B[k]));
+        gx[k] = fma_t(r3, Ab, fma_t(C1, d[k], fma_t(C2, u[k], fma_t(c3, Bb, gx[k]))));
+        gu[k] = fma_t(r3, Bb, fma_t(C2, d[k], gu[k]));
     }
-    // j-side, (Aq, Bq) of q acting on p
-    {
-        const T Ad = Aq[0] * dx + Aq[1] * dy + Aq[2] * dz;
-        const T Bd = Bq[0] * dx + Bq[1] * dy + Bq[2] * dz;
-        const T Bu = Bq[0] * ux + Bq[1] * uy + Bq[2] * uz;
-        const T c1 = -T(3) * r5 * (Ad + Bu) + T(15) * r7 * du * Bd;
-        const T c2 = -T(3) * r5 * Bd;
-        const T c3 = -T(3) * r5 * du;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const T gd = Aq[k] * r3 + c1 * d[k] + c2 * u[k] + c3 * Bq[k];
-            const T gv = Bq[k] * r3 + c2 * d[k];
-            gx[k] += mp * gd;
-            gu[k] += mp * gv;
-        }
-        // phi(-d, -u; Aq, Bq)
-        gm += -(Ad + Bu) * r3 + T(3) * du * Bd * r5;
-    }
+    gm = fma_t(-(Adq + Buq), r3, fma_t(-c3, Bdq, gm));
 }
 
 struct VjpArgs {
