@@ -78,3 +78,12 @@ def test_missing_library_fails_loudly(tmp_path):
             % (ROOT, str(tmp_path / "nope.so")))
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
     assert "raised" in r.stdout
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: any --gpus other than 1 exits with status 2 and a message,
+    before touching a device."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
