@@ -194,7 +194,8 @@ def test_force_all_single_matches_rounded_inputs(eps):
 def test_force_scalar_load_and_lds_paths(prec):
     """All i at N = 4999 (19 full j-tiles and a ragged tail of 135), once with 8 work items
     (one j-range of 20 tiles per item: the float modes read the j-records with scalar loads)
-    and once with 4096 (20 j-ranges of one tile: LDS tiles).  Both meet the tolerances against
+    and once with 400 (20 i-blocks of 256 against 20 j-ranges of one tile: LDS tiles; one
+    lane per i in both).  Both meet the tolerances against
     the oracle (fp32all: against the oracle on float-rounded inputs); they differ only in how
     the per-tile sums are grouped, so they agree to 1e-11 relative (fp32all, whose sums stay
     in float: 1e-6; fp32fixed: bitwise)."""
@@ -206,7 +207,7 @@ def test_force_scalar_load_and_lds_paths(prec):
     with nbody.Context(n, eps, precision=prec) as ctx:
         ctx.nb_bind(st)
         ctx.nb_predict(torch.zeros(1, dtype=torch.int64, device="cuda"))
-        for target in (8, 4096):
+        for target in (8, 400):
             ctx.nb_set_variant(0, dict(ipl=1, unroll=2, target=target, kmax=64))
             acc = torch.zeros((3, n), dtype=torch.float64, device="cuda")
             jerk = torch.zeros_like(acc)
