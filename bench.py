@@ -42,11 +42,11 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def committed_traffic(kernel_sym, n, args):
+def committed_traffic(kernel_sym, n, args, variant=None):
     """HBM bytes per launch of the full-force kernel from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading for a plain copy of known
-    size), or None when the summary is for another workload or the kernel source has changed
-    since the counters were taken."""
+    size), or None when the summary is for another workload or launch configuration, or the
+    kernel source has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "force_full_fp32_plummer_n1048576_traffic.json")
     try:
         with open(path) as f:
@@ -54,7 +54,8 @@ def committed_traffic(kernel_sym, n, args):
     except (OSError, ValueError):
         return None
     if (t.get("kernel") != kernel_sym or t.get("n") != n or t.get("eps") != args.eps
-            or t.get("kernel_source_sha256_16") != kernel_source_hash()):
+            or t.get("kernel_source_sha256_16") != kernel_source_hash()
+            or (variant is not None and t.get("variant") != variant)):
         return None
     return t.get("hbm_bytes_per_launch")
 
@@ -665,7 +666,7 @@ def main():
     avg_full_ms = full_ms / max(full_n, 1)
     achieved = FLOP_PER_INTERACTION * n * n / (avg_full_ms * 1e-3) / 1e12
     kernel_sym = "force_kernel<ModeF32, %d, %d, true, 0>" % (variant_full["ipl"], variant_full["unroll"])
-    traffic = committed_traffic(kernel_sym, n, args)
+    traffic = committed_traffic(kernel_sym, n, args, variant_full)
     roofline = {"bound": "alu", "kernel": kernel_sym, "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,

@@ -231,9 +231,10 @@ typedef struct {
 nb_status nb_get_variant(nb_ctx *ctx, int32_t which, nb_variant *out);
 
 /* Replace that variant (HOST struct).  NB_EINVAL if it is not compiled, if its target exceeds
- * 128 work items per compute unit, or if its j-split would need more partial-sum storage than
+ * 256 work items per compute unit, or if its j-split would need more partial-sum storage than
  * the context holds (sized for one or two i per work-item with up to 16 items per compute unit
- * and any split, or up to 128 items per compute unit and at most 64 j-ranges). */
+ * and any split, up to 256 items per compute unit and at most 64 j-ranges with one i per
+ * work-item, or up to 128 with two). */
 nb_status nb_set_variant(nb_ctx *ctx, int32_t which, const nb_variant *v);
 
 /* Autotuner: launch every available variant on the first n_i particles against the

@@ -181,15 +181,16 @@ SchedView sched_view(const nb_ctx *c) {
 // Work-item targets: up to FULL_ITEMS_PER_CU per compute unit with at most FULL_KMAX j-ranges
 // (the full-force class), or up to BLOCK_ITEMS_PER_CU with any split; partial planes are sized
 // for both families.
-constexpr int32_t FULL_ITEMS_PER_CU = 128, FULL_KMAX = 64, BLOCK_ITEMS_PER_CU = 16;
+constexpr int32_t FULL_ITEMS_PER_CU = 256, FULL_KMAX = 64, BLOCK_ITEMS_PER_CU = 16;
 
 // Heuristic defaults per size class; nb_tune() replaces them with measured choices.
 Variant default_variant(int32_t n, int prec, int num_cu, bool block) {
     Variant v;
     // measured on MI355X: full-force calls at N = 2^20 take one i per work-item, unroll 2 and
-    // 128 work items per compute unit (FP32 with scalar j-loads: 611 ms, against 616 ms with
-    // two i per work-item and unroll 1, 622 ms at 64 items per CU; fine items shorten the
-    // last, partly filled round of workgroups), with the j-split capped at 64 ranges; block
+    // 256 work items per compute unit (FP32 with scalar j-loads: 601-605 ms, against 612 ms at
+    // 128 per CU and 622 ms at 64; K = 16 j-ranges of 2.6 MB, so that the XCD streaming one
+    // range holds it in its 4 MB L2; two i per work-item and unroll 1: 616 ms at 128 per CU),
+    // with the j-split capped at 64 ranges; block
     // steps (N = 65536 run, every block size from 1 to N) take one i per work-item, unroll 2
     // and 16 items per compute unit (more, shorter items at every block size)
     (void)n; (void)prec;
@@ -492,7 +493,8 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
     {
         int64_t rows = 0;
         for (int ipl = 1; ipl <= 2; ++ipl) {
-            rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->num_cu * FULL_ITEMS_PER_CU,
+            // two i per work-item: sized for half the full target (the same partial rows)
+            rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->num_cu * FULL_ITEMS_PER_CU / ipl,
                                                               FULL_KMAX}, smax_of(precision)));
             rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->num_cu * BLOCK_ITEMS_PER_CU,
                                                               1 << 16}, smax_of(precision)));
@@ -871,7 +873,7 @@ nb_status nb_tune(nb_ctx *c, int32_t which, int32_t n_i, int32_t reps, nb_varian
     double bms = 1e300;
     const int ipls[] = {1, 2, 4}, unrs[] = {1, 2, 4};
     const int32_t targets[] = {c->num_cu * 4, c->num_cu * 8, c->num_cu * 16, c->num_cu * 32,
-                               c->num_cu * 64, c->num_cu * FULL_ITEMS_PER_CU};
+                               c->num_cu * 64, c->num_cu * 128, c->num_cu * FULL_ITEMS_PER_CU};
     for (int ipl : ipls)
         for (int unr : unrs)
             for (int32_t tg : targets) {

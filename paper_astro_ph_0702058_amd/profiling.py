@@ -79,6 +79,7 @@ def main(argv=None):
     b.add_argument("--eps", type=float, required=True); b.add_argument("--symbol", required=True)
     b.add_argument("--algorithmic-bytes", type=float, required=True)
     b.add_argument("--cmd-fetch", required=True); b.add_argument("--cmd-write", required=True)
+    b.add_argument("--variant", help="launch configuration of the profiled launches (JSON)")
     c = sub.add_parser("counters"); c.add_argument("csv"); c.add_argument("--kernel", required=True)
     c.add_argument("--interactions", type=float,
                    help="interactions per dispatch: also print per-interaction figures")
@@ -94,6 +95,7 @@ def main(argv=None):
                "fetch_scale": t["FETCH_SIZE"]["scale"], "write_scale": t["WRITE_SIZE"]["scale"],
                "copy_bytes": args.copy_bytes, "algorithmic_bytes_per_launch": args.algorithmic_bytes,
                "kernel_source_sha256_16": kernel_source_hash(),
+               "variant": json.loads(args.variant) if args.variant else None,
                "commands": {"FETCH_SIZE": args.cmd_fetch, "WRITE_SIZE": args.cmd_write},
                "raw_kib": {"FETCH_SIZE": t["FETCH_SIZE"]["kib_per_dispatch"],
                            "WRITE_SIZE": t["WRITE_SIZE"]["kib_per_dispatch"],
