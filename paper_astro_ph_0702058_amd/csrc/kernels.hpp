@@ -540,8 +540,12 @@ struct ModeF64 {
     struct I {
         double x, y, z, vx, vy, vz, m;
     };
+    // one 64-byte record per staged j (a single LDS address for all seven values)
+    struct Rec {
+        double x, y, z, m, vx, vy, vz, pad;
+    };
     struct Smem {
-        double x[TJ], y[TJ], z[TJ], m[TJ], vx[TJ], vy[TJ], vz[TJ];
+        Rec r[TJ];
     };
     struct Tile {
         double ax, ay, az, jx, jy, jz, p;
@@ -553,9 +557,9 @@ struct ModeF64 {
     }
     __device__ static void stage(const Args &a, Smem &s, int t, int j, int n) {
         const bool ok = j < n;
-        s.x[t] = ok ? a.px[j] : 0.0; s.y[t] = ok ? a.py[j] : 0.0; s.z[t] = ok ? a.pz[j] : 0.0;
-        s.m[t] = ok ? a.pm[j] : 0.0;
-        s.vx[t] = ok ? a.vx[j] : 0.0; s.vy[t] = ok ? a.vy[j] : 0.0; s.vz[t] = ok ? a.vz[j] : 0.0;
+        s.r[t] = Rec{ok ? a.px[j] : 0.0, ok ? a.py[j] : 0.0, ok ? a.pz[j] : 0.0,
+                     ok ? a.pm[j] : 0.0, ok ? a.vx[j] : 0.0, ok ? a.vy[j] : 0.0,
+                     ok ? a.vz[j] : 0.0, 0.0};
     }
     __device__ static Tile tile_zero() { return Tile{0., 0., 0., 0., 0., 0., 0.}; }
     __device__ static Sum sum_zero() { return tile_zero(); }
@@ -563,8 +567,7 @@ struct ModeF64 {
         return I{xp[0], xp[1], xp[2], vp[0], vp[1], vp[2], m};
     }
     __device__ static void put(Smem &s, int t, const double xp[3], const double vp[3], double m) {
-        s.x[t] = xp[0]; s.y[t] = xp[1]; s.z[t] = xp[2]; s.m[t] = m;
-        s.vx[t] = vp[0]; s.vy[t] = vp[1]; s.vz[t] = vp[2];
+        s.r[t] = Rec{xp[0], xp[1], xp[2], m, vp[0], vp[1], vp[2], 0.0};
     }
 
     struct J {
@@ -577,7 +580,8 @@ struct ModeF64 {
     template <bool SOFT>
     __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, double eps2,
                                                     Tile &T) {
-        pair<SOFT>(i, J{s.x[jj], s.y[jj], s.z[jj], s.m[jj], s.vx[jj], s.vy[jj], s.vz[jj]}, eps2, T);
+        const Rec &q = s.r[jj];
+        pair<SOFT>(i, J{q.x, q.y, q.z, q.m, q.vx, q.vy, q.vz}, eps2, T);
     }
     template <bool SOFT>
     __device__ static __forceinline__ void pair(const I &i, const J &j, double eps2, Tile &T) {
