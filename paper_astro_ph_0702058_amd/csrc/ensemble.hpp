@@ -1,10 +1,9 @@
 // ensemble.hpp -- gfx950 device code for many independent clusters integrated together.
 //
 // Every cluster runs its own Sec. 2 block-step scheme (own times, levels and blocks).  One
-// global step advances every unfinished cluster by one of its own block steps, in three kernels:
-//   ens_plan   one workgroup: the prefix over clusters of their force work items
-//              (cluster, i-block, j-range)
-//   ens_force  all workgroups take items.  An item is an
+// global step advances every unfinished cluster by one of its own block steps, in two kernels:
+//   ens_force  all workgroups take work items (cluster, i-block, j-range); each workgroup
+//              first forms the prefix over clusters of their item counts itself.  An item is an
 //              i-block of the cluster's block against a range of whole j-tiles of the same
 //              cluster; i- and j-particles are predicted to the cluster's block time as they
 //              are loaded (Sec. 2 predictor, FP64); small blocks share each i among several
@@ -35,7 +34,6 @@ struct EnsView {
     const double *eps2;         // softening^2 of each cluster (> 0)
     EnsCluster *cl;
     int32_t *active;            // global indices, cluster c's block at active[off[c]...]
-    int32_t *item_start;        // C + 1 exclusive prefix of force work items (ens_plan)
     double *partial;
     double *crit;
     int32_t *flags;             // [0]: non-finite seen, [1]: step clamped at 2^-lmax
@@ -211,34 +209,39 @@ __global__ void __launch_bounds__(WGL) ens_local(EnsView e, StateRW s, double et
     }
 }
 
-// Exclusive prefix over clusters of their force work items (one workgroup of WGL).
-__global__ void __launch_bounds__(WGL) ens_plan(EnsView e) {
-    __shared__ int32_t buf[WGL];
-    __shared__ int32_t carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int32_t c0 = 0; c0 < e.C; c0 += WGL) {
-        const int32_t c = c0 + threadIdx.x;
-        int32_t items = 0;
-        if (c < e.C) {
-            const int32_t na = e.cl[c].n_act;
-            const int32_t ibc = WG / lane_split(na, true);
-            items = na > 0 ? ((na + ibc - 1) / ibc) * e.K[c] : 0;
-        }
-        buf[threadIdx.x] = items;
-        __syncthreads();
-        for (int o = 1; o < WGL; o <<= 1) {  // inclusive scan (Hillis-Steele)
-            const int32_t v = (int)threadIdx.x >= o ? buf[threadIdx.x - o] : 0;
-            __syncthreads();
-            buf[threadIdx.x] += v;
-            __syncthreads();
-        }
-        if (c < e.C) e.item_start[c] = carry + buf[threadIdx.x] - items;
-        __syncthreads();
-        if (threadIdx.x == WGL - 1) carry += buf[WGL - 1];
-        __syncthreads();
+// Exclusive prefix over clusters of their force work items, start[0..C], formed by one
+// workgroup of BS in its LDS: each work-item takes a contiguous run of clusters, the runs'
+// totals are scanned across the wave (shuffles) and across waves (wsum).
+template <int BS>
+__device__ void ens_item_prefix(const EnsView &e, int32_t *start, int32_t *wsum) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t per = (e.C + BS - 1) / BS;
+    const int32_t c0 = (int32_t)threadIdx.x * per;
+    const int32_t c1 = c0 + per < e.C ? c0 + per : e.C;
+    int32_t own = 0;
+    for (int32_t c = c0; c < c1; ++c) {
+        const int32_t na = e.cl[c].n_act;
+        const int32_t ibc = BS / lane_split(na, true);
+        const int32_t items = na > 0 ? ((na + ibc - 1) / ibc) * e.K[c] : 0;
+        start[c] = items;
+        own += items;
     }
-    if (threadIdx.x == 0) e.item_start[e.C] = carry;
+    int32_t inc = own;  // inclusive scan over the wave
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t v = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += v;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    int32_t run = inc - own;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+    for (int32_t c = c0; c < c1; ++c) {
+        const int32_t items = start[c];
+        start[c] = run;
+        run += items;
+    }
+    if (threadIdx.x == BS - 1) start[e.C] = run;
+    __syncthreads();
 }
 
 template <class M> __device__ __forceinline__ typename EpsOf<M>::T eps_as(double e2);
@@ -260,13 +263,13 @@ __device__ __forceinline__ void predicted(const StateRW &s, int32_t i, int64_t t
 
 // Softened (eps > 0) interactions only; one i per work-item, S lanes per i when the
 // cluster's block is small.
-// Dynamic LDS: the C + 1 item starts, copied once per workgroup.
+// Dynamic LDS: the C + 1 item starts, formed once per workgroup.
 template <class M, int UNR>
 __global__ void __launch_bounds__(WG) ens_force(EnsView e, StateRW st) {
     __shared__ typename M::Smem sm;
+    __shared__ int32_t wsum[WG / 64];
     extern __shared__ int32_t start[];
-    for (int32_t c = threadIdx.x; c <= e.C; c += WG) start[c] = e.item_start[c];
-    __syncthreads();
+    ens_item_prefix<WG>(e, start, wsum);
     const int32_t total = start[e.C];
     for (int32_t w = blockIdx.x; w < total; w += gridDim.x) {
         // cluster of item w: the last c with start[c] <= w

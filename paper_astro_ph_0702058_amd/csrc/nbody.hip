@@ -99,7 +99,7 @@ struct nb_ens {
     std::vector<int64_t> part_off_h;
     std::vector<double> eps2_h;
     int32_t *off = nullptr, *K = nullptr, *tpi = nullptr, *prow = nullptr, *active = nullptr;
-    int32_t *flags = nullptr, *item_start = nullptr;
+    int32_t *flags = nullptr;
     int64_t *part_off = nullptr;
     double *eps2 = nullptr, *partial = nullptr, *crit = nullptr, *ek = nullptr, *ep = nullptr;
     EnsCluster *cl = nullptr;
@@ -957,7 +957,7 @@ EnsView ens_view(const nb_ens *e, int64_t t_end) {
     EnsView v;
     v.C = e->C; v.off = e->off; v.K = e->K; v.tpi = e->tpi; v.part_off = e->part_off;
     v.prow = e->prow; v.eps2 = e->eps2; v.cl = e->cl; v.active = e->active;
-    v.item_start = e->item_start; v.partial = e->partial; v.crit = e->crit; v.flags = e->flags;
+    v.partial = e->partial; v.crit = e->crit; v.flags = e->flags;
     v.lmin = e->lmin; v.lmax = e->lmax; v.tick_len = std::ldexp(1.0, -e->lmax); v.t_end = t_end;
     return v;
 }
@@ -1010,8 +1010,6 @@ nb_status ens_enqueue_local(nb_ens *e, double eta, int32_t phase, int64_t t_end,
 
 nb_status ens_enqueue_force(nb_ens *e, int64_t t_end, hipStream_t s) {
     const EnsView v = ens_view(e, t_end);
-    ens_plan<<<1, WGL, 0, s>>>(v);
-    ELAUNCH_OK(e);
     switch (e->prec) {
         case NB_FP32: ens_launch_force<ModeF32>(e, v, s); break;
         case NB_DS: ens_launch_force<ModeDS>(e, v, s); break;
@@ -1104,7 +1102,6 @@ nb_status nb_ens_create(nb_ens **out, int32_t n_clusters, const int32_t *offsets
     ok = ok && A(&p, C * sizeof(EnsCluster)); if (ok) e->cl = (EnsCluster *)p;
     ok = ok && A(&p, N * sizeof(int32_t)); if (ok) e->active = (int32_t *)p;
     ok = ok && A(&p, 2 * sizeof(int32_t)); if (ok) e->flags = (int32_t *)p;
-    ok = ok && A(&p, (C + 1) * sizeof(int32_t)); if (ok) e->item_start = (int32_t *)p;
     ok = ok && A(&p, (size_t)e->part_off_h[C] * sizeof(double)); if (ok) e->partial = (double *)p;
     ok = ok && A(&p, 2 * N * sizeof(double)); if (ok) e->crit = (double *)p;
     ok = ok && A(&p, 2 * C * sizeof(double)); if (ok) { e->ek = (double *)p; e->ep = e->ek + C; }
@@ -1129,7 +1126,7 @@ nb_status nb_ens_destroy(nb_ens *e) {
     (void)hipDeviceSynchronize();
     ens_drop_graph(e);
     void *bufs[] = {e->off, e->K, e->tpi, e->prow, e->part_off, e->eps2, e->cl, e->active,
-                    e->flags, e->item_start, e->partial, e->crit, e->ek};
+                    e->flags, e->partial, e->crit, e->ek};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
