@@ -311,8 +311,9 @@ __global__ void __launch_bounds__(WG) ens_force(EnsView e, StateRW st) {
             }
             __syncthreads();
             typename M::Tile T = M::tile_zero();
+            const int32_t jn = n_c - t * TJ < TJ ? n_c - t * TJ : TJ;  // padding is skipped
 #pragma unroll UNR
-            for (int jj = slice; jj < TJ; jj += Sl) M::template interact<true>(ii, sm, jj, eps2, T);
+            for (int jj = slice; jj < jn; jj += Sl) M::template interact<true>(ii, sm, jj, eps2, T);
             M::fold(S, T);
         }
         for (int off = Sl >> 1; off > 0; off >>= 1) M::shfl_add(S, off);
