@@ -37,25 +37,37 @@ def run_ensemble(sizes, eps, eta, t_end, prec, lmin=3, layout=None, graph=True, 
     return xs, vs, ms, g, ctl, e0, e1
 
 
-def test_ensemble_fp64_matches_independent_oracle_runs():
-    """Six clusters of uneven size (tiles plus ragged tails), eps = 1/N_c, eta = 0.02, to
-    t = 1/8, FP64 interaction: each cluster follows its own oracle run step for step."""
-    sizes = [64, 100, 257, 300, 513, 1000]
+def check_against_oracle_runs(sizes, t_end):
+    """FP64 interaction, eps = 1/N_c, eta = 0.02: every cluster follows its own oracle run
+    step for step (levels, ticks, positions, energies)."""
     eps = [1.0 / n for n in sizes]
-    xs, vs, ms, g, ctl, e0, e1 = run_ensemble(sizes, eps, 0.02, 0.125, "fp64")
+    xs, vs, ms, g, ctl, e0, e1 = run_ensemble(sizes, eps, 0.02, t_end, "fp64")
     off = np.concatenate([[0], np.cumsum(sizes)])
     for c, n in enumerate(sizes):
         ref = oracle.BlockIntegrator(xs[c], vs[c], ms[c], eps=eps[c], nu=0.02, lmin=3)
         E0 = ref.energy()
-        ref.run_until(0.125)
+        ref.run_until(t_end)
         sl = slice(off[c], off[c + 1])
         assert ctl[c].n_steps == ref.n_steps, (c, ctl[c].n_steps, ref.n_steps)
         assert ctl[c].n_active_sum == ref.n_active_total
         assert ctl[c].t_cur == ref.t and ctl[c].flags == 1
         assert np.array_equal(g["level"][sl], ref.level) and np.array_equal(g["tick"][sl], ref.tick)
         assert np.max(np.abs(g["x"][sl] - ref.x)) < 1e-10, c
-        assert abs((e0[0][c] + e0[1][c]) - E0) < 1e-13 * abs(E0)
-        assert abs((e1[0][c] + e1[1][c]) - ref.energy()) < 1e-11 * abs(E0)
+        assert abs((e0[0][c] + e0[1][c]) - E0) <= 1e-13 * abs(E0)
+        assert abs((e1[0][c] + e1[1][c]) - ref.energy()) <= 1e-11 * abs(E0)
+
+
+def test_ensemble_fp64_matches_independent_oracle_runs():
+    """Six clusters of uneven size (tiles plus ragged tails, last tiles of one particle), to
+    t = 1/8."""
+    check_against_oracle_runs([64, 100, 257, 300, 513, 1000], 0.125)
+
+
+def test_ensemble_whole_tiles_and_tiny_clusters():
+    """Clusters that fill whole j-tiles exactly (256, 512), one short of a tile, and the
+    degenerate one- and two-particle clusters (a lone particle feels no force and takes the
+    longest step), to t = 1/8."""
+    check_against_oracle_runs([1, 256, 2, 512, 255], 0.125)
 
 
 def test_ensemble_layouts_agree():
