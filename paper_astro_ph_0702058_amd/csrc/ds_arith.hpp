@@ -73,6 +73,22 @@ __device__ __forceinline__ ds ds_mul(ds a, ds b) {
     return fast_two_sum(p.hi, p.lo);
 }
 
+// The same products before their final renormalisation: hi + lo is exactly the sum that
+// ds_mul / ds_sqr return (fast_two_sum is error-free), with |lo| up to about two units in the
+// last place of hi.  For operands of an addition, which renormalises its own result.
+__device__ __forceinline__ ds ds_mul_raw(ds a, ds b) {
+    ds p = two_prod(a.hi, b.hi);
+    p.lo = __builtin_fmaf(a.hi, b.lo, p.lo);
+    p.lo = __builtin_fmaf(a.lo, b.hi, p.lo);
+    return p;
+}
+
+__device__ __forceinline__ ds ds_sqr_raw(ds a) {
+    ds p = two_prod(a.hi, a.hi);
+    p.lo = __builtin_fmaf(a.hi + a.hi, a.lo, p.lo);
+    return p;
+}
+
 __device__ __forceinline__ ds ds_mul_f(ds a, float b) {
     ds p = two_prod(a.hi, b);
     p.lo = __builtin_fmaf(a.lo, b, p.lo);

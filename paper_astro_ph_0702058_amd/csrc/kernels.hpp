@@ -466,15 +466,19 @@ struct ModeDS {
     template <bool SOFT>
     __device__ static __forceinline__ void pair(const I &i, const J &j, ds eps2, Tile &T) {
         const float4 h = j.h, l = j.l, vh = j.vh, vl = j.vl;
-        const ds dx = ds_sub(ds{h.x, l.x}, i.x);
-        const ds dy = ds_sub(ds{h.y, l.y}, i.y);
-        const ds dz = ds_sub(ds{h.z, l.z}, i.z);
+        // separations: the high parts' difference is exact (two_sum), the low parts' adds one
+        // rounding of about 2^-48 |x|; products that only feed an addition skip their own
+        // renormalisation
+        const ds dx = ds_add_sloppy(ds{h.x, l.x}, ds_neg(i.x));
+        const ds dy = ds_add_sloppy(ds{h.y, l.y}, ds_neg(i.y));
+        const ds dz = ds_add_sloppy(ds{h.z, l.z}, ds_neg(i.z));
         const ds ux = ds_add_sloppy(ds{vh.x, vl.x}, ds_neg(i.vx));
         const ds uy = ds_add_sloppy(ds{vh.y, vl.y}, ds_neg(i.vy));
         const ds uz = ds_add_sloppy(ds{vh.z, vl.z}, ds_neg(i.vz));
-        const ds r2 = ds_add_sloppy(ds_add_sloppy(ds_add_sloppy(eps2, ds_sqr(dx)), ds_sqr(dy)),
-                                    ds_sqr(dz));
-        const ds rv = ds_add_sloppy(ds_add_sloppy(ds_mul(dx, ux), ds_mul(dy, uy)), ds_mul(dz, uz));
+        const ds r2 = ds_add_sloppy(
+            ds_add_sloppy(ds_add_sloppy(eps2, ds_sqr_raw(dx)), ds_sqr_raw(dy)), ds_sqr_raw(dz));
+        const ds rv = ds_add_sloppy(ds_add_sloppy(ds_mul_raw(dx, ux), ds_mul_raw(dy, uy)),
+                                    ds_mul_raw(dz, uz));
         ds rinv = ds_rsqrt(r2);
         if (!SOFT && !(r2.hi > 0.0f)) rinv = ds{0.f, 0.f};
         const ds rinv2 = ds_sqr(rinv);
@@ -482,12 +486,12 @@ struct ModeDS {
         const ds mr3 = ds_mul(mr, rinv2);
         const ds t = ds_mul_f(ds_mul(rv, rinv2), -3.0f);
         T.p = ds_add_sloppy(T.p, mr);
-        T.ax = ds_add_sloppy(T.ax, ds_mul(mr3, dx));
-        T.ay = ds_add_sloppy(T.ay, ds_mul(mr3, dy));
-        T.az = ds_add_sloppy(T.az, ds_mul(mr3, dz));
-        T.jx = ds_add_sloppy(T.jx, ds_mul(mr3, ds_add_sloppy(ux, ds_mul(t, dx))));
-        T.jy = ds_add_sloppy(T.jy, ds_mul(mr3, ds_add_sloppy(uy, ds_mul(t, dy))));
-        T.jz = ds_add_sloppy(T.jz, ds_mul(mr3, ds_add_sloppy(uz, ds_mul(t, dz))));
+        T.ax = ds_add_sloppy(T.ax, ds_mul_raw(mr3, dx));
+        T.ay = ds_add_sloppy(T.ay, ds_mul_raw(mr3, dy));
+        T.az = ds_add_sloppy(T.az, ds_mul_raw(mr3, dz));
+        T.jx = ds_add_sloppy(T.jx, ds_mul_raw(mr3, ds_add_sloppy(ux, ds_mul_raw(t, dx))));
+        T.jy = ds_add_sloppy(T.jy, ds_mul_raw(mr3, ds_add_sloppy(uy, ds_mul_raw(t, dy))));
+        T.jz = ds_add_sloppy(T.jz, ds_mul_raw(mr3, ds_add_sloppy(uz, ds_mul_raw(t, dz))));
     }
     __device__ static void fold(Sum &S, const Tile &T) {
         S.ax = ds_add(S.ax, T.ax); S.ay = ds_add(S.ay, T.ay); S.az = ds_add(S.az, T.az);
@@ -497,8 +501,8 @@ struct ModeDS {
     __device__ static void remove_self(Sum &S, const I &i, ds eps2) {
         // the self pair's r2 is eps2 + 0 + 0 + 0, computed as in interact()
         const ds z{0.f, 0.f};
-        const ds r2 = ds_add_sloppy(ds_add_sloppy(ds_add_sloppy(eps2, ds_sqr(z)), ds_sqr(z)),
-                                    ds_sqr(z));
+        const ds r2 = ds_add_sloppy(
+            ds_add_sloppy(ds_add_sloppy(eps2, ds_sqr_raw(z)), ds_sqr_raw(z)), ds_sqr_raw(z));
         S.p = ds_sub(S.p, ds_mul(i.m, ds_rsqrt(r2)));
     }
     __device__ static Out7 out(const Sum &S) {
