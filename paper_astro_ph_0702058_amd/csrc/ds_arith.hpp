@@ -74,8 +74,9 @@ __device__ __forceinline__ ds ds_mul(ds a, ds b) {
 }
 
 // The same products before their final renormalisation: hi + lo is exactly the sum that
-// ds_mul / ds_sqr return (fast_two_sum is error-free), with |lo| up to about two units in the
-// last place of hi.  For operands of an addition, which renormalises its own result.
+// ds_mul / ds_sqr / ds_mul_f return (fast_two_sum is error-free), with |lo| up to about two
+// units in the last place of hi.  Such a value may feed an addition, which renormalises its
+// own result, or another product, whose neglected lo * lo term stays below about 2^-44 of it.
 __device__ __forceinline__ ds ds_mul_raw(ds a, ds b) {
     ds p = two_prod(a.hi, b.hi);
     p.lo = __builtin_fmaf(a.hi, b.lo, p.lo);
@@ -86,6 +87,12 @@ __device__ __forceinline__ ds ds_mul_raw(ds a, ds b) {
 __device__ __forceinline__ ds ds_sqr_raw(ds a) {
     ds p = two_prod(a.hi, a.hi);
     p.lo = __builtin_fmaf(a.hi + a.hi, a.lo, p.lo);
+    return p;
+}
+
+__device__ __forceinline__ ds ds_mul_f_raw(ds a, float b) {
+    ds p = two_prod(a.hi, b);
+    p.lo = __builtin_fmaf(a.lo, b, p.lo);
     return p;
 }
 

@@ -467,8 +467,8 @@ struct ModeDS {
     __device__ static __forceinline__ void pair(const I &i, const J &j, ds eps2, Tile &T) {
         const float4 h = j.h, l = j.l, vh = j.vh, vl = j.vl;
         // separations: the high parts' difference is exact (two_sum), the low parts' adds one
-        // rounding of about 2^-48 |x|; products that only feed an addition skip their own
-        // renormalisation
+        // rounding of about 2^-48 |x|; products skip their own renormalisation (the additions
+        // renormalise)
         const ds dx = ds_add_sloppy(ds{h.x, l.x}, ds_neg(i.x));
         const ds dy = ds_add_sloppy(ds{h.y, l.y}, ds_neg(i.y));
         const ds dz = ds_add_sloppy(ds{h.z, l.z}, ds_neg(i.z));
@@ -481,10 +481,10 @@ struct ModeDS {
                                     ds_mul_raw(dz, uz));
         ds rinv = ds_rsqrt(r2);
         if (!SOFT && !(r2.hi > 0.0f)) rinv = ds{0.f, 0.f};
-        const ds rinv2 = ds_sqr(rinv);
-        const ds mr = ds_mul(ds{h.w, l.w}, rinv);
-        const ds mr3 = ds_mul(mr, rinv2);
-        const ds t = ds_mul_f(ds_mul(rv, rinv2), -3.0f);
+        const ds rinv2 = ds_sqr_raw(rinv);
+        const ds mr = ds_mul_raw(ds{h.w, l.w}, rinv);
+        const ds mr3 = ds_mul_raw(mr, rinv2);
+        const ds t = ds_mul_f_raw(ds_mul_raw(rv, rinv2), -3.0f);
         T.p = ds_add_sloppy(T.p, mr);
         T.ax = ds_add_sloppy(T.ax, ds_mul_raw(mr3, dx));
         T.ay = ds_add_sloppy(T.ay, ds_mul_raw(mr3, dy));
