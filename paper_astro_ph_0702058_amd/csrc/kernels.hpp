@@ -522,18 +522,14 @@ struct ModeDS {
 };
 
 // ------------------------------------------------------------------------------------------
-// FP64 interaction: IEEE double throughout; s^(-1/2) from the hardware estimate refined by two
-// Newton steps.
+// FP64 interaction: IEEE double throughout; s^(-1/2) from the hardware estimate refined by one
+// correction step of third order, y = y0 (1 + r/2 + 3 r^2/8) with r = 1 - s y0^2 (relative
+// error about 5/16 of the estimate's cubed).
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ double rsqrt_f64(double s) {
-    double y = __builtin_amdgcn_rsq(s);
-    double h = s * y;
-    double r = __builtin_fma(-h, y, 1.0);
-    y = __builtin_fma(0.5 * y, r, y);
-    h = s * y;
-    r = __builtin_fma(-h, y, 1.0);
-    y = __builtin_fma(0.5 * y, r, y);
-    return y;
+    const double y = __builtin_amdgcn_rsq(s);
+    const double r = __builtin_fma(-(s * y), y, 1.0);
+    return __builtin_fma(y * r, __builtin_fma(0.375, r, 0.5), y);
 }
 
 struct ModeF64 {
