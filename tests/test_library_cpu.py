@@ -87,3 +87,19 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_committed_profiles_match_the_kernel_source():
+    """The committed HBM-traffic summary of the full-force launch was taken on the current
+    kernel source (bench.py reports its figure only then), and every committed summary names
+    the command that produced it."""
+    import json
+    from paper_astro_ph_0702058_amd.profiling import kernel_source_hash
+    prof = os.path.join(ROOT, "profiles")
+    t = json.load(open(os.path.join(prof, "force_full_fp32_plummer_n1048576_traffic.json")))
+    assert t["kernel_source_sha256_16"] == kernel_source_hash()
+    assert t["variant"] == {"ipl": 1, "unroll": 2, "target": 65536, "kmax": 64}
+    assert set(t["commands"]) == {"FETCH_SIZE", "WRITE_SIZE"}
+    for name in os.listdir(prof):
+        if name.endswith(".txt"):
+            assert "# command: " in open(os.path.join(prof, name)).read(), name
