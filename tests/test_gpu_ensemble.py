@@ -37,11 +37,11 @@ def run_ensemble(sizes, eps, eta, t_end, prec, lmin=3, layout=None, graph=True, 
     return xs, vs, ms, g, ctl, e0, e1
 
 
-def check_against_oracle_runs(sizes, t_end):
-    """FP64 interaction, eps = 1/N_c, eta = 0.02: every cluster follows its own oracle run
-    step for step (levels, ticks, positions, energies)."""
+def check_against_oracle_runs(sizes, t_end, prec="fp64"):
+    """eps = 1/N_c, eta = 0.02: every cluster follows its own oracle run step for step
+    (levels, ticks, positions, energies)."""
     eps = [1.0 / n for n in sizes]
-    xs, vs, ms, g, ctl, e0, e1 = run_ensemble(sizes, eps, 0.02, t_end, "fp64")
+    xs, vs, ms, g, ctl, e0, e1 = run_ensemble(sizes, eps, 0.02, t_end, prec)
     off = np.concatenate([[0], np.cumsum(sizes)])
     for c, n in enumerate(sizes):
         ref = oracle.BlockIntegrator(xs[c], vs[c], ms[c], eps=eps[c], nu=0.02, lmin=3)
@@ -61,6 +61,12 @@ def test_ensemble_fp64_matches_independent_oracle_runs():
     """Six clusters of uneven size (tiles plus ragged tails, last tiles of one particle), to
     t = 1/8."""
     check_against_oracle_runs([64, 100, 257, 300, 513, 1000], 0.125)
+
+
+def test_ensemble_double_single_matches_independent_oracle_runs():
+    """The double-single interaction (forces to about 1e-14 of the FP64 oracle's) keeps every
+    cluster on its oracle run step for step as well, to t = 1/8."""
+    check_against_oracle_runs([64, 257, 700, 1000], 0.125, "ds")
 
 
 def test_ensemble_whole_tiles_and_tiny_clusters():
