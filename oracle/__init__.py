@@ -38,6 +38,7 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     sig = {
         "orc_force": (None, [_I64, _i64, _I64, _d, _d, _d, _D, _d, _d, _d]),
+        "orc_force_scale": (None, [_I64, _i64, _I64, _d, _d, _d, _D, _d, _d]),
         "orc_energy": (None, [_I64, _d, _d, _d, _D, _d, _d]),
         "orc_predict": (None, [_I64, _d, _d, _d, _d, _i64, _I64, _D, _d, _d]),
         "orc_correct": (None, [_I64, _i64, _i32, _d, _d, _d, _d, _d, _d, _d, _d, _d, _d, _d]),
@@ -88,6 +89,21 @@ def force(x, v, m, eps2, idx=None):
     lib.orc_force(ni, _p(idx, _i64), n, _p(x), _p(v), _p(m), float(eps2), _p(acc), _p(jerk),
                   _p(pot))
     return acc, jerk, pot
+
+
+def force_scale(x, v, m, eps2, idx=None):
+    """Sum over j != i of the sizes of the terms of Eq. Force on the particles ``idx`` (all if
+    None): (sa (n_i,), sk (n_i,)) with sa_i = sum_j m_j |d| s^-3/2 and
+    sk_i = sum_j m_j (|u| s^-3/2 + 3 |d.u| |d| s^-5/2).  A sum of terms each rounded to a
+    relative u is off by at most about u times this scale, however much the terms cancel."""
+    lib = _load()
+    x = _f64(x, (-1, 3)); v = _f64(v, (-1, 3)); m = _f64(m)
+    n = x.shape[0]
+    idx = np.arange(n, dtype=np.int64) if idx is None else np.ascontiguousarray(idx, np.int64)
+    ni = idx.shape[0]
+    sa = np.zeros(ni); sk = np.zeros(ni)
+    lib.orc_force_scale(ni, _p(idx, _i64), n, _p(x), _p(v), _p(m), float(eps2), _p(sa), _p(sk))
+    return sa, sk
 
 
 def energy(x, v, m, eps2):

@@ -98,6 +98,42 @@ void orc_force(int64_t n_i, const int64_t *idx, int64_t n, const double *x, cons
 }
 
 /* ------------------------------------------------------------------------------------------
+ * Size of the terms of Eq. Force on each listed i, the scale against which the rounding of a
+ * sum of those terms is measured (a sum of terms rounded to relative u has an error of at most
+ * about u times the sum of the terms' magnitudes, however much the terms cancel):
+ *   sa_i = sum_{j != i} m_j |d| s^{-3/2}                                (the pulls' sizes)
+ *   sk_i = sum_{j != i} m_j ( |u| s^{-3/2} + 3 |d.u| |d| s^{-5/2} )    (both jerk parts)
+ * with d, u, s as in orc_force.
+ * ------------------------------------------------------------------------------------------ */
+void orc_force_scale(int64_t n_i, const int64_t *idx, int64_t n, const double *x,
+                     const double *v, const double *m, double eps2, double *sa, double *sk)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t q = 0; q < n_i; ++q) {
+        const int64_t i = idx[q];
+        acc_t a = 0, k = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double dx = x[3 * j + 0] - x[3 * i + 0];
+            const double dy = x[3 * j + 1] - x[3 * i + 1];
+            const double dz = x[3 * j + 2] - x[3 * i + 2];
+            const double ux = v[3 * j + 0] - v[3 * i + 0];
+            const double uy = v[3 * j + 1] - v[3 * i + 1];
+            const double uz = v[3 * j + 2] - v[3 * i + 2];
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double s = r2 + eps2;
+            const double inv_r3 = 1.0 / (s * sqrt(s));
+            const double dist = sqrt(r2), speed = sqrt(ux * ux + uy * uy + uz * uz);
+            const double du = fabs(dx * ux + dy * uy + dz * uz);
+            a += m[j] * dist * inv_r3;
+            k += m[j] * (speed * inv_r3 + 3.0 * du * dist * inv_r3 / s);
+        }
+        sa[q] = (double)a;
+        sk[q] = (double)k;
+    }
+}
+
+/* ------------------------------------------------------------------------------------------
  * Sec. 4.2 energy diagnostic: kinetic energy sum_i m_i |v_i|^2 / 2 and potential energy
  * -1/2 sum_i sum_{j != i} m_i m_j s^{-1/2} (softened, the same potential the force derives
  * from).  Written to ekin and epot.

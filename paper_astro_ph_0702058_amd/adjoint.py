@@ -55,8 +55,8 @@ class SharedRunner:
     def backward(self, x0, v0, m, checkpoints, gx, gv):
         """Adjoints (x0_bar, v0_bar, m_bar) from those of the final positions and velocities."""
         n = self.n
-        xb = gx.clone() if gx is not None else torch.zeros((3, n), dtype=torch.float64, device="cuda")
-        vb = gv.clone() if gv is not None else torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        xb = gx.clone(memory_format=torch.contiguous_format) if gx is not None else torch.zeros((3, n), dtype=torch.float64, device="cuda")
+        vb = gv.clone(memory_format=torch.contiguous_format) if gv is not None else torch.zeros((3, n), dtype=torch.float64, device="cuda")
         ab = torch.zeros((3, n), dtype=torch.float64, device="cuda")
         kb = torch.zeros_like(ab)
         mb = torch.zeros(n, dtype=torch.float64, device="cuda")

@@ -142,6 +142,49 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _device_tensor(t, name, dtype, shape=None):
+    """Raise unless t is a contiguous GPU tensor of this dtype (and shape): the library reads
+    and writes through raw device pointers, so a host tensor or another element type would be
+    misread on the device."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: dtype must be {dtype} (got {t.dtype})")
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a GPU tensor (got device {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape must be {tuple(shape)} (got {tuple(t.shape)})")
+
+
+def check_force_args(n, acc, jerk, pot, i_idx, n_i, n_i_max):
+    """Validate nb_force arguments on the host before anything is enqueued.  acc, jerk:
+    (3, n_i_max) float64 GPU tensors; pot: (n_i_max,).  i_idx: None (rows 0 .. n_i - 1), a
+    device address (int, not checkable here), or an int32 GPU tensor of at least n_i_max
+    entries (checked to lie in [0, n) when it is a tensor and no device count is given).  n_i:
+    None, a device address, or an int32 GPU tensor of one or more entries."""
+    torch = _torch()
+    if not 0 <= n_i_max <= n:
+        raise ValueError(f"n_i_max {n_i_max} outside [0, {n}]")
+    _device_tensor(acc, "acc", torch.float64, (3, n_i_max))
+    _device_tensor(jerk, "jerk", torch.float64, (3, n_i_max))
+    _device_tensor(pot, "pot", torch.float64, (n_i_max,))
+    if n_i is not None and not isinstance(n_i, int):
+        _device_tensor(n_i, "n_i", torch.int32)
+        if n_i.numel() < 1:
+            raise ValueError("n_i: needs one entry")
+    if i_idx is not None and not isinstance(i_idx, int):
+        _device_tensor(i_idx, "i_idx", torch.int32)
+        if i_idx.dim() != 1 or i_idx.numel() < (n_i_max if n_i is None else 1):
+            raise ValueError(f"i_idx: a 1-D list of at least {n_i_max} entries is required")
+        if n_i is None and n_i_max > 0:
+            lo, hi = int(i_idx[:n_i_max].min()), int(i_idx[:n_i_max].max())
+            if lo < 0 or hi >= n:
+                raise ValueError(f"i_idx: indices must lie in [0, {n}) (got {lo} .. {hi})")
+
+
 class DeviceState:
     """FP64 master state on the GPU as torch tensors, structure-of-arrays:
     x, v, a, k: (3, n) float64; m, pot: (n,) float64; tick: (n,) int64; level: (n,) int32."""
@@ -260,20 +303,25 @@ class Context:
 
     def nb_predict(self, t=None):
         """Predict all particles to the device int64 tensor t (ticks), or to the block time."""
+        if t is not None:
+            _device_tensor(t, "t", _torch().int64)
         self._check(self.lib.nb_predict(self.h, _ptr(t)))
 
     def nb_force(self, acc, jerk, pot, i_idx=None, n_i=None, n_i_max=None):
         """acc, jerk: (3, n_i_max) float64 tensors; pot: (n_i_max,).  i_idx: int32 tensor or a
         device address; n_i: int32 device tensor/address (or None = n_i_max)."""
         n_i_max = acc.shape[1] if n_i_max is None else int(n_i_max)
-        assert acc.shape == (3, n_i_max) and jerk.shape == (3, n_i_max) and pot.shape == (n_i_max,)
-        for t in (acc, jerk, pot):
-            assert t.dtype == _torch().float64 and t.is_contiguous()
+        check_force_args(self.n, acc, jerk, pot, i_idx, n_i, n_i_max)
         ii = ctypes.c_void_p(i_idx) if isinstance(i_idx, int) else _ptr(i_idx)
         nn = ctypes.c_void_p(n_i) if isinstance(n_i, int) else _ptr(n_i)
         self._check(self.lib.nb_force(self.h, ii, nn, n_i_max, _ptr(acc), _ptr(jerk), _ptr(pot)))
 
     def nb_correct(self, acc, jerk, pot):
+        """acc, jerk: (3, n) float64 GPU tensors (the block's rows first), pot: (n,)."""
+        torch = _torch()
+        _device_tensor(acc, "acc", torch.float64, (3, self.n))
+        _device_tensor(jerk, "jerk", torch.float64, (3, self.n))
+        _device_tensor(pot, "pot", torch.float64, (self.n,))
         self._check(self.lib.nb_correct(self.h, _ptr(acc), _ptr(jerk), _ptr(pot)))
 
     def nb_step(self, eta, nsteps=1, use_graph=True):
@@ -318,11 +366,19 @@ class Context:
 
     def nb_force_vjp(self, abar, kbar, xbar, vbar, mbar):
         """Adds the force VJP at the predicted stream to xbar, vbar (3, n) and mbar (n,)."""
+        torch = _torch()
+        for t, name in ((abar, "abar"), (kbar, "kbar"), (xbar, "xbar"), (vbar, "vbar")):
+            _device_tensor(t, name, torch.float64, (3, self.n))
+        _device_tensor(mbar, "mbar", torch.float64, (self.n,))
         self._check(self.lib.nb_force_vjp(self.h, _ptr(abar), _ptr(kbar), _ptr(xbar), _ptr(vbar),
                                           _ptr(mbar)))
 
     def nb_step_vjp(self, dt, xbar, vbar, abar, kbar, mbar):
         """In place: output adjoints of one shared step from the bound state -> input adjoints."""
+        torch = _torch()
+        for t, name in ((xbar, "xbar"), (vbar, "vbar"), (abar, "abar"), (kbar, "kbar")):
+            _device_tensor(t, name, torch.float64, (3, self.n))
+        _device_tensor(mbar, "mbar", torch.float64, (self.n,))
         self._check(self.lib.nb_step_vjp(self.h, float(dt), _ptr(xbar), _ptr(vbar), _ptr(abar),
                                          _ptr(kbar), _ptr(mbar)))
 

@@ -13,20 +13,14 @@ import numpy as np
 import pytest
 import torch
 
-import oracle
 from paper_astro_ph_0702058_amd import nbody
 from paper_astro_ph_0702058_amd.plummer import plummer, sample_indices
+from _parity import check, reference
 
 pytestmark = pytest.mark.gpu
 
 VARIANTS = [dict(ipl=i, unroll=u, target=t, kmax=65536)
             for i in (1, 2) for u in (1, 2) for t in (8, 256, 4096)]
-
-
-def rms_rel(got, ref):
-    if got.ndim == 1:
-        return float(np.sqrt(np.mean(((got - ref) / ref) ** 2)))
-    return float(np.sqrt(np.mean(np.sum((got - ref) ** 2, 1) / np.sum(ref ** 2, 1))))
 
 
 def forces(ctx, n, idx, which):
@@ -65,12 +59,9 @@ def test_bitwise_identical_across_variants(eps, count):
             for which in (0, 1):
                 ctx.nb_set_variant(which, var)
                 results.append((var, which, forces(ctx, n, idx, which)))
-    ref = oracle.force(x, v, m, eps * eps, idx=idx)
+    ref, scale = reference(x, v, m, eps * eps, idx=idx)
     first = results[0][2]
-    e = [rms_rel(first[c], ref[c]) for c in range(3)]
-    print(f"count={count} eps={eps}: e_acc={e[0]:.3e} e_jerk={e[1]:.3e} e_pot={e[2]:.3e}",
-          flush=True)
-    assert e[0] <= 2e-6 and e[1] <= 1e-5 and e[2] <= 2e-6
+    check("fp32", first, ref, scale, f"fp32fixed count={count} eps={eps}")
     for var, which, got in results[1:]:
         for c in range(3):
             assert np.array_equal(got[c], first[c]), (var, which, c)
@@ -94,10 +85,8 @@ def test_full_size_sampled_and_same_as_block_class():
         ii = torch.as_tensor(idx, device="cuda")
         full = (acc[:, ii].cpu().numpy().T, jerk[:, ii].cpu().numpy().T, pot[ii].cpu().numpy())
         blk = forces(ctx, n, idx, 1)
-    ref = oracle.force(x, v, m, (1 / 256) ** 2, idx=idx)
-    e = [rms_rel(full[c], ref[c]) for c in range(3)]
-    print(f"N=2^20: e_acc={e[0]:.3e} e_jerk={e[1]:.3e} e_pot={e[2]:.3e}", flush=True)
-    assert e[0] <= 2e-6 and e[1] <= 1e-5 and e[2] <= 2e-6
+    ref, scale = reference(x, v, m, (1 / 256) ** 2, idx=idx)
+    check("fp32", full, ref, scale, "fp32fixed N=2^20")
     for c in range(3):
         assert np.array_equal(full[c], blk[c]), c
 

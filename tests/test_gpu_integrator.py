@@ -43,9 +43,12 @@ def test_init_levels_and_first_block(prec):
     ctx.nb_init(nu)
     g = st.numpy()
     ref = oracle.BlockIntegrator(x, v, m, eps=eps, nu=nu, lmin=lmin)
-    tol = 1e-13 if prec == "fp64" else 2e-5
-    assert np.sqrt(np.mean(np.sum((g["a"] - ref.a) ** 2, 1) / np.sum(ref.a ** 2, 1))) < tol
-    assert np.sqrt(np.mean(np.sum((g["k"] - ref.k) ** 2, 1) / np.sum(ref.k ** 2, 1))) < 10 * tol
+    # the initial force: the targets of the interaction arithmetic (fp32: acc 2e-6, jerk 1e-5)
+    tol_a, tol_k = (1e-13, 1e-12) if prec == "fp64" else (2e-6, 1e-5)
+    e_a = np.sqrt(np.mean(np.sum((g["a"] - ref.a) ** 2, 1) / np.sum(ref.a ** 2, 1)))
+    e_k = np.sqrt(np.mean(np.sum((g["k"] - ref.k) ** 2, 1) / np.sum(ref.k ** 2, 1)))
+    print(f"{prec} init: e_acc={e_a:.3e} e_jerk={e_k:.3e}", flush=True)
+    assert e_a < tol_a and e_k < tol_k
     assert np.all(g["tick"] == 0)
     dt0 = np.array([oracle.initial_dt(nu, ref.a[i], ref.k[i]) for i in range(n)])
     diff = g["level"] != ref.level

@@ -7,20 +7,24 @@ dt <= 1/8, integrated to t = 1 by the device-resident loop.
    time, then sums over all j.  Blocks are not a uniform sample: the first ones hold the
    particles with the smallest steps, e.g. one near the centre whose pulls cancel to a tiny
    |a| (dt = nu |a|/|k|), where rounding of size u * sum_j |a_ij| is large against |a|.  So
-   every sampled block must meet the force tolerances on the error measured against the sum of
-   the magnitudes of the terms, e = sqrt(mean_i |a_i - a_i^ref|^2 / (sum_j |a_ij|)^2) (jerk
-   alike; the potential terms share one sign, so its relative error is that already), and the
-   blocks at t = 1/64 and 1/16, which hold every particle of level <= 6 or <= 4, must also meet
-   them on the plain rms relative error.
+   every sampled row of every sampled block must meet the force tolerances on its error
+   measured against the size of its terms (|a_i - a_i^ref| / sa_i, with sa_i and the jerk's sk_i
+   from oracle.force_scale; the potential terms share one sign, so its relative error is that
+   already), and the blocks at t = 1/64 and 1/16, which hold every particle of level <= 6 or
+   <= 4, must also meet them on the plain rms relative error.
 2. The first 300 block steps in FP64 follow the oracle step for step (same block times, same
    levels and ticks, positions to 1e-10): the trajectories have not yet parted.
 3. The whole run to t = 1 against the committed FP64 oracle run of the same initial conditions
    (tests/golden/plummer_runs.json, written by make_plummer_reference.py from the oracle only).
-   Over t = 1 the trajectories of a 65536-body system part, and the block-step count is set
-   by the few tightest pairs (a single close pair at level l adds 2^l / 8 block times), so
-   what is compared is what the bulk fixes: the total number of particle steps within 5 %, the
-   block-step count within 25 %, and the energy error within a factor 10 of the oracle's (at
-   eps = 1e-3 it is the integrator's, from close encounters, not the arithmetic's).
+   FP64 and double-single interactions (force errors 1e-16 and 1e-15 relative) take the
+   oracle's decisions at every block: exactly its block steps and particle steps, and its
+   energy error to 1e-3 relative.  Single precision (force errors ~2e-8) eventually decides a
+   level differently where the criterion lies within its rounding of a power of two; from then
+   on the trajectories part, and the block-step count is set by the few tightest pairs (a
+   single close pair at level l adds 2^l / 8 block times), so for it what is compared is what
+   the bulk fixes: the total number of particle steps within 5 %, the block-step count within
+   25 %, and the energy error within a factor 10 of the oracle's (at eps = 1e-3 it is the
+   integrator's, from close encounters, not the arithmetic's).
 """
 import json
 import os
@@ -31,29 +35,13 @@ import pytest
 import oracle
 from paper_astro_ph_0702058_amd import nbody
 from paper_astro_ph_0702058_amd.plummer import plummer, sample_indices
+from _parity import row_errors
 
 pytestmark = pytest.mark.gpu
 
 N, SEED, EPS, NU, LMIN, LMAX, T_END = 65536, 2, 1e-3, 0.01, 3, 26, 1.0
 TOL = {"fp32": (2e-6, 1e-5, 2e-6), "ds": (1e-11, 1e-10, 1e-11), "fp64": (1e-13, 1e-13, 1e-13)}
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plummer_runs.json")
-
-
-def term_magnitude_sums(xp, vp, m, rows, eps=EPS, chunk=32):
-    """sum_j |a_ij| and sum_j |k_ij| over j != i for the listed i (FP64, chunks of rows)."""
-    sa = np.empty(len(rows)); sk = np.empty(len(rows))
-    for c0 in range(0, len(rows), chunk):
-        r = rows[c0:c0 + chunk]
-        d = xp[None, :, :] - xp[r][:, None, :]
-        u = vp[None, :, :] - vp[r][:, None, :]
-        s = np.sum(d * d, axis=2) + eps * eps
-        s[np.arange(len(r)), r] = np.inf          # drop j = i
-        w3 = m[None, :] * s ** -1.5
-        rv = np.sum(d * u, axis=2)
-        sa[c0:c0 + chunk] = np.sum(w3 * np.linalg.norm(d, axis=2), axis=1)
-        kv = w3[:, :, None] * (u - 3.0 * (rv / s)[:, :, None] * d)
-        sk[c0:c0 + chunk] = np.sum(np.linalg.norm(kv, axis=2), axis=1)
-    return sa, sk
 
 
 def rms_rel(got, ref):
@@ -96,17 +84,18 @@ def test_block_forces_inside_run(prec):
             gk = jerk[:, :c.n_act].cpu().numpy().T[rows]
             gp = pot[:c.n_act].cpu().numpy()[rows]
             xp, vp = oracle.predict(g["x"], g["v"], g["a"], g["k"], g["tick"], c.t_next, LMAX)
-            ra, rk, rp = oracle.force(xp, vp, m, EPS * EPS, idx=blk[rows])
-            sa, sk = term_magnitude_sums(xp, vp, m, blk[rows])
-            ea_s = float(np.sqrt(np.mean(np.sum((ga - ra) ** 2, 1) / sa ** 2)))
-            ek_s = float(np.sqrt(np.mean(np.sum((gk - rk) ** 2, 1) / sk ** 2)))
-            ea, ek, ep = rms_rel(ga, ra), rms_rel(gk, rk), rms_rel(gp, rp)
-            cond = float(np.median(sa / np.linalg.norm(ra, axis=1)))
+            ref = oracle.force(xp, vp, m, EPS * EPS, idx=blk[rows])
+            scale = oracle.force_scale(xp, vp, m, EPS * EPS, idx=blk[rows])
+            ea_w, ek_w, ep_w = (float(e.max()) for e in row_errors((ga, gk, gp), ref, scale))
+            ea, ek, ep = rms_rel(ga, ref[0]), rms_rel(gk, ref[1]), rms_rel(gp, ref[2])
+            cond = float(np.median(scale[0] / np.linalg.norm(ref[0], axis=1)))
             print(f"{prec} {kind} {where:g}: n_act={c.n_act} t={c.t_next / 2.0 ** LMAX:.6f} "
-                  f"scaled e_acc={ea_s:.3e} e_jerk={ek_s:.3e}; e_acc={ea:.3e} e_jerk={ek:.3e} "
-                  f"e_pot={ep:.3e}; median sum|a_ij|/|a| {cond:.1f}", flush=True)
+                  f"worst row scaled acc {ea_w:.3e} jerk {ek_w:.3e} pot {ep_w:.3e}; rms e_acc="
+                  f"{ea:.3e} e_jerk={ek:.3e} e_pot={ep:.3e}; median sum|a_ij|/|a| {cond:.1f}",
+                  flush=True)
             ta, tk, tp = TOL[prec]
-            assert ea_s <= ta and ek_s <= tk and ep <= tp, (kind, where, ea_s, ek_s, ep)
+            assert ea_w <= ta and ek_w <= tk and ep_w <= tp and ep <= tp, \
+                (kind, where, ea_w, ek_w, ep_w, ep)
             if kind == "time":
                 assert ea <= ta and ek <= tk, (where, ea, ek)
 
@@ -157,9 +146,13 @@ def test_run_to_t1_against_oracle_run(prec):
     print(f"{prec}: steps {c.n_steps} vs {ref['n_steps']}; particle steps {c.n_active_sum} vs "
           f"{ref['n_active_sum']}; dE/E {de:.3e} vs {ref['de_rel']:.3e}", flush=True)
     assert c.t_cur == int(T_END * 2 ** LMAX) and np.all(g["tick"] == c.t_cur)
-    assert abs(c.n_active_sum - ref["n_active_sum"]) <= 0.05 * ref["n_active_sum"]
-    assert abs(c.n_steps - ref["n_steps"]) <= 0.25 * ref["n_steps"]
-    assert abs(de) <= 10 * abs(ref["de_rel"])
+    if prec in ("fp64", "ds"):
+        assert c.n_steps == ref["n_steps"] and c.n_active_sum == ref["n_active_sum"]
+        assert abs(de - ref["de_rel"]) <= 1e-3 * abs(ref["de_rel"])
+    else:
+        assert abs(c.n_active_sum - ref["n_active_sum"]) <= 0.05 * ref["n_active_sum"]
+        assert abs(c.n_steps - ref["n_steps"]) <= 0.25 * ref["n_steps"]
+        assert abs(de) <= 10 * abs(ref["de_rel"])
 
 
 def test_block_forces_at_full_size():
@@ -196,16 +189,15 @@ def test_block_forces_at_full_size():
             gk = jerk[:, :c.n_act].cpu().numpy().T[rows]
             gp = pot[:c.n_act].cpu().numpy()[rows]
             xp, vp = oracle.predict(g["x"], g["v"], g["a"], g["k"], g["tick"], c.t_next, LMAX)
-            ra, rk, rp = oracle.force(xp, vp, m, eps * eps, idx=blk[rows])
-            ea, ek, ep = rms_rel(ga, ra), rms_rel(gk, rk), rms_rel(gp, rp)
-            k64 = slice(0, min(64, len(rows)))
-            sa, sk = term_magnitude_sums(xp, vp, m, blk[rows][k64], eps=eps, chunk=4)
-            ea_s = float(np.sqrt(np.mean(np.sum((ga[k64] - ra[k64]) ** 2, 1) / sa ** 2)))
-            ek_s = float(np.sqrt(np.mean(np.sum((gk[k64] - rk[k64]) ** 2, 1) / sk ** 2)))
+            ref = oracle.force(xp, vp, m, eps * eps, idx=blk[rows])
+            scale = oracle.force_scale(xp, vp, m, eps * eps, idx=blk[rows])
+            ea, ek, ep = rms_rel(ga, ref[0]), rms_rel(gk, ref[1]), rms_rel(gp, ref[2])
+            ea_w, ek_w, ep_w = (float(e.max()) for e in row_errors((ga, gk, gp), ref, scale))
             print(f"N=2^20 {kind} {where:g}: n_act={c.n_act} e_acc={ea:.3e} e_jerk={ek:.3e} "
-                  f"e_pot={ep:.3e}; scaled (64 rows) e_acc={ea_s:.3e} e_jerk={ek_s:.3e}", flush=True)
+                  f"e_pot={ep:.3e}; worst row scaled acc {ea_w:.3e} jerk {ek_w:.3e} "
+                  f"pot {ep_w:.3e}", flush=True)
             ta, tk, tp = TOL["fp32"]
-            assert ep <= tp and ea_s <= ta and ek_s <= tk
+            assert ep <= tp and ea_w <= ta and ek_w <= tk and ep_w <= tp
             if kind == "time":
                 assert c.t_next == int(where * 2 ** LMAX)
                 assert ea <= ta and ek <= tk

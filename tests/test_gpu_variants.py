@@ -4,20 +4,15 @@ import numpy as np
 import pytest
 import torch
 
-import oracle
 from paper_astro_ph_0702058_amd import nbody
 from paper_astro_ph_0702058_amd.plummer import plummer, sample_indices
+from _parity import check, reference
 
 pytestmark = pytest.mark.gpu
 
-TOL_ACC = {"fp32": 2e-6, "ds": 1e-11, "fp64": 1e-13}
 F32 = [(i, u) for i in (1, 2) for u in (1, 2, 4)] + [(4, 1), (4, 2)]
 OTHER = [(1, u) for u in (1, 2)]
 CASES = [("fp32",) + c for c in F32] + [("ds",) + c for c in OTHER] + [("fp64",) + c for c in OTHER]
-
-
-def rms_rel(got, ref):
-    return float(np.sqrt(np.mean(np.sum((got - ref) ** 2, 1) / np.sum(ref ** 2, 1))))
 
 
 @pytest.mark.parametrize("prec,ipl,unr", CASES)
@@ -43,10 +38,10 @@ def test_variant_parity(prec, ipl, unr, target, count):
         jerk = torch.zeros_like(acc); pot = torch.zeros(n, dtype=torch.float64, device="cuda")
         ctx.nb_force(acc, jerk, pot, i_idx=ii, n_i=cnt)   # device count -> block variant
         ctx.nb_sync()
-    ra, rk, rp = oracle.force(x, v, m, eps * eps, idx=idx)
-    ga = acc[:, :idx.size].cpu().numpy().T
-    e = rms_rel(ga, ra)
-    assert e <= TOL_ACC[prec], e
+    ref, scale = reference(x, v, m, eps * eps, idx=idx)
+    got = (acc[:, :idx.size].cpu().numpy().T, jerk[:, :idx.size].cpu().numpy().T,
+           pot[:idx.size].cpu().numpy())
+    check(prec, got, ref, scale, f"ipl={ipl} unroll={unr} target={target} count={count}")
     assert np.all(acc[:, idx.size:].cpu().numpy() == 0)   # rows beyond the count untouched
 
 
@@ -80,6 +75,6 @@ def test_tuner_picks_a_working_variant():
         jerk = torch.zeros_like(acc); pot = torch.zeros(n, dtype=torch.float64, device="cuda")
         ctx.nb_force(acc, jerk, pot)
         ctx.nb_sync()
-        ga = acc.cpu().numpy().T[idx]
-    ra, _, _ = oracle.force(x, v, m, (1 / 256) ** 2, idx=idx)
-    assert rms_rel(ga, ra) <= 2e-6
+        got = (acc.cpu().numpy().T[idx], jerk.cpu().numpy().T[idx], pot.cpu().numpy()[idx])
+    ref, scale = reference(x, v, m, (1 / 256) ** 2, idx=idx)
+    check("fp32", got, ref, scale, f"tuned {chosen}")

@@ -5,6 +5,7 @@ import re
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -103,3 +104,21 @@ def test_committed_profiles_match_the_kernel_source():
     for name in os.listdir(prof):
         if name.endswith(".txt"):
             assert "# command: " in open(os.path.join(prof, name)).read(), name
+
+
+def test_binding_rejects_host_tensors_and_wrong_index_types():
+    """nb_force arguments are checked on the host before any launch: host tensors, another
+    element type (an int64 index list would be read as int32 pairs on the device), wrong shapes
+    and out-of-range indices raise; the checks need no GPU (they stop at the first problem)."""
+    import torch
+    from paper_astro_ph_0702058_amd import nbody
+    n = 8
+    acc = torch.zeros((3, n), dtype=torch.float64)
+    with pytest.raises(ValueError, match="GPU tensor"):
+        nbody.check_force_args(n, acc, acc, acc[0], None, None, n)
+    with pytest.raises(TypeError, match="dtype"):
+        nbody._device_tensor(torch.zeros(3, dtype=torch.int64), "i_idx", torch.int32)
+    with pytest.raises(ValueError, match="n_i_max"):
+        nbody.check_force_args(n, acc, acc, acc[0], None, None, n + 1)
+    with pytest.raises(TypeError, match="torch tensor"):
+        nbody.check_force_args(n, np.zeros((3, n)), acc, acc[0], None, None, n)

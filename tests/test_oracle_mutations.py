@@ -26,6 +26,9 @@ MUTATIONS = {
     "no_commensurability": ("if (t % two_dt == 0) return l - 1;", "return l - 1;"),
     "energy_double_count": ("*epot = (double)(-0.5L * w);", "*epot = (double)(-w);"),
     "initial_dt_inverted": ("return nu * na / nk;", "return nu * nk / na;"),
+    "scale_jerk_factor": ("k += m[j] * (speed * inv_r3 + 3.0 * du * dist * inv_r3 / s);",
+                          "k += m[j] * (speed * inv_r3 + du * dist * inv_r3 / s);"),
+    "scale_no_mass": ("a += m[j] * dist * inv_r3;", "a += dist * inv_r3;"),
 }
 
 

@@ -131,6 +131,37 @@ def test_subset_equals_full():
     assert np.array_equal(a[idx], a2) and np.array_equal(k[idx], k2) and np.array_equal(p[idx], p2)
 
 
+def test_force_scale_closed_form_and_bounds():
+    """The sum of the term sizes of Eq. Force (the scale of per-row error bounds).
+    Worked by hand for one pair: d = (1, 2, 2), eps^2 = 16 (s = 25, |d| = 3), m_j = 1,
+    u = (0, 0, 1) (|u| = 1, d.u = 2): sa = 3/125 = 0.024, sk = 1/125 + 3 * 2 * 3 / 3125 = 0.01376.
+    Pulls that all point one way add up to their sizes (sa = |a|); in general sa >= |a| and
+    sk >= |k| (triangle inequality), and sa scales as m and as 1/length^2 without softening."""
+    x = np.array([[0.0, 0, 0], [1.0, 2, 2]]); v = np.array([[0.0, 0, 0], [0.0, 0, 1]])
+    m = np.array([1.0, 1.0])
+    sa, sk = oracle.force_scale(x, v, m, 16.0, idx=[0])
+    assert abs(sa[0] - 0.024) < 1e-17 and abs(sk[0] - 0.01376) < 1e-17
+    # collinear pulls on particle 0 from masses on the positive x axis
+    x = np.array([[0.0, 0, 0], [0.5, 0, 0], [1.5, 0, 0], [4.0, 0, 0]])
+    v = np.array([[0.0, 0, 0], [0.1, 0, 0], [0.0, 0.3, 0], [-0.2, 0, 0.1]])
+    m = np.array([1.0, 0.3, 0.7, 2.0])
+    a, k, _ = oracle.force(x, v, m, 0.01, idx=[0])
+    sa, sk = oracle.force_scale(x, v, m, 0.01, idx=[0])
+    assert abs(sa[0] - np.linalg.norm(a[0])) <= 1e-15 * sa[0]
+    # bounds on a Plummer sphere, and the scaling laws
+    x, v, m = plummer(300, 8)
+    idx = np.array([0, 5, 77, 299])
+    a, k, _ = oracle.force(x, v, m, 1e-4, idx=idx)
+    sa, sk = oracle.force_scale(x, v, m, 1e-4, idx=idx)
+    assert np.all(sa >= np.linalg.norm(a, axis=1)) and np.all(sk >= np.linalg.norm(k, axis=1))
+    sa2, sk2 = oracle.force_scale(x, v, 3.0 * m, 1e-4, idx=idx)
+    np.testing.assert_allclose(sa2, 3.0 * sa, rtol=1e-14)
+    np.testing.assert_allclose(sk2, 3.0 * sk, rtol=1e-14)
+    s0, _ = oracle.force_scale(x, v, m, 0.0, idx=idx)
+    s1, _ = oracle.force_scale(2.0 * x, v, m, 0.0, idx=idx)
+    np.testing.assert_allclose(s1, s0 / 4.0, rtol=1e-14)
+
+
 # ------------------------------------------------------------------ energy diagnostic
 def test_energy_circular_binary():
     """Equal-mass circular binary (G = 1, m = 1/2 each, separation 1): E = -m1 m2 / (2 r)."""
