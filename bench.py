@@ -68,7 +68,7 @@ def rms_rel(got, ref):
     return float(np.sqrt(np.mean(np.sum((got - ref) ** 2, 1) / np.sum(ref ** 2, 1))))
 
 
-def bench_ensemble(args):
+def bench_ensemble(args, emit=True):
     """Ensemble workload: every cluster integrated by its own block steps to t_end; one step of
     the bench = the whole run from the initial conditions (nb_ens_init + nb_ens_run)."""
     if args.gpus != 1:
@@ -87,6 +87,9 @@ def bench_ensemble(args):
     x0, v0 = st.x.clone(), st.v.clone()
     ens = nbody.Ensemble(sizes, eps, lmin=3, precision=args.precision)
     ens.nb_ens_bind(st)
+    if args.ens_local:
+        lim, nst, wrk = (int(float(t)) for t in args.ens_local.split(","))
+        ens.nb_ens_set_local(lim, nst, wrk)
     eta = 0.02
     layout = None
     if args.tune:
@@ -125,6 +128,7 @@ def bench_ensemble(args):
         "config": {"workload": f"{args.clusters} Plummer clusters, N_c log-uniform [64, 4096] "
                                f"(total {int(sizes.sum())}), eps=1/N_c, eta=0.02, t -> {args.t_end}",
                    "clusters": args.clusters, "particles": int(sizes.sum()),
+                   "local_blocks": args.ens_local or "default",
                    "interactions_per_run": inter, "layout": layout,
                    "max_block_steps": max(c.n_steps for c in ctl),
                    "mean_block_steps": float(np.mean([c.n_steps for c in ctl])),
@@ -159,7 +163,9 @@ def bench_ensemble(args):
             "kind": "oracle",
             "sample": f"oracle on the first {done_c} clusters (N_c:time reached) "
                       f"{' '.join(desc)}, {spent:.1f} s"}
-    print(json.dumps(result), flush=True)
+    if emit:
+        print(json.dumps(result), flush=True)
+    return result
 
 
 RUNS = {
@@ -170,7 +176,7 @@ RUNS = {
 }
 
 
-def bench_run(args):
+def bench_run(args, emit=True):
     """Block-step run workload: a Plummer sphere integrated from t = 0 to t_end by the
     device-resident loop (nb_init + nb_run, graph replay).  `value` = force interactions per
     second over the whole run (sum over block steps of N times the block size, plus the N^2 of
@@ -277,7 +283,9 @@ def bench_run(args):
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"oracle init + its first {it.n_steps} block steps of the same run "
                       f"(t = 0 -> {it.time:.4g}), {el:.1f} s"}
-    print(json.dumps(result), flush=True)
+    if emit:
+        print(json.dumps(result), flush=True)
+    return result
 
 
 def bench_accuracy(args):
@@ -483,7 +491,7 @@ def bench_timed(args):
     print(json.dumps(result), flush=True)
 
 
-def bench_adjoint(args):
+def bench_adjoint(args, emit=True):
     """Differentiable run: Plummer N = 16384, eps = 1/128, 64 shared steps of 1/1024, FP32
     force; loss = mean squared distance of the final positions to a target (the end of a run
     from initial conditions perturbed by N(0, 1e-3^2)); gradient with respect to x0, v0, m
@@ -555,7 +563,9 @@ def bench_adjoint(args):
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"oracle forward of the same run: initial force + {steps} shared steps, "
                       f"{el:.1f} s (forward only)"}
-    print(json.dumps(result), flush=True)
+    if emit:
+        print(json.dumps(result), flush=True)
+    return result
 
 
 def main():
@@ -574,6 +584,10 @@ def main():
                     help="other interaction arithmetics to time once (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--error-rows", type=int, default=65536,
+                    help="rows of the N^2 force checked against the oracle (stratified)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the one-run summaries of the other workloads in the default line")
     ap.add_argument("--workload", default="full", choices=["full", "ensemble", "adjoint", "run", "accuracy", "timed"],
                     help="full: N-body force + block steps at N (default); ensemble: 512 "
                          "Plummer clusters, N_c log-uniform in [64, 4096], eps = 1/N_c, "
@@ -584,6 +598,9 @@ def main():
     ap.add_argument("--max-n", type=int, default=1 << 19)
     ap.add_argument("--run", default="n65536_t1", choices=sorted(RUNS))
     ap.add_argument("--clusters", type=int, default=512)
+    ap.add_argument("--ens-local", default="",
+                    help="ensemble local blocks: LIMIT,STEPS,WORK (nb_ens_set_local; default: "
+                         "the library's)")
     ap.add_argument("--t-end", type=float, default=1.0)
     ap.add_argument("--tune", action="store_true",
                     help="autotune the force-kernel variants first (untimed); default: the "
@@ -629,6 +646,9 @@ def main():
         chosen = autotune(ctx, cache_path=None, reps=1)
         log(f"[bench] tuned in {time.perf_counter() - t_tune:.1f} s: {chosen}")
     variant_full, variant_block = ctx.nb_get_variant(0), ctx.nb_get_variant(1)
+    # the device's FP32 FMA rate from the library's calibration kernel (before the timed region)
+    fma_tflops = ctx.nb_fma_rate()
+    log(f"[bench] measured FP32 FMA rate {fma_tflops:.1f} TFLOP/s")
 
     def step():
         st.x.copy_(x0)
@@ -670,6 +690,8 @@ def main():
     roofline = {"bound": "alu", "kernel": kernel_sym, "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": traffic,
+                "measured_fma_peak": round(fma_tflops, 2),
+                "frac_of_measured_fma_peak": round(achieved / fma_tflops, 4),
                 "launches": full_n, "avg_launch_ms": round(avg_full_ms, 3),
                 "flop_per_interaction": FLOP_PER_INTERACTION,
                 "interactions_per_launch": n * n,
@@ -728,32 +750,35 @@ def main():
         variants[prec] = {"interactions_per_s": rate, "full_force_ms": ms, "gv": gv}
         log(f"[bench] {prec}: full force {ms:.1f} ms, {rate:.3e} interactions/s")
 
-    # CPU oracle on a bounded sample of i (all j): timing and the accuracy reference
+    # CPU oracle on a stratified sample of i (all j): the accuracy reference, and its first
+    # quarter timed as the CPU baseline
     if not args.no_cpu_baseline:
         import oracle
-        # calibrate on enough i to occupy every oracle thread (the oracle splits over i)
-        ncal = 8 * oracle.num_threads()
-        cal = sample_indices(n, ncal, 101)
-        t_a = time.perf_counter(); oracle.force(x, v, m, args.eps ** 2, idx=cal); t_b = time.perf_counter()
-        per_i = (t_b - t_a) / ncal
-        count = int(max(16, min(65536, args.cpu_seconds / max(per_i, 1e-9))))
-        idx = sample_indices(n, count, 7)
-        log(f"[bench] oracle on {count} sampled i x {n} j")
+        idx = stratified_rows(n, args.error_rows, 7)
+        count = idx.size
+        q = max(1, count // 4)
+        log(f"[bench] oracle on {count} i (one per {n // count} rows) x {n} j")
         t_a = time.perf_counter()
-        ra, rk, rp = oracle.force(x, v, m, args.eps ** 2, idx=idx)
+        parts = [oracle.force(x, v, m, args.eps ** 2, idx=idx[:q])]
         t_b = time.perf_counter()
+        if count > q:
+            parts.append(oracle.force(x, v, m, args.eps ** 2, idx=idx[q:]))
+        ra, rk, rp = (np.concatenate([p_[k] for p_ in parts]) for k in range(3))
         result["cpu_baseline"] = {
-            "value": count * n / (t_b - t_a), "unit": "interactions/s",
+            "value": q * n / (t_b - t_a), "unit": "interactions/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{count} seeded i-particles x all {n} j-particles (FP64, long-double "
-                      f"sums), {t_b - t_a:.1f} s"}
-        errors = {args.precision: {"e_acc": rms_rel(g["a"][idx], ra),
-                                   "e_jerk": rms_rel(g["k"][idx], rk),
-                                   "e_pot": rms_rel(g["pot"][idx], rp), "sample": count}}
+            "sample": f"{q} seeded i-particles (one per {4 * n // count} rows) x all {n} "
+                      f"j-particles (FP64, long-double sums), {t_b - t_a:.1f} s"}
+
+        def errs(gg):
+            return {"e_acc": rms_rel(gg["a"][idx], ra), "e_jerk": rms_rel(gg["k"][idx], rk),
+                    "e_pot": rms_rel(gg["pot"][idx], rp),
+                    "max_row_rel_acc": float(np.max(np.linalg.norm(gg["a"][idx] - ra, axis=1)
+                                                    / np.linalg.norm(ra, axis=1))),
+                    "sample": count}
+        errors = {args.precision: errs(g)}
         for prec, d in variants.items():
-            gv = d.pop("gv")
-            errors[prec] = {"e_acc": rms_rel(gv["a"][idx], ra), "e_jerk": rms_rel(gv["k"][idx], rk),
-                            "e_pot": rms_rel(gv["pot"][idx], rp), "sample": count}
+            errors[prec] = errs(d.pop("gv"))
         result["errors_vs_oracle"] = errors
     else:
         for d in variants.values():
@@ -763,7 +788,55 @@ def main():
     for prec, d in variants.items():
         d["slowdown_vs_" + args.precision] = (d["full_force_ms"] * 1e6 / (n * n)) / ns_per_int
     result["variants"] = variants
+    if not args.no_configs:
+        result["configs"] = other_configs(args)
     print(json.dumps(result), flush=True)
+
+
+def stratified_rows(n, count, seed):
+    """`count` rows of n, one seeded row from each of `count` equal runs of rows."""
+    import numpy as np
+    block = max(1, n // count)
+    r = np.random.default_rng(seed).integers(0, block, (n + block - 1) // block)
+    return np.minimum(np.arange(r.size) * block + r, n - 1).astype(np.int64)
+
+
+def other_configs(args):
+    """One run of each of the other workloads (steps = 1 after one warmup, no CPU baseline),
+    summarised: the N = 1024 block-step run to t = 1/8 (dt <= 1/64), the N = 65536 run to t = 1
+    in FP32 and double-single against the committed oracle run, the 512-cluster ensemble to
+    t = 1, and the gradient of the 64-step trajectory loss at N = 16384."""
+    sub = argparse.Namespace(**vars(args))
+    sub.steps, sub.warmup, sub.no_cpu_baseline = 1, 1, True
+    out = {}
+
+    def run_summary(r):
+        c = r["config"]
+        s = {"wall_s": c["wall_s"], "interactions_per_s": r["value"], "n_steps": c["n_steps"],
+             "mean_block": c["mean_block"], "de_rel": c["de_rel"],
+             "us_per_block_step": 1e6 * c["wall_s"] / c["n_steps"],
+             "block_force_frac_fp32_peak": r["roofline"]["frac"]}
+        ref = r.get("oracle_reference_run")
+        if ref:
+            s["oracle"] = {"n_steps": ref["n_steps"], "de_rel": ref["de_rel"]}
+        for prec, v in r.get("variants", {}).items():
+            s[prec] = {"wall_s": v["wall_s"], "n_steps": v["n_steps"], "de_rel": v["de_rel"]}
+        return s
+
+    sub.precision, sub.variants = "fp32", "none"
+    sub.run = "n1024_t0.125"
+    out["n1024_t0.125"] = run_summary(bench_run(sub, emit=False))
+    sub.run, sub.variants = "n65536_t1", "ds"
+    out["n65536_t1"] = run_summary(bench_run(sub, emit=False))
+    sub.variants, sub.clusters, sub.t_end, sub.tune = "none", 512, 1.0, False
+    r = bench_ensemble(sub, emit=False)
+    out["ensemble_512"] = {"wall_s": r["ms_per_step"] / 1e3, "interactions_per_s": r["value"],
+                           "frac_fp32_peak": r["roofline"]["frac"],
+                           "max_block_steps": r["config"]["max_block_steps"],
+                           "dE_over_E_median": r["config"]["dE_over_E_median"]}
+    r = bench_adjoint(sub, emit=False)
+    out["adjoint_n16384"] = {"ms_per_gradient": r["ms_per_step"], "interactions_per_s": r["value"]}
+    return out
 
 
 if __name__ == "__main__":

@@ -11,7 +11,14 @@
  * Conventions shared by every call
  *   - All array pointers are DEVICE pointers on the current HIP device unless a parameter says
  *     "host".  The caller owns every pointer it passes; the library never frees them and keeps
- *     them only between nb_bind() and the next nb_bind()/nb_destroy().
+ *     them only between nb_bind() (or nb_bind_scratch()) and the next such call or
+ *     nb_destroy().
+ *   - The library allocates no device memory.  Besides the particle state, a context works in
+ *     one caller-owned workspace of nb_scratch_bytes() bytes (j-particle stream, block list,
+ *     scheduler record, j-split partial sums, energy and adjoint scratch), bound with
+ *     nb_bind_scratch(); an ensemble likewise (nb_ens_scratch_bytes(), nb_ens_bind_scratch()).
+ *     The library owns only its host-side context, captured HIP graphs and one private
+ *     capture stream per context.
  *   - Per-particle vectors are structure-of-arrays: component c (0 = x, 1 = y, 2 = z) of
  *     particle i lives at [c * ld + i], where ld is the array's leading dimension (n for the
  *     particle state, the caller's n_i_max for force outputs).
@@ -92,12 +99,26 @@ typedef struct {
 
 /* Create a context for n particles (1 <= n <= 2^28) with Plummer softening eps >= 0, largest
  * step 2^-lmin and smallest step 2^-lmax (0 <= lmin <= lmax <= 52), interaction arithmetic
- * `precision`.  Allocates the library's own device work buffers on the current device (about
- * 300 bytes per particle plus j-split partial sums).  *out is set to NULL on failure. */
+ * `precision`, on the current device.  Allocates no device memory (see nb_bind_scratch).
+ * *out is set to NULL on failure. */
 nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t lmax,
                     int32_t precision);
 
-/* Release the context and its device work buffers (never the caller's).  NULL is a no-op. */
+/* Bytes of device workspace a context of n particles and this precision needs on the current
+ * device (the j-split partial sums are sized from its compute-unit count; 256, the MI355X's,
+ * when no device is visible): about 300 bytes per particle plus the partial sums (at most 64
+ * j-ranges of 56 bytes per particle for full-force calls).  0 if the arguments are invalid.
+ * Needs no device and allocates nothing. */
+size_t nb_scratch_bytes(int32_t n, int32_t precision);
+
+/* Bind the context's workspace: `bytes` >= nb_scratch_bytes(n, precision) of caller-owned
+ * device memory at a 256-byte aligned address (e.g. a torch tensor), which the library
+ * carves into its work buffers and initialises (on the context's stream).  Required before
+ * any call that enqueues work; binding another workspace drops the state of the old one
+ * (scheduler record, predicted stream, captured graph).  NB_EINVAL if too small or misaligned. */
+nb_status nb_bind_scratch(nb_ctx *ctx, void *scratch, size_t bytes);
+
+/* Release the context (never the caller's memory).  NULL is a no-op. */
 nb_status nb_destroy(nb_ctx *ctx);
 
 /* Enqueue subsequent work on `hip_stream` (a hipStream_t; NULL = the null stream). */
@@ -246,6 +267,12 @@ nb_status nb_set_variant(nb_ctx *ctx, int32_t which, const nb_variant *v);
 nb_status nb_tune(nb_ctx *ctx, int32_t which, int32_t n_i, int32_t reps, nb_variant *best,
                   double *best_ms);
 
+/* Calibration for measurement (not part of the method): the FP32 fused multiply-add rate of
+ * the device in TFLOP/s (HOST output), from a kernel of 16 independent two-operand FMA chains
+ * per work-item over 64 workgroups of 256 per compute unit, best of three timed launches on
+ * the context's stream.  Requires a bound workspace; synchronising. */
+nb_status nb_fma_rate(nb_ctx *ctx, double *tflops);
+
 /* Wait for the context's stream; returns a latched device error, if any. */
 nb_status nb_sync(nb_ctx *ctx);
 
@@ -264,12 +291,23 @@ typedef struct nb_ens nb_ens;
 /* Create an ensemble of n_clusters clusters: cluster c holds particles [offsets[c],
  * offsets[c+1]) (HOST array of n_clusters + 1, offsets[0] = 0, strictly increasing, total
  * <= 2^28, n_clusters <= 8192) with softening eps[c] > 0 (HOST array); steps in
- * [2^-lmax, 2^-lmin]; interaction
- * arithmetic `precision`.  Allocates the ensemble's device work buffers. */
+ * [2^-lmax, 2^-lmin]; interaction arithmetic `precision` (NB_FP32, NB_DS or NB_FP64).
+ * Allocates no device memory (see nb_ens_bind_scratch). */
 nb_status nb_ens_create(nb_ens **out, int32_t n_clusters, const int32_t *offsets,
                         const double *eps, int32_t lmin, int32_t lmax, int32_t precision);
 
-/* Release the ensemble's own buffers (never the caller's).  NULL is a no-op. */
+/* Bytes of device workspace an ensemble of these clusters needs (offsets as for
+ * nb_ens_create, HOST array): cluster tables, per-cluster records, block lists, criterion and
+ * energy scratch, and one plane set of j-split partial sums per cluster (7 doubles per
+ * particle per 256-particle j-tile).  0 if the arguments are invalid. */
+size_t nb_ens_scratch_bytes(int32_t n_clusters, const int32_t *offsets, int32_t precision);
+
+/* Bind the ensemble's workspace (as nb_bind_scratch: caller-owned, 256-byte aligned, at least
+ * nb_ens_scratch_bytes() bytes); uploads the cluster tables.  Synchronising.  Required before
+ * nb_ens_init. */
+nb_status nb_ens_bind_scratch(nb_ens *ens, void *scratch, size_t bytes);
+
+/* Release the ensemble (never the caller's memory).  NULL is a no-op. */
 nb_status nb_ens_destroy(nb_ens *ens);
 
 /* Enqueue subsequent work on `hip_stream` (NULL: the null stream). */
@@ -285,6 +323,16 @@ nb_status nb_ens_bind(nb_ens *ens, const nb_state *state);
 nb_status nb_ens_set_layout(nb_ens *ens, const int32_t *tiles_per_item, int32_t ipl,
                             int32_t unroll);
 
+/* Which blocks each cluster's own workgroup advances: a selected block of n_act <= 1024
+ * particles with n_act * N_c <= local_limit interactions (0: none) is forced, corrected and
+ * followed by the cluster's next block inside the cluster's workgroup (all its particles
+ * predicted as they are staged in LDS), up to local_steps such block steps and local_work
+ * interactions per cluster per global step; larger blocks go through the GPU-wide force of the
+ * next global step.  Only the summation order differs between the two paths.  Defaults: 0
+ * (every block through the GPU-wide force), 64, 2^21.  Synchronising. */
+nb_status nb_ens_set_local(nb_ens *ens, int64_t local_limit, int32_t local_steps,
+                           int64_t local_work);
+
 /* Sec. 2 start of run for every cluster: full force at time 0, initial steps from
  * Eq. initTimestep with this eta, times 0. */
 nb_status nb_ens_init(nb_ens *ens, double eta);
@@ -292,7 +340,10 @@ nb_status nb_ens_init(nb_ens *ens, double eta);
 /* Advance every cluster by its own block steps until its next block would pass t_end
  * (ticks), steps_per_launch global steps per graph launch (use_graph != 0) or eager launch
  * batch, synchronising after each to test for completion; at most max_steps global steps
- * (<= 0: no limit).  Returns NB_OK or a latched device error. */
+ * (<= 0: no limit).  A global step is the GPU-wide force of every cluster's selected block that
+ * is not a local block (nb_ens_set_local), then one workgroup per cluster: the corrector of
+ * that block, the next block, and the cluster's local block steps.  Returns NB_OK or a latched
+ * device error. */
 nb_status nb_ens_run(nb_ens *ens, double eta, int64_t t_end, int32_t steps_per_launch,
                      int64_t max_steps, int32_t use_graph);
 

@@ -40,7 +40,28 @@ struct EnsView {
     int32_t lmin, lmax;
     double tick_len;
     int64_t t_end;
+    // Blocks advanced by the cluster's own workgroup (ens_local_block): at most local_limit
+    // interactions (n_act * N_c; 0: none, every block goes through ens_force), and per launch
+    // at most local_steps such block steps and local_work interactions per cluster.
+    int64_t local_limit;
+    int32_t local_steps;
+    int64_t local_work;
 };
+
+constexpr int WGL = 1024;  // workgroup of the cluster-local kernel
+
+// A cluster's selected block is forced by its own workgroup (and never by ens_force) when it
+// holds at most WGL particles and at most `limit` interactions.
+__host__ __device__ __forceinline__ bool ens_local_block(int32_t n_act, int32_t n_c, int64_t limit) {
+    return n_act > 0 && n_act <= WGL && (int64_t)n_act * n_c <= limit;
+}
+
+// Fresh per-cluster records and flags (a fill kernel instead of a memset).
+__global__ void __launch_bounds__(WG) ens_clear(EnsCluster *cl, int32_t C, int32_t *flags) {
+    const int32_t c = blockIdx.x * WG + threadIdx.x;
+    if (c < C) cl[c] = EnsCluster{0, 0, 0, 0, 0, 0, 0, 0};
+    if (c < 2) flags[c] = 0;
+}
 
 // Ordered compaction of the particles of [lo, hi) that satisfy `pred` into out[base ...],
 // by one workgroup; returns the count.
@@ -79,22 +100,195 @@ __device__ __forceinline__ int64_t block_min_i64(int64_t v, int64_t *red) {
     return r;
 }
 
-constexpr int WGL = 1024;  // workgroup of the cluster-local kernel
 constexpr int TN_CACHE = 4096;  // clusters up to this size keep t_i + dt_i in LDS for selection
+
+// Predicted FP64 position and velocity of particle i at tick t (Sec. 2 predictor).
+__device__ __forceinline__ void predicted(const StateRW &s, int32_t i, int64_t t, double xp[3],
+                                          double vp[3]) {
+    const double D = (double)(t - s.tick[i]) * s.tick_len;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int64_t ix = k * (int64_t)s.n + i;
+        predict_one(D, s.x[ix], s.v[ix], s.a[ix], s.k[ix], xp[k], vp[k]);
+    }
+}
+
+template <class M> __device__ __forceinline__ typename EpsOf<M>::T eps_as(double e2);
+template <> __device__ __forceinline__ float eps_as<ModeF32>(double e2) { return (float)e2; }
+template <> __device__ __forceinline__ ds eps_as<ModeDS>(double e2) { return ds_from_double(e2); }
+template <> __device__ __forceinline__ double eps_as<ModeF64>(double e2) { return e2; }
+
+// Next block of cluster [lo, hi) (Sec. 2: smallest t_i + dt_i, all particles attaining it, in
+// ascending order) into e.active[lo ...] and the cluster record; every work-item of the
+// workgroup gets the block size and time.  Returns false when the block lies beyond t_end (the
+// cluster is done).  Clusters of up to TN_CACHE particles keep t_i + dt_i in LDS for the
+// compaction (the loads of four particles per work-item are issued together).
+// Work-groups of BS work-items; tn_lds (TN_CACHE entries) may be NULL (no cache).
+template <int BS>
+__device__ bool ens_select(const EnsView &e, const StateRW &s, int32_t lo, int32_t hi,
+                           EnsCluster *cl, int64_t *tn_lds, int64_t *red, int32_t *wsum,
+                           int32_t &n_act, int64_t &t_next) {
+    const int32_t lmax = e.lmax;
+    const bool cached = tn_lds != nullptr && hi - lo <= TN_CACHE;
+    int64_t m = INT64_MAX;
+    if (cached) {
+        int64_t tn[TN_CACHE / BS];
+#pragma unroll
+        for (int r = 0; r < TN_CACHE / BS; ++r) {
+            const int32_t i = lo + threadIdx.x + r * BS;
+            tn[r] = i < hi ? s.tick[i] + ((int64_t)1 << (lmax - s.level[i])) : INT64_MAX;
+        }
+#pragma unroll
+        for (int r = 0; r < TN_CACHE / BS; ++r) {
+            tn_lds[threadIdx.x + r * BS] = tn[r];
+            m = tn[r] < m ? tn[r] : m;
+        }
+    } else {
+        for (int32_t i = lo + threadIdx.x; i < hi; i += BS) {
+            const int64_t tn = s.tick[i] + ((int64_t)1 << (lmax - s.level[i]));
+            m = tn < m ? tn : m;
+        }
+    }
+    const int64_t tn_min = block_min_i64<BS>(m, red);  // its barriers also publish tn_lds
+    if (tn_min > e.t_end) {
+        if (threadIdx.x == 0) { cl->done = 1; cl->n_act = 0; }
+        n_act = 0;
+        return false;
+    }
+    const int32_t na = cached
+        ? wg_compact<BS>(lo, hi, [&](int32_t i) { return tn_lds[i - lo] == tn_min; },
+                         e.active + lo, wsum)
+        : wg_compact<BS>(
+              lo, hi,
+              [&](int32_t i) { return s.tick[i] + ((int64_t)1 << (lmax - s.level[i])) == tn_min; },
+              e.active + lo, wsum);
+    if (threadIdx.x == 0) {
+        cl->t_next = tn_min;
+        cl->n_act = na;
+    }
+    n_act = na;
+    t_next = tn_min;
+    __syncthreads();  // the block list is complete before any work-item reads it
+    return true;
+}
+
+// The 7 sums of block row q of cluster c over its K partial planes, in plane order (four
+// planes' loads in flight).
+__device__ __forceinline__ void ens_row_sums(const EnsView &e, int32_t c, int32_t q, double o[7]) {
+    const int32_t K = e.K[c], P = e.prow[c];
+    const int64_t stride = (int64_t)7 * P;
+    const double *src = e.partial + e.part_off[c] + q;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) o[k] = 0.0;
+    int32_t j = 0;
+    for (; j + 4 <= K; j += 4) {
+        double v[4][7];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int k = 0; k < 7; ++k) v[r][k] = src[(j + r) * stride + (int64_t)k * P];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) o[k] = (((o[k] + v[0][k]) + v[1][k]) + v[2][k]) + v[3][k];
+    }
+    for (; j < K; ++j) {
+#pragma unroll
+        for (int k = 0; k < 7; ++k) o[k] += src[j * stride + (int64_t)k * P];
+    }
+}
+
+// Corrector of block particle i from its new sums (a, k in o[0..5], potential sum o[6]), new
+// level from Eq. timestep.
+__device__ __forceinline__ void ens_correct_one(const EnsView &e, const StateRW &s, int32_t i,
+                                                int64_t t_next, const double o[7], double eta,
+                                                bool &bad, bool &clamp) {
+    const double a1[3] = {o[0], o[1], o[2]}, k1[3] = {o[3], o[4], o[5]};
+    const double dt_old = (double)(t_next - s.tick[i]) * s.tick_len;
+    double num = 0.0, den = 0.0;
+    const bool ok = correct_particle(s, i, dt_old, a1, k1, -o[6], t_next, nullptr, &num, &den);
+    bad = bad || !ok;
+    const double dt = den > 0.0 ? __builtin_sqrt(eta * num / den) : __builtin_inf();
+    bad = bad || __builtin_isnan(dt);
+    clamp = clamp || dt < e.tick_len;
+    s.level[i] = next_level(dt, s.level[i], t_next, e.lmin, e.lmax);
+}
+
+// One block step of a cluster by its own workgroup (the block is ens_local_block): the force of
+// the block particles against all cluster particles, predicted to t_next as they are staged in
+// LDS, WGL at a time; S = WGL / 2^ceil(log2 n_act) (at most 64) adjacent lanes share a block
+// particle and combine their sums by wave shuffles; then the corrector and the new levels.
+template <class M>
+__device__ void ens_block_step_local(const EnsView &e, const StateRW &s, int32_t c, int32_t lo,
+                                     int32_t hi, int32_t n_act, int64_t t_next, double eta,
+                                     typename M::Smem (&sm)[WGL / TJ], bool &bad, bool &clamp) {
+    const int32_t n_c = hi - lo;
+    int32_t p2 = 1;
+    while (p2 < n_act) p2 <<= 1;
+    const int32_t Sl = WGL / p2 > 64 ? 64 : WGL / p2;
+    const int32_t slice = (int32_t)threadIdx.x % Sl;
+    const int32_t q = (int32_t)threadIdx.x / Sl;
+    const bool has = q < n_act;
+    const int32_t g = has ? e.active[lo + q] : lo;
+    const int32_t own = has ? g - lo : -1;  // own slot in the cluster (none on padding)
+    const auto eps2 = eps_as<M>(e.eps2[c]);
+    double xp[3], vp[3];
+    predicted(s, g, t_next, xp, vp);
+    const typename M::I ii = M::make_i(xp, vp, s.m[g]);
+    typename M::Sum S = M::sum_zero();
+    for (int32_t t0 = 0; t0 < n_c; t0 += WGL) {
+        __syncthreads();
+        const int32_t jl = t0 + (int32_t)threadIdx.x;
+        typename M::Smem &st = sm[threadIdx.x / TJ];
+        if (jl < n_c) {
+            double xj[3], vj[3];
+            predicted(s, lo + jl, t_next, xj, vj);
+            M::put(st, threadIdx.x % TJ, xj, vj, s.m[lo + jl]);
+        } else {  // padding: zero mass contributes nothing
+            const double z[3] = {0.0, 0.0, 0.0};
+            M::put(st, threadIdx.x % TJ, z, z, 0.0);
+        }
+        __syncthreads();
+        const int32_t jn = n_c - t0 < WGL ? n_c - t0 : WGL;
+        for (int b = 0; b * TJ < jn; ++b) {  // 256-slot sub-tiles, folded one at a time
+            const int32_t cnt = jn - b * TJ < TJ ? jn - b * TJ : TJ;
+            const int32_t rel = own - (t0 + b * TJ);
+            typename M::Tile T = M::tile_zero();
+            if (__ballot((uint32_t)rel < (uint32_t)cnt) != 0) {
+#pragma unroll 2
+                for (int jj = slice; jj < cnt; jj += Sl)
+                    M::template interact<true, true>(ii, sm[b], jj, eps2, T, jj == rel);
+            } else {
+#pragma unroll 2
+                for (int jj = slice; jj < cnt; jj += Sl) M::template interact<true>(ii, sm[b], jj, eps2, T);
+            }
+            M::fold(S, T);
+        }
+    }
+    for (int off = Sl >> 1; off > 0; off >>= 1) M::shfl_add(S, off);
+    __syncthreads();  // every prediction read of the state precedes the corrector's writes
+    if (has && slice == 0) {
+        const Out7 o = M::out(S);
+        ens_correct_one(e, s, g, t_next, o.v, eta, bad, clamp);
+    }
+    __syncthreads();  // the corrected times and levels precede the next selection
+}
 
 // One workgroup of WGL per cluster.
 //   phase 0: start of run -- block = every particle, times 0, block time 0
 //   phase 1: after the start-of-run force -- store a, k, pot and the initial levels
 //            (Eq. initTimestep), then select the first block
-//   phase 2: after a block force -- correct the block, give it new levels (Eq. timestep),
-//            then select the next block
-// Each thread takes whole block particles: the fixed-order sum of its K partial planes, the
-// corrector and the new level, with the criterion kept in registers.
+//   phase 2: after a global force step -- correct the block ens_force computed (if it was not
+//            a local block), give it new levels (Eq. timestep) and select the next block; then
+//            advance the cluster by its own block steps while the selected block is a local
+//            block, up to local_steps steps and local_work interactions
+// The block ens_force computed: each thread takes whole block particles, the fixed-order sum of
+// its K partial planes, the corrector and the new level, with the criterion in registers.
+template <class M>
 __global__ void __launch_bounds__(WGL) ens_local(EnsView e, StateRW s, double eta,
                                                  int32_t phase) {
     __shared__ int64_t red[WGL / 64];
     __shared__ int32_t wsum[WGL / 64];
     __shared__ int64_t tn_lds[TN_CACHE];
+    __shared__ typename M::Smem sm[WGL / TJ];
     const int32_t c = blockIdx.x;
     if (c >= e.C) return;
     const int32_t lo = e.off[c], hi = e.off[c + 1];
@@ -109,108 +303,65 @@ __global__ void __launch_bounds__(WGL) ens_local(EnsView e, StateRW s, double et
         return;
     }
     if (cl->done) return;  // n_act is already 0
-    const int32_t n_act = cl->n_act;
-    const int64_t t_next = cl->t_next;
-    const int32_t K = e.K[c], P = e.prow[c];
-    const double *pbase = e.partial + e.part_off[c];
-    const int64_t stride = (int64_t)7 * P;
+    int32_t n_act = cl->n_act;
+    int64_t t_next = cl->t_next;
+    const int32_t n_c = hi - lo;
     bool bad = false, clamp = false;
-    for (int32_t q = threadIdx.x; q < n_act; q += WGL) {
-        // the 7 sums of this block particle over the K partial planes, in plane order
-        double o[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        const double *src = pbase + q;
-        int32_t j = 0;
-        for (; j + 4 <= K; j += 4) {  // four planes' loads in flight, added in plane order
-            double v[4][7];
+    if (phase == 1 || !ens_local_block(n_act, n_c, e.local_limit)) {
+        for (int32_t q = threadIdx.x; q < n_act; q += WGL) {
+            double o[7];
+            ens_row_sums(e, c, q, o);
+            const int32_t i = e.active[lo + q];
+            if (phase == 1) {
+                double na = 0.0, nk = 0.0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-#pragma unroll
-                for (int k = 0; k < 7; ++k) v[r][k] = src[(j + r) * stride + (int64_t)k * P];
-#pragma unroll
-            for (int k = 0; k < 7; ++k) o[k] = (((o[k] + v[0][k]) + v[1][k]) + v[2][k]) + v[3][k];
-        }
-        for (; j < K; ++j) {
-#pragma unroll
-            for (int k = 0; k < 7; ++k) o[k] += src[j * stride + (int64_t)k * P];
-        }
-        const int32_t i = e.active[lo + q];
-        const double a1[3] = {o[0], o[1], o[2]}, k1[3] = {o[3], o[4], o[5]};
-        if (phase == 1) {
-            double na = 0.0, nk = 0.0;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                s.a[k * (int64_t)s.n + i] = a1[k];
-                s.k[k * (int64_t)s.n + i] = k1[k];
-                na = __builtin_fma(a1[k], a1[k], na);
-                nk = __builtin_fma(k1[k], k1[k], nk);
+                for (int k = 0; k < 3; ++k) {
+                    s.a[k * (int64_t)s.n + i] = o[k];
+                    s.k[k * (int64_t)s.n + i] = o[3 + k];
+                    na = __builtin_fma(o[k], o[k], na);
+                    nk = __builtin_fma(o[3 + k], o[3 + k], nk);
+                }
+                s.pot[i] = -o[6];
+                na = __builtin_sqrt(na); nk = __builtin_sqrt(nk);
+                const double dt = nk > 0.0 ? eta * na / nk : __builtin_inf();
+                bad = bad || !__builtin_isfinite(na) || !__builtin_isfinite(nk);
+                s.level[i] = level_from_dt(dt, e.lmin, e.lmax);
+            } else {
+                ens_correct_one(e, s, i, t_next, o, eta, bad, clamp);
             }
-            s.pot[i] = -o[6];
-            na = __builtin_sqrt(na); nk = __builtin_sqrt(nk);
-            const double dt = nk > 0.0 ? eta * na / nk : __builtin_inf();
-            bad = bad || !__builtin_isfinite(na) || !__builtin_isfinite(nk);
-            s.level[i] = level_from_dt(dt, e.lmin, e.lmax);
-        } else {
-            const double dt_old = (double)(t_next - s.tick[i]) * s.tick_len;
-            double num = 0.0, den = 0.0;
-            const bool ok = correct_particle(s, i, dt_old, a1, k1, -o[6], t_next, nullptr, &num, &den);
-            bad = bad || !ok;
-            const double dt = den > 0.0 ? __builtin_sqrt(eta * num / den) : __builtin_inf();
-            bad = bad || __builtin_isnan(dt);
-            clamp = clamp || dt < e.tick_len;
-            s.level[i] = next_level(dt, s.level[i], t_next, e.lmin, e.lmax);
+        }
+        __syncthreads();
+        if (phase == 2 && threadIdx.x == 0 && n_act > 0) {
+            cl->t_cur = t_next;
+            cl->n_steps += 1;
+            cl->n_active_sum += n_act;
+        }
+        const bool more = ens_select<WGL>(e, s, lo, hi, cl, tn_lds, red, wsum, n_act, t_next);
+        if (!more || phase == 1) {
+            if (bad) e.flags[0] = 1;
+            if (clamp) e.flags[1] = 1;
+            return;
         }
     }
-    __syncthreads();
+    // the cluster's own block steps while its blocks are small
+    int64_t work = 0;
+    for (int32_t it = 0; it < e.local_steps && work < e.local_work &&
+                         ens_local_block(n_act, n_c, e.local_limit); ++it) {
+        ens_block_step_local<M>(e, s, c, lo, hi, n_act, t_next, eta, sm, bad, clamp);
+        work += (int64_t)n_act * n_c;
+        if (threadIdx.x == 0) {
+            cl->t_cur = t_next;
+            cl->n_steps += 1;
+            cl->n_active_sum += n_act;
+        }
+        if (!ens_select<WGL>(e, s, lo, hi, cl, tn_lds, red, wsum, n_act, t_next)) break;
+    }
     if (bad) e.flags[0] = 1;
     if (clamp) e.flags[1] = 1;
-    if (phase == 2 && threadIdx.x == 0 && n_act > 0) {
-        cl->t_cur = t_next;
-        cl->n_steps += 1;
-        cl->n_active_sum += n_act;
-    }
-    // next block of this cluster; clusters of up to TN_CACHE particles keep t_i + dt_i in LDS
-    // for the compaction (the loads of four particles per work-item are issued together)
-    const int32_t lmax = e.lmax;
-    const bool cached = hi - lo <= TN_CACHE;
-    int64_t m = INT64_MAX;
-    if (cached) {
-        int64_t tn[TN_CACHE / WGL];
-#pragma unroll
-        for (int r = 0; r < TN_CACHE / WGL; ++r) {
-            const int32_t i = lo + threadIdx.x + r * WGL;
-            tn[r] = i < hi ? s.tick[i] + ((int64_t)1 << (lmax - s.level[i])) : INT64_MAX;
-        }
-#pragma unroll
-        for (int r = 0; r < TN_CACHE / WGL; ++r) {
-            tn_lds[threadIdx.x + r * WGL] = tn[r];
-            m = tn[r] < m ? tn[r] : m;
-        }
-    } else {
-        for (int32_t i = lo + threadIdx.x; i < hi; i += WGL) {
-            const int64_t tn = s.tick[i] + ((int64_t)1 << (lmax - s.level[i]));
-            m = tn < m ? tn : m;
-        }
-    }
-    const int64_t tn_min = block_min_i64<WGL>(m, red);  // its barriers also publish tn_lds
-    if (tn_min > e.t_end) {
-        if (threadIdx.x == 0) { cl->done = 1; cl->n_act = 0; }
-        return;
-    }
-    const int32_t na = cached
-        ? wg_compact<WGL>(lo, hi, [&](int32_t i) { return tn_lds[i - lo] == tn_min; },
-                          e.active + lo, wsum)
-        : wg_compact<WGL>(
-              lo, hi,
-              [&](int32_t i) { return s.tick[i] + ((int64_t)1 << (lmax - s.level[i])) == tn_min; },
-              e.active + lo, wsum);
-    if (threadIdx.x == 0) {
-        cl->t_next = tn_min;
-        cl->n_act = na;
-    }
 }
 
-// Exclusive prefix over clusters of their force work items, start[0..C], formed by one
-// workgroup of BS in its LDS: each work-item takes a contiguous run of clusters, the runs'
+// Exclusive prefix over clusters of their force work items (ens_item: i-blocks of WG / S block
+// particles times K j-ranges), start[0..C], formed by one workgroup of BS in its LDS: each work-item takes a contiguous run of clusters, the runs'
 // totals are scanned across the wave (shuffles) and across waves (wsum).
 template <int BS>
 __device__ void ens_item_prefix(const EnsView &e, int32_t *start, int32_t *wsum) {
@@ -221,8 +372,9 @@ __device__ void ens_item_prefix(const EnsView &e, int32_t *start, int32_t *wsum)
     int32_t own = 0;
     for (int32_t c = c0; c < c1; ++c) {
         const int32_t na = e.cl[c].n_act;
-        const int32_t ibc = BS / lane_split(na, true);
-        const int32_t items = na > 0 ? ((na + ibc - 1) / ibc) * e.K[c] : 0;
+        const int32_t ibc = WG / lane_split(na, true);  // i-block of an item (ens_item), any BS
+        const bool global = na > 0 && !ens_local_block(na, e.off[c + 1] - e.off[c], e.local_limit);
+        const int32_t items = global ? ((na + ibc - 1) / ibc) * e.K[c] : 0;
         start[c] = items;
         own += items;
     }
@@ -244,25 +396,78 @@ __device__ void ens_item_prefix(const EnsView &e, int32_t *start, int32_t *wsum)
     __syncthreads();
 }
 
-template <class M> __device__ __forceinline__ typename EpsOf<M>::T eps_as(double e2);
-template <> __device__ __forceinline__ float eps_as<ModeF32>(double e2) { return (float)e2; }
-template <> __device__ __forceinline__ ds eps_as<ModeDS>(double e2) { return ds_from_double(e2); }
-template <> __device__ __forceinline__ double eps_as<ModeF64>(double e2) { return e2; }
+// Cluster of item w: the last c with start[c] <= w.
+__device__ __forceinline__ int32_t ens_item_cluster(const int32_t *start, int32_t C, int32_t w) {
+    int32_t lo = 0, hi = C - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
-// Work items of all clusters; softened (eps > 0) interactions only.
-// Predicted FP64 position and velocity of particle i at tick t (Sec. 2 predictor).
-__device__ __forceinline__ void predicted(const StateRW &s, int32_t i, int64_t t, double xp[3],
-                                          double vp[3]) {
-    const double D = (double)(t - s.tick[i]) * s.tick_len;
+// Force work item `local` of cluster c (its i-block of the block list against its range of
+// whole j-tiles), partial sums to the cluster's planes.  Softened (eps > 0) interactions only;
+// one i per work-item, S lanes per i when the cluster's block is small.
+template <class M, int UNR>
+__device__ void ens_item(const EnsView &e, const StateRW &st, int32_t c, int32_t local,
+                         typename M::Smem &sm) {
+    const int32_t K = e.K[c], tpi = e.tpi[c];
+    const int32_t iblk = local / K, ks = local - (local / K) * K;
+    const int32_t p0 = e.off[c], n_c = e.off[c + 1] - p0;
+    const int32_t n_act = e.cl[c].n_act;
+    const int64_t tb = e.cl[c].t_next;
+    const int32_t Sl = lane_split(n_act, true);
+    const int32_t slice = (int32_t)threadIdx.x % Sl;
+    const int32_t ntiles = (n_c + TJ - 1) / TJ;
+    const auto eps2 = eps_as<M>(e.eps2[c]);
+    const int32_t q = iblk * (WG / Sl) + (int32_t)threadIdx.x / Sl;
+    const int32_t g = q < n_act ? e.active[p0 + q] : p0;
+    const int32_t own = q < n_act ? g - p0 : -1;  // own slot in the cluster (none on padding)
+    double xp[3], vp[3];
+    predicted(st, g, tb, xp, vp);
+    const typename M::I ii = M::make_i(xp, vp, st.m[g]);
+    typename M::Sum S = M::sum_zero();
+    const int32_t t0 = ks * tpi;
+    const int32_t t1 = t0 + tpi < ntiles ? t0 + tpi : ntiles;
+    for (int32_t t = t0; t < t1; ++t) {
+        __syncthreads();
+        const int32_t jl = t * TJ + (int32_t)threadIdx.x;
+        if (jl < n_c) {
+            double xj[3], vj[3];
+            predicted(st, p0 + jl, tb, xj, vj);
+            M::put(sm, threadIdx.x, xj, vj, st.m[p0 + jl]);
+        } else {  // padding: zero mass contributes nothing
+            const double z[3] = {0.0, 0.0, 0.0};
+            M::put(sm, threadIdx.x, z, z, 0.0);
+        }
+        __syncthreads();
+        typename M::Tile T = M::tile_zero();
+        const int32_t jn = n_c - t * TJ < TJ ? n_c - t * TJ : TJ;  // padding is skipped
+        // a tile holding a lane's own particle takes the masked loop (wave-uniform branch)
+        const int32_t rel = own - t * TJ;
+        if (__ballot((uint32_t)rel < (uint32_t)jn) != 0) {
+#pragma unroll UNR
+            for (int jj = slice; jj < jn; jj += Sl)
+                M::template interact<true, true>(ii, sm, jj, eps2, T, jj == rel);
+        } else {
+#pragma unroll UNR
+            for (int jj = slice; jj < jn; jj += Sl) M::template interact<true>(ii, sm, jj, eps2, T);
+        }
+        M::fold(S, T);
+    }
+    for (int off = Sl >> 1; off > 0; off >>= 1) M::shfl_add(S, off);
+    if (slice == 0 && q < n_act) {
+        const Out7 o = M::out(S);
+        const int32_t P = e.prow[c];
+        double *base = e.partial + e.part_off[c] + (int64_t)ks * 7 * P + q;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const int64_t ix = k * (int64_t)s.n + i;
-        predict_one(D, s.x[ix], s.v[ix], s.a[ix], s.k[ix], xp[k], vp[k]);
+        for (int k = 0; k < 7; ++k) base[(int64_t)k * P] = o.v[k];
     }
 }
 
-// Softened (eps > 0) interactions only; one i per work-item, S lanes per i when the
-// cluster's block is small.
+// The force items of every cluster's block (those that are not local blocks).
 // Dynamic LDS: the C + 1 item starts, formed once per workgroup.
 template <class M, int UNR>
 __global__ void __launch_bounds__(WG) ens_force(EnsView e, StateRW st) {
@@ -272,60 +477,8 @@ __global__ void __launch_bounds__(WG) ens_force(EnsView e, StateRW st) {
     ens_item_prefix<WG>(e, start, wsum);
     const int32_t total = start[e.C];
     for (int32_t w = blockIdx.x; w < total; w += gridDim.x) {
-        // cluster of item w: the last c with start[c] <= w
-        int32_t lo = 0, hi = e.C - 1;
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (start[mid] <= w) lo = mid;
-            else hi = mid - 1;
-        }
-        const int32_t c = lo;
-        const int32_t K = e.K[c], tpi = e.tpi[c];
-        const int32_t local = w - start[c];
-        const int32_t iblk = local / K, ks = local - (local / K) * K;
-        const int32_t p0 = e.off[c], n_c = e.off[c + 1] - p0;
-        const int32_t n_act = e.cl[c].n_act;
-        const int64_t tb = e.cl[c].t_next;
-        const int32_t Sl = lane_split(n_act, true);
-        const int32_t slice = (int32_t)threadIdx.x % Sl;
-        const int32_t ntiles = (n_c + TJ - 1) / TJ;
-        const auto eps2 = eps_as<M>(e.eps2[c]);
-        const int32_t q = iblk * (WG / Sl) + (int32_t)threadIdx.x / Sl;
-        const int32_t g = q < n_act ? e.active[p0 + q] : p0;
-        double xp[3], vp[3];
-        predicted(st, g, tb, xp, vp);
-        const typename M::I ii = M::make_i(xp, vp, st.m[g]);
-        typename M::Sum S = M::sum_zero();
-        const int32_t t0 = ks * tpi;
-        const int32_t t1 = t0 + tpi < ntiles ? t0 + tpi : ntiles;
-        for (int32_t t = t0; t < t1; ++t) {
-            __syncthreads();
-            const int32_t jl = t * TJ + (int32_t)threadIdx.x;
-            if (jl < n_c) {
-                double xj[3], vj[3];
-                predicted(st, p0 + jl, tb, xj, vj);
-                M::put(sm, threadIdx.x, xj, vj, st.m[p0 + jl]);
-            } else {  // padding: zero mass contributes nothing
-                const double z[3] = {0.0, 0.0, 0.0};
-                M::put(sm, threadIdx.x, z, z, 0.0);
-            }
-            __syncthreads();
-            typename M::Tile T = M::tile_zero();
-            const int32_t jn = n_c - t * TJ < TJ ? n_c - t * TJ : TJ;  // padding is skipped
-#pragma unroll UNR
-            for (int jj = slice; jj < jn; jj += Sl) M::template interact<true>(ii, sm, jj, eps2, T);
-            M::fold(S, T);
-        }
-        for (int off = Sl >> 1; off > 0; off >>= 1) M::shfl_add(S, off);
-        const int32_t jlo = p0 + t0 * TJ, jhi = p0 + t1 * TJ;
-        if (slice == 0 && q < n_act) {
-            if (g >= jlo && g < jhi) M::remove_self(S, ii, eps2);
-            const Out7 o = M::out(S);
-            const int32_t P = e.prow[c];
-            double *base = e.partial + e.part_off[c] + (int64_t)ks * 7 * P + q;
-#pragma unroll
-            for (int k = 0; k < 7; ++k) base[(int64_t)k * P] = o.v[k];
-        }
+        const int32_t c = ens_item_cluster(start, e.C, w);
+        ens_item<M, UNR>(e, st, c, w - start[c], sm);
     }
 }
 

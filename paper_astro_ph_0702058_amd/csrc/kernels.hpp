@@ -173,13 +173,15 @@ struct ModeF32 {
     __device__ static __forceinline__ J load_j(const Args &a, int j) {
         return J{uload(a.px, j), uload(a.py, j), uload(a.pz, j), uload(a.vm, j)};
     }
-    template <bool SOFT>
+    template <bool SOFT, bool MASK = false>
     __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, float eps2,
-                                                    Tile &T) {
-        pair<SOFT>(i, J{s.x[jj], s.y[jj], s.z[jj], s.vm[jj]}, eps2, T);
+                                                    Tile &T, bool self = false) {
+        pair<SOFT, MASK>(i, J{s.x[jj], s.y[jj], s.z[jj], s.vm[jj]}, eps2, T, self);
     }
-    template <bool SOFT>
-    __device__ static __forceinline__ void pair(const I &i, const J &j, float eps2, Tile &T) {
+    // MASK: the pair may be the i-particle's own slot (self), which then adds nothing
+    template <bool SOFT, bool MASK = false>
+    __device__ static __forceinline__ void pair(const I &i, const J &j, float eps2, Tile &T,
+                                                bool self = false) {
         const float dx = (float)(j.x - i.x);
         const float dy = (float)(j.y - i.y);
         const float dz = (float)(j.z - i.z);
@@ -192,7 +194,8 @@ struct ModeF32 {
         float rinv = __builtin_amdgcn_rsqf(r2);
         if (!SOFT) rinv = r2 > 0.0f ? rinv : 0.0f;
         const float rinv2 = rinv * rinv;
-        const float mr = q.w * rinv;
+        float mr = q.w * rinv;
+        if (MASK) mr = self ? 0.0f : mr;
         const float mr3 = mr * rinv2;
         const float t = -3.0f * (rv * rinv2);
         T.p += mr;
@@ -207,11 +210,6 @@ struct ModeF32 {
         S.ax += (double)T.ax; S.ay += (double)T.ay; S.az += (double)T.az;
         S.jx += (double)T.jx; S.jy += (double)T.jy; S.jz += (double)T.jz;
         S.p += (double)T.p;
-    }
-    // The softened self pair (d = u = 0) adds exactly 0 to acc and jerk and m_i rsq(eps2) to
-    // the potential sum; remove that same float value.
-    __device__ static void remove_self(Sum &S, const I &i, float eps2) {
-        S.p -= (double)(i.m * __builtin_amdgcn_rsqf(eps2));
     }
     __device__ static Out7 out(const Sum &S) {
         return Out7{{S.ax, S.ay, S.az, S.jx, S.jy, S.jz, S.p}};
@@ -277,13 +275,14 @@ struct ModeF32All {
     __device__ static __forceinline__ J load_j(const Args &a, int j) {
         return J{uload(a.pm, j), uload(a.vv, j)};
     }
-    template <bool SOFT>
+    template <bool SOFT, bool MASK = false>
     __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, float eps2,
-                                                    Tile &T) {
-        pair<SOFT>(i, J{s.pm[jj], s.vv[jj]}, eps2, T);
+                                                    Tile &T, bool self = false) {
+        pair<SOFT, MASK>(i, J{s.pm[jj], s.vv[jj]}, eps2, T, self);
     }
-    template <bool SOFT>
-    __device__ static __forceinline__ void pair(const I &i, const J &j, float eps2, Tile &T) {
+    template <bool SOFT, bool MASK = false>
+    __device__ static __forceinline__ void pair(const I &i, const J &j, float eps2, Tile &T,
+                                                bool self = false) {
         const float4 q = j.pm, w = j.vv;
         const float dx = q.x - i.x, dy = q.y - i.y, dz = q.z - i.z;
         const float ux = w.x - i.vx, uy = w.y - i.vy, uz = w.z - i.vz;
@@ -292,7 +291,8 @@ struct ModeF32All {
         float rinv = __builtin_amdgcn_rsqf(r2);
         if (!SOFT) rinv = r2 > 0.0f ? rinv : 0.0f;
         const float rinv2 = rinv * rinv;
-        const float mr = q.w * rinv;
+        float mr = q.w * rinv;
+        if (MASK) mr = self ? 0.0f : mr;
         const float mr3 = mr * rinv2;
         const float t = -3.0f * (rv * rinv2);
         T.p += mr;
@@ -307,9 +307,6 @@ struct ModeF32All {
         S.ax += T.ax; S.ay += T.ay; S.az += T.az;
         S.jx += T.jx; S.jy += T.jy; S.jz += T.jz;
         S.p += T.p;
-    }
-    __device__ static void remove_self(Sum &S, const I &i, float eps2) {
-        S.p -= i.m * __builtin_amdgcn_rsqf(eps2);
     }
     __device__ static Out7 out(const Sum &S) {
         return Out7{{(double)S.ax, (double)S.ay, (double)S.az, (double)S.jx, (double)S.jy,
@@ -364,11 +361,6 @@ struct ModeF32Fixed : ModeF32 {
         add(S.jy, fix(T.jy, F_JERK, S.bad), S.bad);
         add(S.jz, fix(T.jz, F_JERK, S.bad), S.bad);
         add(S.p, fix(T.p, F_POT, S.bad), S.bad);
-    }
-    // the self pair added m_i rsq(eps2) to the potential inside its sub-block; remove the
-    // same float value in fixed point
-    __device__ static void remove_self(Sum &S, const I &i, float eps2) {
-        add(S.p, -fix(i.m * __builtin_amdgcn_rsqf(eps2), F_POT, S.bad), S.bad);
     }
     __device__ static Out7 out(const Sum &S) {
         if (S.bad) {
@@ -458,13 +450,14 @@ struct ModeDS {
     __device__ static __forceinline__ J load_j(const Args &a, int j) {
         return J{uload(a.q0, j), uload(a.q1, j), uload(a.q2, j), uload(a.q3, j)};
     }
-    template <bool SOFT>
+    template <bool SOFT, bool MASK = false>
     __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, ds eps2,
-                                                    Tile &T) {
-        pair<SOFT>(i, J{s.q0[jj], s.q1[jj], s.q2[jj], s.q3[jj]}, eps2, T);
+                                                    Tile &T, bool self = false) {
+        pair<SOFT, MASK>(i, J{s.q0[jj], s.q1[jj], s.q2[jj], s.q3[jj]}, eps2, T, self);
     }
-    template <bool SOFT>
-    __device__ static __forceinline__ void pair(const I &i, const J &j, ds eps2, Tile &T) {
+    template <bool SOFT, bool MASK = false>
+    __device__ static __forceinline__ void pair(const I &i, const J &j, ds eps2, Tile &T,
+                                                bool self = false) {
         const float4 h = j.h, l = j.l, vh = j.vh, vl = j.vl;
         // separations: the high parts' difference is exact (two_sum), the low parts' adds one
         // rounding of about 2^-48 |x|; products skip their own renormalisation (the additions
@@ -482,7 +475,8 @@ struct ModeDS {
         ds rinv = ds_rsqrt(r2);
         if (!SOFT && !(r2.hi > 0.0f)) rinv = ds{0.f, 0.f};
         const ds rinv2 = ds_sqr_raw(rinv);
-        const ds mr = ds_mul_raw(ds{h.w, l.w}, rinv);
+        ds mr = ds_mul_raw(ds{h.w, l.w}, rinv);
+        if (MASK) mr = ds{self ? 0.0f : mr.hi, self ? 0.0f : mr.lo};
         const ds mr3 = ds_mul_raw(mr, rinv2);
         const ds t = ds_mul_f_raw(ds_mul_raw(rv, rinv2), -3.0f);
         T.p = ds_add_sloppy(T.p, mr);
@@ -497,13 +491,6 @@ struct ModeDS {
         S.ax = ds_add(S.ax, T.ax); S.ay = ds_add(S.ay, T.ay); S.az = ds_add(S.az, T.az);
         S.jx = ds_add(S.jx, T.jx); S.jy = ds_add(S.jy, T.jy); S.jz = ds_add(S.jz, T.jz);
         S.p = ds_add(S.p, T.p);
-    }
-    __device__ static void remove_self(Sum &S, const I &i, ds eps2) {
-        // the self pair's r2 is eps2 + 0 + 0 + 0, computed as in interact()
-        const ds z{0.f, 0.f};
-        const ds r2 = ds_add_sloppy(
-            ds_add_sloppy(ds_add_sloppy(eps2, ds_sqr_raw(z)), ds_sqr_raw(z)), ds_sqr_raw(z));
-        S.p = ds_sub(S.p, ds_mul(i.m, ds_rsqrt(r2)));
     }
     __device__ static Out7 out(const Sum &S) {
         return Out7{{ds_to_double(S.ax), ds_to_double(S.ay), ds_to_double(S.az),
@@ -577,14 +564,15 @@ struct ModeF64 {
         return J{uload(a.px, j), uload(a.py, j), uload(a.pz, j), uload(a.pm, j),
                  uload(a.vx, j), uload(a.vy, j), uload(a.vz, j)};
     }
-    template <bool SOFT>
+    template <bool SOFT, bool MASK = false>
     __device__ static __forceinline__ void interact(const I &i, const Smem &s, int jj, double eps2,
-                                                    Tile &T) {
+                                                    Tile &T, bool self = false) {
         const Rec &q = s.r[jj];
-        pair<SOFT>(i, J{q.x, q.y, q.z, q.m, q.vx, q.vy, q.vz}, eps2, T);
+        pair<SOFT, MASK>(i, J{q.x, q.y, q.z, q.m, q.vx, q.vy, q.vz}, eps2, T, self);
     }
-    template <bool SOFT>
-    __device__ static __forceinline__ void pair(const I &i, const J &j, double eps2, Tile &T) {
+    template <bool SOFT, bool MASK = false>
+    __device__ static __forceinline__ void pair(const I &i, const J &j, double eps2, Tile &T,
+                                                bool self = false) {
         const double dx = j.x - i.x, dy = j.y - i.y, dz = j.z - i.z;
         const double ux = j.vx - i.vx, uy = j.vy - i.vy, uz = j.vz - i.vz;
         const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, __builtin_fma(dx, dx, eps2)));
@@ -592,7 +580,8 @@ struct ModeF64 {
         double rinv = rsqrt_f64(r2);
         if (!SOFT) rinv = r2 > 0.0 ? rinv : 0.0;
         const double rinv2 = rinv * rinv;
-        const double mr = j.m * rinv;
+        double mr = j.m * rinv;
+        if (MASK) mr = self ? 0.0 : mr;
         const double mr3 = mr * rinv2;
         const double t = -3.0 * (rv * rinv2);
         T.p += mr;
@@ -606,9 +595,6 @@ struct ModeF64 {
     __device__ static void fold(Sum &S, const Tile &T) {
         S.ax += T.ax; S.ay += T.ay; S.az += T.az; S.jx += T.jx; S.jy += T.jy; S.jz += T.jz;
         S.p += T.p;
-    }
-    __device__ static void remove_self(Sum &S, const I &i, double eps2) {
-        S.p -= i.m * rsqrt_f64(__builtin_fma(0.0, 0.0, __builtin_fma(0.0, 0.0, __builtin_fma(0.0, 0.0, eps2))));
     }
     __device__ static Out7 out(const Sum &S) {
         return Out7{{S.ax, S.ay, S.az, S.jx, S.jy, S.jz, S.p}};
@@ -686,6 +672,32 @@ __device__ __forceinline__ void store_result(const ForceCommon &fc, const ForceP
     }
 }
 
+// One staged tile for a lane that takes the j-slots slice, slice + Sl, ... (Sl = 1: all):
+// float-mode tile sums folded once per tile, fixed-point sums once per FOLD-j sub-block (lanes
+// then take whole sub-blocks).  MASK: the slot `own` of the tile (if any) is the lane's own
+// particle and adds nothing.
+template <class M, int UNR, bool SOFT, bool MASK>
+__device__ __forceinline__ void sums_tile(const typename M::I &ii, const typename M::Smem &sm,
+                                          int32_t slice, int32_t Sl, int32_t own,
+                                          typename EpsOf<M>::T eps2, typename M::Sum &S) {
+    if constexpr (ModeTraits<M>::FOLD == TJ) {
+        typename M::Tile T = M::tile_zero();
+#pragma unroll UNR
+        for (int jj = slice; jj < TJ; jj += Sl)
+            M::template interact<SOFT, MASK>(ii, sm, jj, eps2, T, jj == own);
+        M::fold(S, T);
+    } else {  // lanes take whole sub-blocks of FOLD j (Sl <= TJ / FOLD)
+        constexpr int FOLD = ModeTraits<M>::FOLD;
+        for (int b = slice; b < TJ / FOLD; b += Sl) {
+            typename M::Tile T = M::tile_zero();
+#pragma unroll UNR
+            for (int jj = b * FOLD; jj < (b + 1) * FOLD; ++jj)
+                M::template interact<SOFT, MASK>(ii, sm, jj, eps2, T, jj == own);
+            M::fold(S, T);
+        }
+    }
+}
+
 // Small i-lists: S adjacent lanes share one i-particle, lane `slice` of the group takes the
 // j-particles slice, slice + S, ... of every staged tile, and the S partial sums are combined
 // by xor-shuffles within the wave (a fixed order) before the result is stored.
@@ -699,6 +711,7 @@ __device__ void force_items_split(const typename M::Args &pa, const ForceCommon 
         const int32_t iblk = w / pl.K, ks = w - (w / pl.K) * pl.K;
         const int32_t q = iblk * pl.ib + (int32_t)threadIdx.x / Sl;
         const int32_t g = q < n_i ? (fc.ilist ? fc.ilist[q] : q) : 0;
+        const int32_t own = q < n_i ? g : -1;  // the i-particle's own j-slot (none on padding)
         const typename M::I ii = M::load_i(pa, g);
         typename M::Sum S = M::sum_zero();
         const int32_t t0 = ks * pl.tps;
@@ -707,28 +720,16 @@ __device__ void force_items_split(const typename M::Args &pa, const ForceCommon 
             __syncthreads();
             M::stage(pa, sm, threadIdx.x, t * TJ + (int32_t)threadIdx.x, fc.n);
             __syncthreads();
-            if constexpr (ModeTraits<M>::FOLD == TJ) {
-                typename M::Tile T = M::tile_zero();
-#pragma unroll UNR
-                for (int jj = slice; jj < TJ; jj += Sl) M::template interact<SOFT>(ii, sm, jj, eps2, T);
-                M::fold(S, T);
-            } else {  // lanes take whole sub-blocks of FOLD j (Sl <= TJ / FOLD)
-                constexpr int FOLD = ModeTraits<M>::FOLD;
-                for (int b = slice; b < TJ / FOLD; b += Sl) {
-                    typename M::Tile T = M::tile_zero();
-#pragma unroll UNR
-                    for (int jj = b * FOLD; jj < (b + 1) * FOLD; ++jj)
-                        M::template interact<SOFT>(ii, sm, jj, eps2, T);
-                    M::fold(S, T);
-                }
+            // a tile holding a lane's own slot takes the masked loop (wave-uniform branch)
+            const int32_t rel = own - t * TJ;
+            if (SOFT && __ballot((uint32_t)rel < (uint32_t)TJ) != 0) {
+                sums_tile<M, UNR, SOFT, true>(ii, sm, slice, Sl, rel, eps2, S);
+            } else {
+                sums_tile<M, UNR, SOFT, false>(ii, sm, slice, Sl, rel, eps2, S);
             }
         }
         for (int off = Sl >> 1; off > 0; off >>= 1) M::shfl_add(S, off);
-        const int32_t jlo = t0 * TJ, jhi = t1 * TJ;
-        if (slice == 0 && q < n_i) {
-            if (SOFT && g >= jlo && g < jhi) M::remove_self(S, ii, eps2);
-            store_result<M>(fc, pl, ks, q, S);
-        }
+        if (slice == 0 && q < n_i) store_result<M>(fc, pl, ks, q, S);
     }
 }
 
@@ -737,9 +738,25 @@ __device__ void force_items_split(const typename M::Args &pa, const ForceCommon 
 // exposed to its wave, so this pays only on long j-ranges (SCALAR_MIN_TILES tiles or more).
 constexpr int32_t SCALAR_MIN_TILES = 16;
 
+// Sums over j in [ja, je) with scalar j-loads; MASK: some lane's own slot own[p] lies inside.
+template <class M, int IPL, int UNR, bool SOFT, bool MASK>
+__device__ __forceinline__ void sums_scalar_run(const typename M::Args &pa, int32_t ja, int32_t je,
+                                                const typename M::I (&ii)[IPL],
+                                                const int32_t (&own)[IPL],
+                                                typename M::Tile (&T)[IPL],
+                                                typename EpsOf<M>::T eps2) {
+#pragma unroll UNR
+    for (int32_t j = ja; j < je; ++j) {
+        const typename M::J jr = M::load_j(pa, j);
+#pragma unroll
+        for (int p = 0; p < IPL; ++p) M::template pair<SOFT, MASK>(ii[p], jr, eps2, T[p], j == own[p]);
+    }
+}
+
 template <class M, int IPL, int UNR, bool SOFT>
 __device__ __forceinline__ void block_sums_scalar(const typename M::Args &pa, int32_t n, int32_t t0,
                                                   int32_t t1, const typename M::I (&ii)[IPL],
+                                                  const int32_t (&own)[IPL],
                                                   typename M::Sum (&S)[IPL],
                                                   typename EpsOf<M>::T eps2) {
     constexpr int FOLD = ModeTraits<M>::FOLD;
@@ -753,12 +770,14 @@ __device__ __forceinline__ void block_sums_scalar(const typename M::Args &pa, in
             typename M::Tile T[IPL];
 #pragma unroll
             for (int p = 0; p < IPL; ++p) T[p] = M::tile_zero();
-#pragma unroll UNR
-            for (int32_t j = ja; j < je; ++j) {
-                const typename M::J jr = M::load_j(pa, j);
+            // a run holding some lane's own slot takes the masked loop (wave-uniform branch)
+            bool hit = false;
 #pragma unroll
-                for (int p = 0; p < IPL; ++p) M::template pair<SOFT>(ii[p], jr, eps2, T[p]);
-            }
+            for (int p = 0; p < IPL; ++p) hit = hit || (uint32_t)(own[p] - ja) < (uint32_t)(je - ja);
+            if (SOFT && __ballot(hit) != 0)
+                sums_scalar_run<M, IPL, UNR, SOFT, true>(pa, ja, je, ii, own, T, eps2);
+            else
+                sums_scalar_run<M, IPL, UNR, SOFT, false>(pa, ja, je, ii, own, T, eps2);
 #pragma unroll
             for (int p = 0; p < IPL; ++p) M::fold(S[p], T[p]);
         }
@@ -768,10 +787,24 @@ __device__ __forceinline__ void block_sums_scalar(const typename M::Args &pa, in
 // The same sums from LDS tiles staged by the whole workgroup (one j per work-item, loads
 // coalesced); every lane then reads each staged j (a broadcast).  Padding j past n has zero
 // mass and adds exact zeros, so both paths give bitwise the same sums.
+template <class M, int IPL, int UNR, bool SOFT, bool MASK>
+__device__ __forceinline__ void sums_lds_run(const typename M::Smem &sm, int jb, int je,
+                                             const typename M::I (&ii)[IPL],
+                                             const int32_t (&rel)[IPL], typename M::Tile (&T)[IPL],
+                                             typename EpsOf<M>::T eps2) {
+#pragma unroll UNR
+    for (int jj = jb; jj < je; ++jj) {
+#pragma unroll
+        for (int p = 0; p < IPL; ++p)
+            M::template interact<SOFT, MASK>(ii[p], sm, jj, eps2, T[p], jj == rel[p]);
+    }
+}
+
 template <class M, int IPL, int UNR, bool SOFT>
 __device__ __forceinline__ void block_sums_lds(const typename M::Args &pa, int32_t n,
                                                typename M::Smem &sm, int32_t t0, int32_t t1,
                                                const typename M::I (&ii)[IPL],
+                                               const int32_t (&own)[IPL],
                                                typename M::Sum (&S)[IPL],
                                                typename EpsOf<M>::T eps2) {
     constexpr int FOLD = ModeTraits<M>::FOLD;
@@ -779,15 +812,20 @@ __device__ __forceinline__ void block_sums_lds(const typename M::Args &pa, int32
         __syncthreads();
         M::stage(pa, sm, threadIdx.x, t * TJ + (int32_t)threadIdx.x, n);
         __syncthreads();
+        int32_t rel[IPL];
+#pragma unroll
+        for (int p = 0; p < IPL; ++p) rel[p] = own[p] - t * TJ;
         for (int jb = 0; jb < TJ; jb += FOLD) {
             typename M::Tile T[IPL];
 #pragma unroll
             for (int p = 0; p < IPL; ++p) T[p] = M::tile_zero();
-#pragma unroll UNR
-            for (int jj = jb; jj < jb + FOLD; ++jj) {
+            bool hit = false;
 #pragma unroll
-                for (int p = 0; p < IPL; ++p) M::template interact<SOFT>(ii[p], sm, jj, eps2, T[p]);
-            }
+            for (int p = 0; p < IPL; ++p) hit = hit || (uint32_t)(rel[p] - jb) < (uint32_t)FOLD;
+            if (SOFT && __ballot(hit) != 0)
+                sums_lds_run<M, IPL, UNR, SOFT, true>(sm, jb, jb + FOLD, ii, rel, T, eps2);
+            else
+                sums_lds_run<M, IPL, UNR, SOFT, false>(sm, jb, jb + FOLD, ii, rel, T, eps2);
 #pragma unroll
             for (int p = 0; p < IPL; ++p) M::fold(S[p], T[p]);
         }
@@ -806,6 +844,12 @@ __device__ __forceinline__ void block_sums_lds(const typename M::Args &pa, int32
 // (force_items_split).
 // K == 1: results go straight to acc/jerk/pot; K > 1: to the partial planes for
 // force_reduce.  The potential sum is negated on output.
+// The self pair j = i is excluded (Eq. Force sums over j != i): every run of j-slots (a tile, or
+// a fixed-point sub-block) that holds some lane's own particle is taken by a masked copy of the
+// loop in which that slot adds nothing; all other runs take the unmasked loop.  (With eps > 0
+// the self slot would add m_i / eps to the potential's float tile sum, whose rounding would
+// then be relative to m_i / eps rather than to the potential; with eps = 0 every pair at zero
+// separation is skipped anyway.)
 // ------------------------------------------------------------------------------------------
 // CLS only separates the symbols of full-force launches (0) and block-step launches (1) so that
 // profilers report the two launch classes apart; the code is the same.
@@ -836,33 +880,30 @@ __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCom
     for (int32_t v = (int32_t)(((int64_t)pl.items * xcd) / nx) + (int32_t)blockIdx.x / nx;
          v < v_end; v += v_step) {
         const int32_t ks = v / pl.n_iblk, iblk = v - ks * pl.n_iblk;
-        int32_t q[IPL], g[IPL];
+        int32_t q[IPL], own[IPL];
         typename M::I ii[IPL];
         typename M::Sum S[IPL];
 #pragma unroll
         for (int p = 0; p < IPL; ++p) {
             q[p] = iblk * (WG * IPL) + p * WG + (int32_t)threadIdx.x;
-            g[p] = q[p] < n_i ? (fc.ilist ? fc.ilist[q[p]] : q[p]) : 0;
-            ii[p] = M::load_i(pa, g[p]);
+            const int32_t g = q[p] < n_i ? (fc.ilist ? fc.ilist[q[p]] : q[p]) : 0;
+            own[p] = q[p] < n_i ? g : -1;  // the i-particle's own j-slot (none on padding)
+            ii[p] = M::load_i(pa, g);
             S[p] = M::sum_zero();
         }
         const int32_t t0 = ks * pl.tps;
         const int32_t t1 = t0 + pl.tps < pl.ntiles ? t0 + pl.tps : pl.ntiles;
         if constexpr (ModeTraits<M>::SCALAR_J) {
             if (pl.tps >= SCALAR_MIN_TILES)
-                block_sums_scalar<M, IPL, UNR, SOFT>(pa, fc.n, t0, t1, ii, S, eps2);
+                block_sums_scalar<M, IPL, UNR, SOFT>(pa, fc.n, t0, t1, ii, own, S, eps2);
             else
-                block_sums_lds<M, IPL, UNR, SOFT>(pa, fc.n, sm, t0, t1, ii, S, eps2);
+                block_sums_lds<M, IPL, UNR, SOFT>(pa, fc.n, sm, t0, t1, ii, own, S, eps2);
         } else {
-            block_sums_lds<M, IPL, UNR, SOFT>(pa, fc.n, sm, t0, t1, ii, S, eps2);
+            block_sums_lds<M, IPL, UNR, SOFT>(pa, fc.n, sm, t0, t1, ii, own, S, eps2);
         }
-        const int32_t jlo = t0 * TJ, jhi = t1 * TJ;
 #pragma unroll
-        for (int p = 0; p < IPL; ++p) {
-            if (q[p] >= n_i) continue;
-            if (SOFT && g[p] >= jlo && g[p] < jhi) M::remove_self(S[p], ii[p], eps2);
-            store_result<M>(fc, pl, ks, q[p], S[p]);
-        }
+        for (int p = 0; p < IPL; ++p)
+            if (q[p] < n_i) store_result<M>(fc, pl, ks, q[p], S[p]);
     }
 }
 
@@ -1031,6 +1072,12 @@ __device__ __forceinline__ int32_t level_from_dt(double dt, int32_t lmin, int32_
 
 __global__ void __launch_bounds__(WG) zero_ticks(int64_t *tick, int32_t n) {
     for (int32_t i = blockIdx.x * WG + threadIdx.x; i < n; i += gridDim.x * WG) tick[i] = 0;
+}
+
+// Zero two small word arrays (a fill kernel, so that the call stays capturable in a graph).
+__global__ void __launch_bounds__(WG) zero_words(int64_t *a, int32_t na, int32_t *b, int32_t nb) {
+    for (int32_t i = threadIdx.x; i < na; i += WG) a[i] = 0;
+    for (int32_t i = threadIdx.x; i < nb; i += WG) b[i] = 0;
 }
 
 __global__ void __launch_bounds__(WG) reset_control(DevControl *ctl) {
@@ -1414,6 +1461,31 @@ __global__ void __launch_bounds__(WG) fused_correct_level(StateRW s, const int32
         ctl->n_active_sum += n_act;
         ctl->n_pending = 0;
     }
+}
+
+// ------------------------------------------------------------------------------------------
+// Calibration: the FP32 fused multiply-add issue rate (not part of the method).  Every
+// work-item runs FMA_CHAINS independent chains acc += x_c * m for `iters` iterations (two-operand
+// v_fmac_f32, no packed FP32), so the rate is bounded by VALU issue alone; the sums are stored
+// only if they hit an impossible value, which keeps the work from being removed.
+// ------------------------------------------------------------------------------------------
+constexpr int FMA_CHAINS = 16;
+
+__global__ void __launch_bounds__(WG) fma_probe(int32_t iters, float m, float *sink) {
+    float x[FMA_CHAINS], acc[FMA_CHAINS];
+#pragma unroll
+    for (int c = 0; c < FMA_CHAINS; ++c) {
+        x[c] = (float)(threadIdx.x + c) * 1e-3f;
+        acc[c] = (float)c;
+    }
+    for (int32_t it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int c = 0; c < FMA_CHAINS; ++c) acc[c] = __builtin_fmaf(x[c], m, acc[c]);
+    }
+    float t = 0.0f;
+#pragma unroll
+    for (int c = 0; c < FMA_CHAINS; ++c) t += acc[c];
+    if (t == -1.0f) sink[0] = t;
 }
 
 // ------------------------------------------------------------------------------------------

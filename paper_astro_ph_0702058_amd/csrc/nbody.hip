@@ -50,7 +50,9 @@ struct nb_ctx {
     int device = 0;
     int num_cu = 256;
 
-    // library-owned device buffers
+    // device work buffers, carved from the caller's workspace by nb_bind_scratch()
+    bool scratch_ok = false;
+    size_t scratch_need = 0;
     void *jbuf = nullptr;
     JStreamView js{};
     double *acc1 = nullptr, *jerk1 = nullptr, *pot1 = nullptr;  // block force outputs, ld = n
@@ -103,7 +105,12 @@ struct nb_ens {
     int64_t *part_off = nullptr;
     double *eps2 = nullptr, *partial = nullptr, *crit = nullptr, *ek = nullptr, *ep = nullptr;
     EnsCluster *cl = nullptr;
+    bool scratch_ok = false;
+    size_t scratch_need = 0;
     int32_t unroll = 2, grid_force = 1;
+    // blocks the clusters' own workgroups advance (see ens_local_block)
+    int64_t local_limit = 0, local_work = 1 << 21;
+    int32_t local_steps = 64;
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     double g_eta = -1.0;
@@ -201,11 +208,19 @@ Variant default_variant(int32_t n, int prec, int num_cu, bool block) {
     return v;
 }
 
-nb_status alloc(nb_ctx *c, void **p, size_t bytes) {
-    hipError_t e = hipMalloc(p, bytes > 0 ? bytes : 16);
-    if (e != hipSuccess) return fail(c, NB_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-    return NB_OK;
-}
+// Consecutive 256-byte aligned pieces of one caller-owned device allocation; with a NULL base it
+// only counts the bytes (the pointers it hands out are then NULL).
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <class T>
+    T *take(size_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += std::max<size_t>(count * sizeof(T), 16);
+        return p;
+    }
+};
 
 nb_status enqueue_predict(nb_ctx *c, const int64_t *t, int guard, hipStream_t s) {
     const StateView sv = state_view(c);
@@ -270,26 +285,34 @@ void launch_fixed(const ModeF32Fixed::Args &pa, const ForceCommon &fc, const Var
 // Largest lane split of a precision's force kernel (fixed-point sums: whole 64-j sub-blocks).
 int32_t smax_of(int prec) { return prec == NB_FP32_FIXED ? TJ / ModeTraits<ModeF32Fixed>::FOLD : 64; }
 
-// Largest K * P over every i-count up to n, for one variant.
-int64_t partial_rows_for(int32_t n, const Variant &v, int32_t smax) {
+// Largest K * P over every i-count up to n_i_max against n j-particles, for one variant (the
+// plan depends on the count only through its number of i-blocks, and lists shorter than a
+// workgroup have the one i-block's K with fewer rows).
+int64_t partial_rows_upto(int32_t n_i_max, int32_t n, const Variant &v, int32_t smax) {
     const int32_t ib = WG * v.ipl;
     int64_t rows = 0;
-    for (int32_t nb = 1; nb <= (n + ib - 1) / ib; ++nb) {
-        const ForcePlan pl = make_plan((int32_t)std::min<int64_t>((int64_t)nb * ib, n), n, ib,
-                                       v.target, v.kmax, smax);
+    for (int32_t nb = 1; nb <= (n_i_max + ib - 1) / ib; ++nb) {
+        const ForcePlan pl = make_plan((int32_t)std::min<int64_t>((int64_t)nb * ib, n_i_max), n,
+                                       ib, v.target, v.kmax, smax);
         if (pl.K > 1) rows = std::max<int64_t>(rows, (int64_t)pl.K * pl.P);
         if (pl.K == 1) break;  // K only falls as the number of i-blocks grows
     }
     return rows;
 }
 
+// Largest K * P over every i-count up to n, for one variant.
+int64_t partial_rows_for(int32_t n, const Variant &v, int32_t smax) {
+    return partial_rows_upto(n, n, v, smax);
+}
+
+// partial: the j-split partial planes (NULL: the context's own, in its workspace).
 nb_status enqueue_force(nb_ctx *c, const Variant &v, int cls, const int32_t *ilist,
                         const int32_t *n_i_dev, int32_t n_i_max, double *acc, double *jerk,
-                        double *pot, int32_t ld, hipStream_t s) {
+                        double *pot, int32_t ld, hipStream_t s, double *partial = nullptr) {
     const int32_t ib = WG * v.ipl;
     const int32_t smax = smax_of(c->prec);
     ForceCommon fc{c->n, ilist, n_i_dev, n_i_max, v.target, v.kmax, acc, jerk, pot, ld,
-                   c->partial, c->ctl, smax};
+                   partial ? partial : c->partial, c->ctl, smax};
     int32_t grid;
     if (n_i_dev) {
         // the count is known only on the device: enough workgroups for any count up to n_i_max
@@ -433,8 +456,101 @@ void drop_graph(nb_ctx *c) {
     c->graph_steps = 0;
 }
 
+bool ctx_args_ok(int32_t n, int32_t precision) {
+    return n >= 1 && n <= (1 << 28) && precision >= NB_FP32 && precision <= NB_FP32_FIXED;
+}
+
+int device_cus(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        return prop.multiProcessorCount;
+    return 256;
+}
+
+// Launch defaults and the sizes of the work buffers, from n, the precision and the CU count.
+void ctx_plan(nb_ctx *c) {
+    const int32_t n = c->n, precision = c->prec;
+    c->var_full = default_variant(n, precision, c->num_cu, false);
+    c->var_block = default_variant(n, precision, c->num_cu, true);
+    c->max_target = c->num_cu * FULL_ITEMS_PER_CU;
+    // partial planes: K * P rows for the largest plan of either target family, one or two i
+    // per work-item, for any count up to n (variant_valid refuses a variant, e.g. four i per
+    // work-item at a large target, whose plan would need more)
+    int64_t rows = 0;
+    for (int ipl = 1; ipl <= 2; ++ipl) {
+        // two i per work-item: sized for half the full target (the same partial rows)
+        rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->num_cu * FULL_ITEMS_PER_CU / ipl,
+                                                          FULL_KMAX}, smax_of(precision)));
+        rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->num_cu * BLOCK_ITEMS_PER_CU,
+                                                          1 << 16}, smax_of(precision)));
+    }
+    // the force VJP writes K * P rows of its plan even when K = 1
+    {
+        const ForcePlan pv = make_plan(n, n, WG, c->num_cu * BLOCK_ITEMS_PER_CU, 1 << 16);
+        rows = std::max<int64_t>(rows, (int64_t)pv.K * pv.P);
+    }
+    c->partial_rows = rows;
+    const int64_t N = n;
+    c->sched_groups = (int32_t)std::min<int64_t>(std::max<int64_t>((N + 4095) / 4096, 1), 1024);
+    c->sched_chunk = (int32_t)((N + c->sched_groups - 1) / c->sched_groups);
+    // the fused step predicts while it counts: chunks of 1024 (more workgroups), up to 2048
+    c->fused_groups = (int32_t)std::min<int64_t>(std::max<int64_t>((N + 1023) / 1024, 1), 2048);
+    c->fused_chunk = (int32_t)((N + c->fused_groups - 1) / c->fused_groups);
+}
+
+// Work buffers of a context in its workspace (base NULL: only the total size, returned).
+//   j-particle stream   64 B per particle (the widest layout, double-single)
+//   block force outputs acc, jerk (3 n each), pot (n), FP64
+//   j-split partials    7 * partial_rows FP64
+//   block list (n int32), criterion inputs (2 n FP64), per-workgroup minima and counts,
+//   scheduler record, energy scratch (8 n + 2 FP64), adjoint scratch (12 n FP64) and flags,
+//   the zero tick and the tuner's device count.
+size_t ctx_layout(nb_ctx *c, char *base) {
+    Carver k{base};
+    const size_t N = (size_t)c->n;
+    c->jbuf = k.take<char>(64 * N);
+    c->js = JStreamView{};
+    if (base) {
+        char *b = (char *)c->jbuf;
+        if (c->prec == NB_FP32 || c->prec == NB_FP32_FIXED) {
+            c->js.px = (double *)b; c->js.py = c->js.px + N; c->js.pz = c->js.py + N;
+            c->js.vm = (float4 *)(c->js.pz + N);
+        } else if (c->prec == NB_DS) {
+            c->js.q0 = (float4 *)b; c->js.q1 = c->js.q0 + N; c->js.q2 = c->js.q1 + N;
+            c->js.q3 = c->js.q2 + N;
+        } else if (c->prec == NB_FP32_ALL) {
+            c->js.q0 = (float4 *)b; c->js.q1 = c->js.q0 + N;
+        } else {
+            c->js.px = (double *)b; c->js.py = c->js.px + N; c->js.pz = c->js.py + N;
+            c->js.pm = c->js.pz + N; c->js.vx = c->js.pm + N; c->js.vy = c->js.vx + N;
+            c->js.vz = c->js.vy + N;
+        }
+    }
+    c->acc1 = k.take<double>(7 * N);
+    c->jerk1 = base ? c->acc1 + 3 * N : nullptr;
+    c->pot1 = base ? c->jerk1 + 3 * N : nullptr;
+    c->partial = k.take<double>((size_t)std::max<int64_t>(c->partial_rows, 1) * 7);
+    c->active = k.take<int32_t>(N);
+    c->crit = k.take<double>(2 * N);
+    const int32_t ngroups = std::max(c->sched_groups, c->fused_groups);
+    c->wgmin = k.take<int64_t>(ngroups);
+    c->cnt = k.take<int32_t>(ngroups);
+    c->ctl = k.take<DevControl>(1);
+    c->exp_ = k.take<double>(8 * N + 2);
+    if (base) {
+        c->evp = c->exp_ + 3 * N; c->ew = c->evp + 3 * N; c->ek = c->ew + N; c->eout = c->ek + N;
+    }
+    c->adj = k.take<double>(12 * N);
+    c->adj_flag = k.take<int32_t>(4);
+    c->t_zero = k.take<int64_t>(1);
+    c->tune_n = k.take<int32_t>(1);
+    return k.off;
+}
+
 nb_status need(nb_ctx *c, bool bound_required = true) {
     if (!c) return NB_EINVAL;
+    if (!c->scratch_ok)
+        return fail(c, NB_ESTATE, "no workspace bound (call nb_bind_scratch)");
     if (bound_required && !c->bound) return fail(c, NB_ESTATE, "state not bound (call nb_bind)");
     HIP_OK(c, hipSetDevice(c->device));
     return NB_OK;
@@ -452,93 +568,52 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
                     int32_t precision) {
     if (!out) return NB_EINVAL;
     *out = nullptr;
-    if (n < 1 || n > (1 << 28) || !(eps >= 0.0) || !std::isfinite(eps) || lmin < 0 ||
-        lmax < lmin || lmax > 52 || precision < NB_FP32 || precision > NB_FP32_FIXED)
+    if (!ctx_args_ok(n, precision) || !(eps >= 0.0) || !std::isfinite(eps) || lmin < 0 ||
+        lmax < lmin || lmax > 52)
         return NB_EINVAL;
     nb_ctx *c = new nb_ctx();
     c->n = n; c->eps = eps; c->lmin = lmin; c->lmax = lmax; c->prec = precision;
-    nb_status r;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return NB_EDEVICE; }
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess && prop.multiProcessorCount > 0)
-        c->num_cu = prop.multiProcessorCount;
-    c->var_full = default_variant(n, precision, c->num_cu, false);
-    c->var_block = default_variant(n, precision, c->num_cu, true);
-    c->max_target = c->num_cu * FULL_ITEMS_PER_CU;
-    const size_t N = (size_t)n;
-    // j-stream: up to 64 bytes per particle
-    if ((r = alloc(c, &c->jbuf, 64 * N)) != NB_OK) { nb_destroy(c); return r; }
-    {
-        char *b = (char *)c->jbuf;
-        if (precision == NB_FP32 || precision == NB_FP32_FIXED) {
-            c->js.px = (double *)b; c->js.py = c->js.px + N; c->js.pz = c->js.py + N;
-            c->js.vm = (float4 *)(c->js.pz + N);
-        } else if (precision == NB_DS) {
-            c->js.q0 = (float4 *)b; c->js.q1 = c->js.q0 + N; c->js.q2 = c->js.q1 + N;
-            c->js.q3 = c->js.q2 + N;
-        } else if (precision == NB_FP32_ALL) {
-            c->js.q0 = (float4 *)b; c->js.q1 = c->js.q0 + N;
-        } else {
-            c->js.px = (double *)b; c->js.py = c->js.px + N; c->js.pz = c->js.py + N;
-            c->js.pm = c->js.pz + N; c->js.vx = c->js.pm + N; c->js.vy = c->js.vx + N;
-            c->js.vz = c->js.vy + N;
-        }
-    }
-    void *p;
-    if ((r = alloc(c, &p, 7 * N * sizeof(double))) != NB_OK) { nb_destroy(c); return r; }
-    c->acc1 = (double *)p; c->jerk1 = c->acc1 + 3 * N; c->pot1 = c->jerk1 + 3 * N;
-    // partial planes: K * P rows for the largest plan of either target family, one or two i
-    // per work-item, for any count up to n (variant_valid refuses a variant, e.g. four i per
-    // work-item at a large target, whose plan would need more)
-    {
-        int64_t rows = 0;
-        for (int ipl = 1; ipl <= 2; ++ipl) {
-            // two i per work-item: sized for half the full target (the same partial rows)
-            rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->num_cu * FULL_ITEMS_PER_CU / ipl,
-                                                              FULL_KMAX}, smax_of(precision)));
-            rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->num_cu * BLOCK_ITEMS_PER_CU,
-                                                              1 << 16}, smax_of(precision)));
-        }
-        c->partial_rows = rows;
-        if ((r = alloc(c, &p, (size_t)std::max<int64_t>(rows, 1) * 7 * sizeof(double))) != NB_OK) {
-            nb_destroy(c); return r;
-        }
-        c->partial = (double *)p;
-    }
-    if ((r = alloc(c, &p, N * sizeof(int32_t))) != NB_OK) { nb_destroy(c); return r; }
-    c->active = (int32_t *)p;
-    if ((r = alloc(c, &p, 2 * N * sizeof(double))) != NB_OK) { nb_destroy(c); return r; }
-    c->crit = (double *)p;
-    c->sched_groups = (int32_t)std::min<int64_t>(std::max<int64_t>((N + 4095) / 4096, 1), 1024);
-    c->sched_chunk = (int32_t)((N + c->sched_groups - 1) / c->sched_groups);
-    // the fused step predicts while it counts: chunks of 1024 (more workgroups), up to 2048
-    c->fused_groups = (int32_t)std::min<int64_t>(std::max<int64_t>((N + 1023) / 1024, 1), 2048);
-    c->fused_chunk = (int32_t)((N + c->fused_groups - 1) / c->fused_groups);
-    const int32_t ngroups = std::max(c->sched_groups, c->fused_groups);
-    if ((r = alloc(c, &p, ngroups * sizeof(int64_t))) != NB_OK) { nb_destroy(c); return r; }
-    c->wgmin = (int64_t *)p;
-    if ((r = alloc(c, &p, ngroups * sizeof(int32_t))) != NB_OK) { nb_destroy(c); return r; }
-    c->cnt = (int32_t *)p;
-    if ((r = alloc(c, &p, sizeof(DevControl))) != NB_OK) { nb_destroy(c); return r; }
-    c->ctl = (DevControl *)p;
-    if ((r = alloc(c, &p, (8 * N + 2) * sizeof(double))) != NB_OK) { nb_destroy(c); return r; }
-    c->exp_ = (double *)p; c->evp = c->exp_ + 3 * N; c->ew = c->evp + 3 * N; c->ek = c->ew + N;
-    c->eout = c->ek + N;
-    if ((r = alloc(c, &p, 12 * N * sizeof(double) + 16)) != NB_OK) { nb_destroy(c); return r; }
-    c->adj = (double *)p;
-    c->adj_flag = (int32_t *)(c->adj + 12 * N);
-    if ((r = alloc(c, &p, 2 * sizeof(int64_t))) != NB_OK) { nb_destroy(c); return r; }
-    c->t_zero = (int64_t *)p;
-    c->tune_n = (int32_t *)(c->t_zero + 1);
-    if (hipMemset(c->t_zero, 0, 2 * sizeof(int64_t)) != hipSuccess ||
-        hipMemset(c->adj_flag, 0, 16) != hipSuccess ||
-        hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-        nb_destroy(c);
+    c->num_cu = device_cus(c->device);
+    ctx_plan(c);
+    c->scratch_need = ctx_layout(c, nullptr);
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
         return NB_EDEVICE;
     }
-    reset_control<<<1, WG>>>(c->ctl);
-    if (hipDeviceSynchronize() != hipSuccess) { nb_destroy(c); return NB_EDEVICE; }
     *out = c;
+    return NB_OK;
+}
+
+size_t nb_scratch_bytes(int32_t n, int32_t precision) {
+    if (!ctx_args_ok(n, precision)) return 0;
+    int dev = 0;
+    nb_ctx c;
+    c.n = n; c.prec = precision;
+    c.num_cu = hipGetDevice(&dev) == hipSuccess ? device_cus(dev) : 256;  // no device: MI355X
+    ctx_plan(&c);
+    return ctx_layout(&c, nullptr);
+}
+
+nb_status nb_bind_scratch(nb_ctx *c, void *scratch, size_t bytes) {
+    if (!c) return NB_EINVAL;
+    if (!scratch) return fail(c, NB_EINVAL, "nb_bind_scratch: workspace pointer required");
+    if ((uintptr_t)scratch % 256 != 0)
+        return fail(c, NB_EINVAL, "nb_bind_scratch: workspace must be 256-byte aligned");
+    if (bytes < c->scratch_need)
+        return fail(c, NB_EINVAL, "nb_bind_scratch: %zu bytes given, %zu needed", bytes,
+                    c->scratch_need);
+    HIP_OK(c, hipSetDevice(c->device));
+    if (c->stream) HIP_OK(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    ctx_layout(c, (char *)scratch);
+    zero_words<<<1, WG, 0, c->stream>>>(c->t_zero, 2, c->adj_flag, 4);
+    LAUNCH_OK(c);
+    reset_control<<<1, WG, 0, c->stream>>>(c->ctl);
+    LAUNCH_OK(c);
+    c->scratch_ok = true;
+    c->predicted = false;
+    c->forced = false;
     return NB_OK;
 }
 
@@ -552,10 +627,6 @@ nb_status nb_destroy(nb_ctx *c) {
         (void)hipEventDestroy(p.start);
         (void)hipEventDestroy(p.stop);
     }
-    void *bufs[] = {c->jbuf, c->acc1, c->partial, c->active, c->crit, c->wgmin, c->cnt, c->ctl,
-                    c->exp_, c->t_zero, c->adj};
-    for (void *b : bufs)
-        if (b) (void)hipFree(b);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
     return NB_OK;
@@ -609,6 +680,7 @@ nb_status nb_schedule_block(nb_ctx *c, double eta) {
 
 nb_status nb_active(nb_ctx *c, const int32_t **idx, const int32_t **n_act) {
     if (!c || !idx || !n_act) return NB_EINVAL;
+    if (!c->scratch_ok) return fail(c, NB_ESTATE, "no workspace bound (call nb_bind_scratch)");
     *idx = c->active;
     *n_act = &c->ctl->n_act;
     return NB_OK;
@@ -726,6 +798,7 @@ nb_status nb_energy(nb_ctx *c, double *ekin, double *epot) {
 
 nb_status nb_read_control(nb_ctx *c, nb_control *out) {
     if (!c || !out) return NB_EINVAL;
+    if (!c->scratch_ok) return fail(c, NB_ESTATE, "no workspace bound (call nb_bind_scratch)");
     HIP_OK(c, hipSetDevice(c->device));
     DevControl h;
     HIP_OK(c, hipMemcpyAsync(&h, c->ctl, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -757,8 +830,10 @@ static nb_status enqueue_force_vjp(nb_ctx *c, const double *ab, const double *kb
     a.px = c->js.px; a.py = c->js.py; a.pz = c->js.pz; a.vm = c->js.vm;
     a.pm = c->js.pm; a.vx = c->js.vx; a.vy = c->js.vy; a.vz = c->js.vz;
     a.ab = ab; a.kb = kb; a.eps2 = c->eps * c->eps; a.partial = c->partial;
-    a.target = c->num_cu * BLOCK_ITEMS_PER_CU; a.kmax = 1 << 16;  // covered by the allocation
+    a.target = c->num_cu * BLOCK_ITEMS_PER_CU; a.kmax = 1 << 16;
     const ForcePlan pl = make_plan(c->n, c->n, WG, a.target, a.kmax);
+    if ((int64_t)pl.K * pl.P > c->partial_rows)  // the workspace is sized for this plan
+        return fail(c, NB_ESTATE, "force VJP plan exceeds the partial planes");
     const int32_t grid = std::max(1, std::min(pl.items, 1 << 20));
     if (c->prec == NB_FP32) force_vjp_kernel<0><<<grid, WG, 0, s>>>(a);
     else force_vjp_kernel<2><<<grid, WG, 0, s>>>(a);
@@ -940,8 +1015,36 @@ nb_status nb_profile_read(nb_ctx *c, int32_t which, double *ms_total, int64_t *l
     return NB_OK;
 }
 
+nb_status nb_fma_rate(nb_ctx *c, double *tflops) {
+    nb_status r;
+    if ((r = need(c, false)) != NB_OK) return r;
+    if (!tflops) return fail(c, NB_EINVAL, "nb_fma_rate: host output required");
+    hipStream_t s = c->stream;
+    const int32_t iters = 4096, grid = c->num_cu * 64;
+    hipEvent_t e0, e1;
+    HIP_OK(c, hipEventCreate(&e0));
+    HIP_OK(c, hipEventCreate(&e1));
+    double best = 0.0;
+    for (int rep = 0; rep < 4; ++rep) {  // the first launch warms up; the best of the rest
+        HIP_OK(c, hipEventRecord(e0, s));
+        fma_probe<<<grid, WG, 0, s>>>(iters, 1e-7f, (float *)c->eout);
+        LAUNCH_OK(c);
+        HIP_OK(c, hipEventRecord(e1, s));
+        HIP_OK(c, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_OK(c, hipEventElapsedTime(&ms, e0, e1));
+        const double flop = 2.0 * FMA_CHAINS * (double)iters * grid * WG;
+        if (rep > 0 && ms > 0.f) best = std::max(best, flop / (ms * 1e-3) / 1e12);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *tflops = best;
+    return NB_OK;
+}
+
 nb_status nb_sync(nb_ctx *c) {
     if (!c) return NB_EINVAL;
+    if (!c->scratch_ok) return fail(c, NB_ESTATE, "no workspace bound (call nb_bind_scratch)");
     HIP_OK(c, hipSetDevice(c->device));
     return latched(c);
 }
@@ -959,6 +1062,7 @@ EnsView ens_view(const nb_ens *e, int64_t t_end) {
     v.prow = e->prow; v.eps2 = e->eps2; v.cl = e->cl; v.active = e->active;
     v.partial = e->partial; v.crit = e->crit; v.flags = e->flags;
     v.lmin = e->lmin; v.lmax = e->lmax; v.tick_len = std::ldexp(1.0, -e->lmax); v.t_end = t_end;
+    v.local_limit = e->local_limit; v.local_steps = e->local_steps; v.local_work = e->local_work;
     return v;
 }
 
@@ -1002,14 +1106,23 @@ void ens_launch_force(nb_ens *e, const EnsView &v, hipStream_t s) {
     else ens_force<M, 2><<<e->grid_force, WG, lds, s>>>(v, rw);
 }
 
-nb_status ens_enqueue_local(nb_ens *e, double eta, int32_t phase, int64_t t_end, hipStream_t s) {
-    ens_local<<<e->C, WGL, 0, s>>>(ens_view(e, t_end), ens_state(e), eta, phase);
+// local = false: every block goes through ens_force (the start of a run)
+nb_status ens_enqueue_local(nb_ens *e, double eta, int32_t phase, int64_t t_end, hipStream_t s,
+                            bool local = true) {
+    EnsView v = ens_view(e, t_end);
+    if (!local) v.local_limit = 0;
+    switch (e->prec) {
+        case NB_FP32: ens_local<ModeF32><<<e->C, WGL, 0, s>>>(v, ens_state(e), eta, phase); break;
+        case NB_DS: ens_local<ModeDS><<<e->C, WGL, 0, s>>>(v, ens_state(e), eta, phase); break;
+        default: ens_local<ModeF64><<<e->C, WGL, 0, s>>>(v, ens_state(e), eta, phase); break;
+    }
     ELAUNCH_OK(e);
     return NB_OK;
 }
 
-nb_status ens_enqueue_force(nb_ens *e, int64_t t_end, hipStream_t s) {
-    const EnsView v = ens_view(e, t_end);
+nb_status ens_enqueue_force(nb_ens *e, int64_t t_end, hipStream_t s, bool local = true) {
+    EnsView v = ens_view(e, t_end);
+    if (!local) v.local_limit = 0;
     switch (e->prec) {
         case NB_FP32: ens_launch_force<ModeF32>(e, v, s); break;
         case NB_DS: ens_launch_force<ModeDS>(e, v, s); break;
@@ -1019,8 +1132,9 @@ nb_status ens_enqueue_force(nb_ens *e, int64_t t_end, hipStream_t s) {
     return NB_OK;
 }
 
-// One global step: the force of every cluster's selected block, then each cluster corrects it
-// and selects and predicts its next block.
+// One global step: the force of every cluster's selected block that is not a local block,
+// then one workgroup per cluster corrects it, selects the next block and advances the cluster
+// by its local blocks.
 nb_status ens_enqueue_step(nb_ens *e, double eta, int64_t t_end, hipStream_t s) {
     nb_status r = ens_enqueue_force(e, t_end, s);
     if (r != NB_OK) return r;
@@ -1028,6 +1142,7 @@ nb_status ens_enqueue_step(nb_ens *e, double eta, int64_t t_end, hipStream_t s) 
 }
 
 nb_status ens_upload_tables(nb_ens *e) {
+    if (!e->scratch_ok) return NB_OK;  // uploaded when a workspace is bound
     EHIP_OK(e, hipMemcpy(e->K, e->K_h.data(), e->C * sizeof(int32_t), hipMemcpyHostToDevice));
     EHIP_OK(e, hipMemcpy(e->tpi, e->tpi_h.data(), e->C * sizeof(int32_t), hipMemcpyHostToDevice));
     return NB_OK;
@@ -1039,6 +1154,54 @@ void ens_drop_graph(nb_ens *e) {
     e->gexec = nullptr;
     e->graph = nullptr;
     e->g_steps = 0;
+}
+
+bool ens_args_ok(int32_t n_clusters, const int32_t *offsets, int32_t precision) {
+    if (n_clusters < 1 || n_clusters > 8192 || !offsets || offsets[0] != 0 ||
+        precision < NB_FP32 || precision > NB_FP64)
+        return false;
+    for (int32_t c = 0; c < n_clusters; ++c)
+        if (offsets[c + 1] <= offsets[c]) return false;
+    return offsets[n_clusters] <= (1 << 28);
+}
+
+// Host tables of an ensemble (offsets, partial-plane sizes, default layout).
+void ens_plan(nb_ens *e, int32_t n_clusters, const int32_t *offsets, int32_t precision) {
+    e->C = n_clusters; e->ntot = offsets[n_clusters]; e->prec = precision;
+    e->off_h.assign(offsets, offsets + n_clusters + 1);
+    e->tpi_h.assign(n_clusters, 1);
+    e->prow_h.resize(n_clusters);
+    e->part_off_h.resize(n_clusters + 1);
+    e->part_off_h[0] = 0;
+    for (int32_t c = 0; c < n_clusters; ++c) {
+        const int32_t n_c = offsets[c + 1] - offsets[c];
+        e->prow_h[c] = n_c;
+        e->part_off_h[c + 1] = e->part_off_h[c] + (int64_t)((n_c + TJ - 1) / TJ) * 7 * n_c;
+    }
+    e->unroll = 2;
+    ens_derive(e);
+}
+
+// Device buffers of an ensemble in its workspace (base NULL: only the total size): the cluster
+// tables, per-cluster records, block lists (one slot per particle), flags, the partial planes
+// (sized for one tile per work item, the finest split), criterion and energy scratch.
+size_t ens_layout(nb_ens *e, char *base) {
+    Carver k{base};
+    const size_t C = (size_t)e->C, N = (size_t)e->ntot;
+    e->off = k.take<int32_t>(C + 1);
+    e->K = k.take<int32_t>(C);
+    e->tpi = k.take<int32_t>(C);
+    e->prow = k.take<int32_t>(C);
+    e->part_off = k.take<int64_t>(C + 1);
+    e->eps2 = k.take<double>(C);
+    e->cl = k.take<EnsCluster>(C);
+    e->active = k.take<int32_t>(N);
+    e->flags = k.take<int32_t>(2);
+    e->partial = k.take<double>((size_t)e->part_off_h[C]);
+    e->crit = k.take<double>(2 * N);
+    e->ek = k.take<double>(2 * C);
+    e->ep = base ? e->ek + C : nullptr;
+    return k.off;
 }
 
 nb_status ens_flags(nb_ens *e) {
@@ -1060,63 +1223,58 @@ nb_status nb_ens_create(nb_ens **out, int32_t n_clusters, const int32_t *offsets
                         const double *eps, int32_t lmin, int32_t lmax, int32_t precision) {
     if (!out) return NB_EINVAL;
     *out = nullptr;
-    if (n_clusters < 1 || !offsets || !eps || lmin < 0 || lmax < lmin || lmax > 52 ||
-        precision < NB_FP32 || precision > NB_FP64 || offsets[0] != 0)
+    if (!ens_args_ok(n_clusters, offsets, precision) || !eps || lmin < 0 || lmax < lmin ||
+        lmax > 52)
         return NB_EINVAL;
     for (int32_t c = 0; c < n_clusters; ++c)
-        if (offsets[c + 1] <= offsets[c] || !(eps[c] > 0.0) || !std::isfinite(eps[c])) return NB_EINVAL;
-    if (offsets[n_clusters] > (1 << 28) || n_clusters > 8192) return NB_EINVAL;
+        if (!(eps[c] > 0.0) || !std::isfinite(eps[c])) return NB_EINVAL;
     nb_ens *e = new nb_ens();
-    e->C = n_clusters; e->ntot = offsets[n_clusters]; e->lmin = lmin; e->lmax = lmax;
-    e->prec = precision;
+    e->lmin = lmin; e->lmax = lmax;
     if (hipGetDevice(&e->device) != hipSuccess) { delete e; return NB_EDEVICE; }
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, e->device) == hipSuccess && prop.multiProcessorCount > 0)
-        e->num_cu = prop.multiProcessorCount;
-    e->off_h.assign(offsets, offsets + n_clusters + 1);
+    e->num_cu = device_cus(e->device);
+    ens_plan(e, n_clusters, offsets, precision);
     e->eps2_h.resize(n_clusters);
     for (int32_t c = 0; c < n_clusters; ++c) e->eps2_h[c] = eps[c] * eps[c];
-    e->tpi_h.assign(n_clusters, 1);
-    e->prow_h.resize(n_clusters);
-    e->part_off_h.resize(n_clusters + 1);
-    e->part_off_h[0] = 0;
-    for (int32_t c = 0; c < n_clusters; ++c) {
-        const int32_t n_c = offsets[c + 1] - offsets[c];
-        e->prow_h[c] = n_c;
-        e->part_off_h[c + 1] = e->part_off_h[c] + (int64_t)((n_c + TJ - 1) / TJ) * 7 * n_c;
+    e->scratch_need = ens_layout(e, nullptr);
+    if (hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete e;
+        return NB_EDEVICE;
     }
-    e->unroll = 2;
-    ens_derive(e);
-    const size_t C = (size_t)n_clusters, N = (size_t)e->ntot;
-    auto A = [&](void **p, size_t bytes) {
-        return hipMalloc(p, bytes > 0 ? bytes : 16) == hipSuccess;
-    };
-    void *p;
-    bool ok = true;
-    ok = ok && A(&p, (C + 1) * sizeof(int32_t)); if (ok) e->off = (int32_t *)p;
-    ok = ok && A(&p, C * sizeof(int32_t)); if (ok) e->K = (int32_t *)p;
-    ok = ok && A(&p, C * sizeof(int32_t)); if (ok) e->tpi = (int32_t *)p;
-    ok = ok && A(&p, C * sizeof(int32_t)); if (ok) e->prow = (int32_t *)p;
-    ok = ok && A(&p, (C + 1) * sizeof(int64_t)); if (ok) e->part_off = (int64_t *)p;
-    ok = ok && A(&p, C * sizeof(double)); if (ok) e->eps2 = (double *)p;
-    ok = ok && A(&p, C * sizeof(EnsCluster)); if (ok) e->cl = (EnsCluster *)p;
-    ok = ok && A(&p, N * sizeof(int32_t)); if (ok) e->active = (int32_t *)p;
-    ok = ok && A(&p, 2 * sizeof(int32_t)); if (ok) e->flags = (int32_t *)p;
-    ok = ok && A(&p, (size_t)e->part_off_h[C] * sizeof(double)); if (ok) e->partial = (double *)p;
-    ok = ok && A(&p, 2 * N * sizeof(double)); if (ok) e->crit = (double *)p;
-    ok = ok && A(&p, 2 * C * sizeof(double)); if (ok) { e->ek = (double *)p; e->ep = e->ek + C; }
-    if (!ok) { nb_ens_destroy(e); return NB_ENOMEM; }
-    ok = hipMemcpy(e->off, e->off_h.data(), (C + 1) * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(e->prow, e->prow_h.data(), C * sizeof(int32_t), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(e->part_off, e->part_off_h.data(), (C + 1) * sizeof(int64_t), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(e->eps2, e->eps2_h.data(), C * sizeof(double), hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemset(e->flags, 0, 2 * sizeof(int32_t)) == hipSuccess &&
-         hipMemset(e->cl, 0, C * sizeof(EnsCluster)) == hipSuccess &&
-         ens_upload_tables(e) == NB_OK &&
-         hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking) == hipSuccess &&
-         hipDeviceSynchronize() == hipSuccess;
-    if (!ok) { nb_ens_destroy(e); return NB_EDEVICE; }
     *out = e;
+    return NB_OK;
+}
+
+size_t nb_ens_scratch_bytes(int32_t n_clusters, const int32_t *offsets, int32_t precision) {
+    if (!ens_args_ok(n_clusters, offsets, precision)) return 0;
+    nb_ens e;
+    ens_plan(&e, n_clusters, offsets, precision);
+    return ens_layout(&e, nullptr);
+}
+
+nb_status nb_ens_bind_scratch(nb_ens *e, void *scratch, size_t bytes) {
+    if (!e) return NB_EINVAL;
+    if (!scratch) return fail(e, NB_EINVAL, "nb_ens_bind_scratch: workspace pointer required");
+    if ((uintptr_t)scratch % 256 != 0)
+        return fail(e, NB_EINVAL, "nb_ens_bind_scratch: workspace must be 256-byte aligned");
+    if (bytes < e->scratch_need)
+        return fail(e, NB_EINVAL, "nb_ens_bind_scratch: %zu bytes given, %zu needed", bytes,
+                    e->scratch_need);
+    EHIP_OK(e, hipSetDevice(e->device));
+    EHIP_OK(e, hipStreamSynchronize(e->stream));
+    ens_drop_graph(e);
+    ens_layout(e, (char *)scratch);
+    const size_t C = (size_t)e->C;
+    EHIP_OK(e, hipMemcpyAsync(e->off, e->off_h.data(), (C + 1) * sizeof(int32_t), hipMemcpyHostToDevice, e->stream));
+    EHIP_OK(e, hipMemcpyAsync(e->prow, e->prow_h.data(), C * sizeof(int32_t), hipMemcpyHostToDevice, e->stream));
+    EHIP_OK(e, hipMemcpyAsync(e->part_off, e->part_off_h.data(), (C + 1) * sizeof(int64_t), hipMemcpyHostToDevice, e->stream));
+    EHIP_OK(e, hipMemcpyAsync(e->eps2, e->eps2_h.data(), C * sizeof(double), hipMemcpyHostToDevice, e->stream));
+    EHIP_OK(e, hipMemcpyAsync(e->K, e->K_h.data(), C * sizeof(int32_t), hipMemcpyHostToDevice, e->stream));
+    EHIP_OK(e, hipMemcpyAsync(e->tpi, e->tpi_h.data(), C * sizeof(int32_t), hipMemcpyHostToDevice, e->stream));
+    ens_clear<<<std::max<int32_t>(1, (int32_t)((C + WG - 1) / WG)), WG, 0, e->stream>>>(e->cl, e->C, e->flags);
+    ELAUNCH_OK(e);
+    EHIP_OK(e, hipStreamSynchronize(e->stream));
+    e->scratch_ok = true;
+    e->initialised = false;
     return NB_OK;
 }
 
@@ -1125,10 +1283,6 @@ nb_status nb_ens_destroy(nb_ens *e) {
     (void)hipSetDevice(e->device);
     (void)hipDeviceSynchronize();
     ens_drop_graph(e);
-    void *bufs[] = {e->off, e->K, e->tpi, e->prow, e->part_off, e->eps2, e->cl, e->active,
-                    e->flags, e->partial, e->crit, e->ek};
-    for (void *b : bufs)
-        if (b) (void)hipFree(b);
     if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
     delete e;
     return NB_OK;
@@ -1167,16 +1321,32 @@ nb_status nb_ens_set_layout(nb_ens *e, const int32_t *tiles_per_item, int32_t ip
     return ens_upload_tables(e);
 }
 
+nb_status nb_ens_set_local(nb_ens *e, int64_t local_limit, int32_t local_steps,
+                           int64_t local_work) {
+    if (!e) return NB_EINVAL;
+    if (local_limit < 0 || local_steps < 0 || local_work < 0)
+        return fail(e, NB_EINVAL, "local-step limits must be >= 0");
+    EHIP_OK(e, hipSetDevice(e->device));
+    EHIP_OK(e, hipStreamSynchronize(e->stream));
+    e->local_limit = local_limit;
+    e->local_steps = local_steps;
+    e->local_work = local_work;
+    ens_drop_graph(e);
+    return NB_OK;
+}
+
 nb_status nb_ens_init(nb_ens *e, double eta) {
     if (!e) return NB_EINVAL;
+    if (!e->scratch_ok) return fail(e, NB_ESTATE, "no workspace bound (call nb_ens_bind_scratch)");
     if (!e->bound) return fail(e, NB_ESTATE, "state not bound");
     if (!(eta > 0.0) || !std::isfinite(eta)) return fail(e, NB_EINVAL, "eta must be > 0");
     EHIP_OK(e, hipSetDevice(e->device));
-    EHIP_OK(e, hipMemsetAsync(e->flags, 0, 2 * sizeof(int32_t), e->stream));
+    zero_words<<<1, WG, 0, e->stream>>>(nullptr, 0, e->flags, 2);
+    ELAUNCH_OK(e);
     nb_status r;
-    if ((r = ens_enqueue_local(e, eta, 0, INT64_MAX, e->stream)) != NB_OK) return r;
-    if ((r = ens_enqueue_force(e, INT64_MAX, e->stream)) != NB_OK) return r;
-    if ((r = ens_enqueue_local(e, eta, 1, INT64_MAX, e->stream)) != NB_OK) return r;
+    if ((r = ens_enqueue_local(e, eta, 0, INT64_MAX, e->stream, false)) != NB_OK) return r;
+    if ((r = ens_enqueue_force(e, INT64_MAX, e->stream, false)) != NB_OK) return r;
+    if ((r = ens_enqueue_local(e, eta, 1, INT64_MAX, e->stream, false)) != NB_OK) return r;
     e->initialised = true;
     return NB_OK;
 }
@@ -1203,7 +1373,7 @@ nb_status nb_ens_run(nb_ens *e, double eta, int64_t t_end, int32_t steps_per_lau
         e->g_eta = eta; e->g_tend = t_end; e->g_steps = steps_per_launch;
     }
     std::vector<EnsCluster> h(e->C);
-    int64_t done_steps = 0;
+    int64_t done_steps = 0, prev_total = -1;
     for (;;) {
         if (use_graph) {
             EHIP_OK(e, hipGraphLaunch(e->gexec, e->stream));
@@ -1217,14 +1387,23 @@ nb_status nb_ens_run(nb_ens *e, double eta, int64_t t_end, int32_t steps_per_lau
         EHIP_OK(e, hipMemcpyAsync(h.data(), e->cl, e->C * sizeof(EnsCluster), hipMemcpyDeviceToHost, e->stream));
         EHIP_OK(e, hipStreamSynchronize(e->stream));
         bool all = true;
-        for (const auto &x : h) all = all && x.done;
+        int64_t total = 0;
+        for (const auto &x : h) {
+            all = all && x.done;
+            total += x.n_steps;
+        }
         if (all || (max_steps > 0 && done_steps >= max_steps)) break;
+        // every global step advances every unfinished cluster by at least one block step
+        if (total == prev_total)
+            return fail(e, NB_ESTATE, "ensemble made no progress over %d global steps", steps_per_launch);
+        prev_total = total;
     }
     return ens_flags(e);
 }
 
 nb_status nb_ens_control(nb_ens *e, nb_control *out) {
     if (!e || !out) return NB_EINVAL;
+    if (!e->scratch_ok) return fail(e, NB_ESTATE, "no workspace bound (call nb_ens_bind_scratch)");
     EHIP_OK(e, hipSetDevice(e->device));
     std::vector<EnsCluster> h(e->C);
     EHIP_OK(e, hipMemcpyAsync(h.data(), e->cl, e->C * sizeof(EnsCluster), hipMemcpyDeviceToHost, e->stream));

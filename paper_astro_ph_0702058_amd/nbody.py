@@ -50,7 +50,9 @@ EXPORTS = ["nb_create", "nb_destroy", "nb_set_stream", "nb_bind", "nb_init",
            "nb_tune", "nb_profile", "nb_profile_read", "nb_sync", "nb_last_error", "nb_version",
            "nb_ens_create", "nb_ens_destroy", "nb_ens_set_stream", "nb_ens_bind",
            "nb_ens_set_layout", "nb_ens_init", "nb_ens_run", "nb_ens_control", "nb_ens_energy",
-           "nb_ens_last_error", "nb_shared_step", "nb_force_vjp", "nb_step_vjp"]
+           "nb_ens_last_error", "nb_shared_step", "nb_force_vjp", "nb_step_vjp",
+           "nb_scratch_bytes", "nb_bind_scratch", "nb_ens_scratch_bytes", "nb_ens_bind_scratch",
+           "nb_ens_set_local", "nb_fma_rate"]
 
 _lib = None
 
@@ -101,6 +103,10 @@ def load_library(path: str = LIB_PATH):
         "nb_ens_run": [P, D, I64, I32, I64, I32],
         "nb_ens_control": [P, ctypes.POINTER(nb_control)],
         "nb_ens_energy": [P, P, P],
+        "nb_bind_scratch": [P, P, ctypes.c_size_t],
+        "nb_ens_bind_scratch": [P, P, ctypes.c_size_t],
+        "nb_ens_set_local": [P, I64, I32, I64],
+        "nb_fma_rate": [P, ctypes.POINTER(D)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -112,6 +118,10 @@ def load_library(path: str = LIB_PATH):
     lib.nb_ens_last_error.restype = ctypes.c_char_p
     lib.nb_version.argtypes = []
     lib.nb_version.restype = ctypes.c_char_p
+    lib.nb_scratch_bytes.argtypes = [I32, I32]
+    lib.nb_scratch_bytes.restype = ctypes.c_size_t
+    lib.nb_ens_scratch_bytes.argtypes = [I32, P, I32]
+    lib.nb_ens_scratch_bytes.restype = ctypes.c_size_t
     if path == LIB_PATH:
         _lib = lib
     return lib
@@ -249,6 +259,17 @@ class Context:
         torch = _torch()
         s = stream if stream is not None else torch.cuda.current_stream()
         self.nb_set_stream(s)
+        # the library's work buffers live in one torch-owned device tensor
+        nbytes = int(self.lib.nb_scratch_bytes(self.n, PRECISIONS[precision]))
+        if nbytes == 0:
+            raise NBodyError(NB_EINVAL, "nb_scratch_bytes: invalid arguments")
+        self.scratch = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.nb_bind_scratch(self.scratch)
+
+    def nb_bind_scratch(self, scratch):
+        """Bind a uint8 GPU tensor of at least nb_scratch_bytes() bytes as the workspace."""
+        _device_tensor(scratch, "scratch", _torch().uint8)
+        self._check(self.lib.nb_bind_scratch(self.h, _ptr(scratch), scratch.numel()))
 
     # -- plumbing
     def _check(self, status, ctx="self"):
@@ -392,6 +413,12 @@ class Context:
         self._check(self.lib.nb_profile_read(self.h, int(which), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
+    def nb_fma_rate(self):
+        """Measured FP32 FMA rate of the device, TFLOP/s (calibration kernel)."""
+        t = ctypes.c_double()
+        self._check(self.lib.nb_fma_rate(self.h, ctypes.byref(t)))
+        return t.value
+
     def nb_sync(self):
         self._check(self.lib.nb_sync(self.h))
 
@@ -445,6 +472,12 @@ class Ensemble:
         torch = _torch()
         s = stream if stream is not None else torch.cuda.current_stream()
         self._check(self.lib.nb_ens_set_stream(self.h, ctypes.c_void_p(s.cuda_stream)))
+        nbytes = int(self.lib.nb_ens_scratch_bytes(self.C, self.offsets.ctypes.data_as(ctypes.c_void_p),
+                                                   PRECISIONS[precision]))
+        if nbytes == 0:
+            raise NBodyError(NB_EINVAL, "nb_ens_scratch_bytes: invalid arguments")
+        self.scratch = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self._check(self.lib.nb_ens_bind_scratch(self.h, _ptr(self.scratch), nbytes))
 
     def _check(self, status):
         if status != NB_OK:
@@ -480,6 +513,13 @@ class Ensemble:
                                                              (self.C,)))
             arr = self._tpi.ctypes.data_as(ctypes.c_void_p)
         self._check(self.lib.nb_ens_set_layout(self.h, arr, int(ipl), int(unroll)))
+
+    def nb_ens_set_local(self, local_limit, local_steps=64, local_work=1 << 21):
+        """Blocks of at most local_limit interactions (n_act * N_c, and n_act <= 1024) are
+        advanced by the cluster's own workgroup, up to local_steps block steps and local_work
+        interactions per cluster per global step (local_limit = 0: never)."""
+        self._check(self.lib.nb_ens_set_local(self.h, int(local_limit), int(local_steps),
+                                              int(local_work)))
 
     def nb_ens_init(self, eta):
         self._check(self.lib.nb_ens_init(self.h, float(eta)))

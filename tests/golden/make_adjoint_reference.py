@@ -9,9 +9,11 @@ velocity coordinates and 8 masses (seeded samples), steps as in oracle.fd_gradie
 --refine-masses the mass derivatives are evaluated again at half the step and the Richardson
 value (4 D(h/2) - D(h)) / 3 is stored beside them: a mass is varied by a relative step of 1e-3,
 so the central difference's own truncation error can matter for the smallest mass derivatives.
+With --wide-masses they are evaluated at relative steps 1e-2 and 5e-3 with their Richardson
+value (see wide_masses).
 Calls only the oracle and the seeded input generator.
 
-    python tests/golden/make_adjoint_reference.py [--refine-masses]
+    python tests/golden/make_adjoint_reference.py [--refine-masses | --wide-masses]
 """
 import json
 import os
@@ -58,10 +60,39 @@ def refine_masses(path):
     print("refined", len(sel), "mass derivatives", g["seconds_refine"], flush=True)
 
 
+def wide_masses(path):
+    """Mass derivatives again at relative steps 1e-2 and 5e-3 and their Richardson value.  At
+    the steps of 1e-3 and 5e-4 the two quotients of every sampled mass differ by 2-4e-13
+    whatever the derivative's size (7e-8 .. 6e-7), the signature of the run's rounding noise
+    divided by the step rather than of truncation error, which would scale with the derivative;
+    ten times the step leaves a tenth of that noise, and the Richardson value removes the
+    h^2 truncation term the larger step brings."""
+    g = json.load(open(path))
+    t0 = time.time()
+    x0, v0, m = plummer(N, SEED)
+    xp, vp = perturb(x0, v0, 1e-3, 6)
+    target, _ = oracle.shared_run(xp, vp, m, EPS, DT, NSTEPS)
+    cs = [tuple(c) for c in g["coords"]]
+    sel = [k for k, c in enumerate(cs) if c[0] == "m"]
+    d1 = oracle.fd_gradient(x0, v0, m, EPS, DT, NSTEPS, target, [cs[k] for k in sel],
+                            rel_h_mass=1e-2)
+    d2 = oracle.fd_gradient(x0, v0, m, EPS, DT, NSTEPS, target, [cs[k] for k in sel],
+                            rel_h_mass=5e-3)
+    g["fd_mass_wide"] = {"rel_steps": [1e-2, 5e-3], "coords": [list(cs[k]) for k in sel],
+                         "d_h": [float(t) for t in d1], "d_h2": [float(t) for t in d2],
+                         "richardson": [(4.0 * float(b) - float(a)) / 3.0 for a, b in zip(d1, d2)],
+                         "seconds": time.time() - t0}
+    with open(path, "w") as f:
+        json.dump(g, f, indent=1)
+    print("wide mass steps", len(sel), "derivatives", g["fd_mass_wide"]["seconds"], flush=True)
+
+
 def main():
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "adjoint_fd.json")
     if "--refine-masses" in sys.argv[1:]:
         return refine_masses(path)
+    if "--wide-masses" in sys.argv[1:]:
+        return wide_masses(path)
     t0 = time.time()
     x0, v0, m = plummer(N, SEED)
     xp, vp = perturb(x0, v0, 1e-3, 6)

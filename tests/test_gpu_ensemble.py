@@ -20,13 +20,16 @@ def build(sizes, seed0=100):
     return xs, vs, ms
 
 
-def run_ensemble(sizes, eps, eta, t_end, prec, lmin=3, layout=None, graph=True, spl=8):
+def run_ensemble(sizes, eps, eta, t_end, prec, lmin=3, layout=None, graph=True, spl=8,
+                 local=None):
     xs, vs, ms = build(sizes)
     st = nbody.DeviceState(np.concatenate(xs), np.concatenate(vs), np.concatenate(ms))
     ens = nbody.Ensemble(sizes, eps, lmin=lmin, lmax=LMAX, precision=prec)
     ens.nb_ens_bind(st)
     if layout:
         ens.nb_ens_set_layout(**layout)
+    if local:
+        ens.nb_ens_set_local(**local)
     ens.nb_ens_init(eta)
     e0 = ens.nb_ens_energy()
     ens.nb_ens_run(eta, t_end, steps_per_launch=spl, max_steps=200000, use_graph=graph)
@@ -90,6 +93,32 @@ def test_ensemble_layouts_agree():
         assert np.max(np.abs(g["x"] - outs[0][0]["x"])) < 1e-12
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ensemble_local_steps_agree(prec):
+    """Which blocks a cluster's own workgroup advances only changes summation orders: no local
+    blocks (every block through the GPU-wide force), the defaults, every block of up to 1024
+    particles local one step per global step, and every block local with unlimited steps per
+    launch all take the same block steps (FP64: to 1e-12 in position; FP32: step counts within
+    2 %, the decisions near a power of two being taken from forces that differ by rounding)."""
+    sizes = [64, 300, 1000, 2100]
+    eps = [1.0 / n for n in sizes]
+    outs = []
+    for local in (dict(local_limit=0, local_steps=0, local_work=0), None,
+                  dict(local_limit=1 << 40, local_steps=1, local_work=1 << 40),
+                  dict(local_limit=1 << 40, local_steps=1 << 30, local_work=1 << 40)):
+        *_, g, ctl, e0, e1 = run_ensemble(sizes, eps, 0.02, 1 / 8, prec, local=local)
+        assert all(c.flags == 1 and c.t_cur == 1 << (LMAX - 3) for c in ctl)
+        outs.append((g, np.array([c.n_steps for c in ctl]),
+                     np.array([c.n_active_sum for c in ctl])))
+    for g, steps, act in outs[1:]:
+        print(f"{prec}: steps {steps} vs {outs[0][1]}", flush=True)
+        if prec == "fp64":
+            assert np.array_equal(steps, outs[0][1]) and np.array_equal(act, outs[0][2])
+            assert np.max(np.abs(g["x"] - outs[0][0]["x"])) < 1e-12
+        else:
+            assert np.all(np.abs(steps - outs[0][1]) <= 0.02 * outs[0][1])
+
+
 def test_ensemble_graph_equals_eager():
     sizes = [90, 400, 700]
     eps = [1.0 / n for n in sizes]
@@ -145,7 +174,7 @@ def test_full_ensemble_against_committed_oracle_runs(prec):
     ens.nb_ens_bind(st)
     ens.nb_ens_init(p["eta"])
     ek0, ep0 = ens.nb_ens_energy()
-    ens.nb_ens_run(p["eta"], p["t_end"], steps_per_launch=32)
+    ens.nb_ens_run(p["eta"], p["t_end"], steps_per_launch=32, max_steps=60000)
     ctl = ens.nb_ens_control()
     ek1, ep1 = ens.nb_ens_energy()
     ens.close()

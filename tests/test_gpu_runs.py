@@ -11,7 +11,11 @@ dt <= 1/8, integrated to t = 1 by the device-resident loop.
    measured against the size of its terms (|a_i - a_i^ref| / sa_i, with sa_i and the jerk's sk_i
    from oracle.force_scale; the potential terms share one sign, so its relative error is that
    already), and the blocks at t = 1/64 and 1/16, which hold every particle of level <= 6 or
-   <= 4, must also meet them on the plain rms relative error.
+   <= 4, must also meet them on the plain rms relative error.  One exception for the per-row
+   bound in FP64: the oracle predicts from the device's state with its own order of the Taylor
+   terms, so the two predicted positions differ by about an ulp of |x|, and a pair at
+   separation |d| then differs by about u |x| / |d| relative, some 2e-13 for the closest pairs
+   (|d| near eps = 1e-3, |x| near 1); FP64 rows are held to 1e-12 there (the rms to 1e-13).
 2. The first 300 block steps in FP64 follow the oracle step for step (same block times, same
    levels and ticks, positions to 1e-10): the trajectories have not yet parted.
 3. The whole run to t = 1 against the committed FP64 oracle run of the same initial conditions
@@ -41,6 +45,8 @@ pytestmark = pytest.mark.gpu
 
 N, SEED, EPS, NU, LMIN, LMAX, T_END = 65536, 2, 1e-3, 0.01, 3, 26, 1.0
 TOL = {"fp32": (2e-6, 1e-5, 2e-6), "ds": (1e-11, 1e-10, 1e-11), "fp64": (1e-13, 1e-13, 1e-13)}
+# per-row bound inside runs: FP64 limited by the two sides' predictor rounding (see above)
+ROW_TOL = dict(TOL, fp64=(1e-12, 1e-12, 1e-13))
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "plummer_runs.json")
 
 
@@ -94,7 +100,8 @@ def test_block_forces_inside_run(prec):
                   f"{ea:.3e} e_jerk={ek:.3e} e_pot={ep:.3e}; median sum|a_ij|/|a| {cond:.1f}",
                   flush=True)
             ta, tk, tp = TOL[prec]
-            assert ea_w <= ta and ek_w <= tk and ep_w <= tp and ep <= tp, \
+            ra, rk, rp = ROW_TOL[prec]
+            assert ea_w <= ra and ek_w <= rk and ep_w <= rp and ep <= tp, \
                 (kind, where, ea_w, ek_w, ep_w, ep)
             if kind == "time":
                 assert ea <= ta and ek <= tk, (where, ea, ek)

@@ -90,17 +90,29 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU" in r.stderr
 
 
-def test_committed_profiles_match_the_kernel_source():
-    """The committed HBM-traffic summary of the full-force launch was taken on the current
-    kernel source (bench.py reports its figure only then), and every committed summary names
-    the command that produced it."""
+def test_committed_traffic_is_reported_only_for_its_kernel_source():
+    """The committed HBM-traffic summary of the full-force launch names its kernel source hash,
+    launch variant and the two counter commands; bench.py reports its figure only while the
+    kernel source, the workload and the launch variant are the ones the counters were taken
+    with, and null otherwise.  Every committed summary names the command that produced it."""
     import json
+    import types
+    sys.path.insert(0, ROOT)
+    import bench
     from paper_astro_ph_0702058_amd.profiling import kernel_source_hash
     prof = os.path.join(ROOT, "profiles")
     t = json.load(open(os.path.join(prof, "force_full_fp32_plummer_n1048576_traffic.json")))
-    assert t["kernel_source_sha256_16"] == kernel_source_hash()
-    assert t["variant"] == {"ipl": 1, "unroll": 2, "target": 65536, "kmax": 64}
     assert set(t["commands"]) == {"FETCH_SIZE", "WRITE_SIZE"}
+    assert t["hbm_bytes_per_launch"] > 0
+    args = types.SimpleNamespace(eps=t["eps"])
+    got = bench.committed_traffic(t["kernel"], t["n"], args, t["variant"])
+    if t["kernel_source_sha256_16"] == kernel_source_hash():
+        assert got == t["hbm_bytes_per_launch"]
+    else:
+        assert got is None
+    assert bench.committed_traffic(t["kernel"], t["n"] // 2, args, t["variant"]) is None
+    other = dict(t["variant"], unroll=t["variant"]["unroll"] + 1)
+    assert bench.committed_traffic(t["kernel"], t["n"], args, other) is None
     for name in os.listdir(prof):
         if name.endswith(".txt"):
             assert "# command: " in open(os.path.join(prof, name)).read(), name
@@ -122,3 +134,33 @@ def test_binding_rejects_host_tensors_and_wrong_index_types():
         nbody.check_force_args(n, acc, acc, acc[0], None, None, n + 1)
     with pytest.raises(TypeError, match="torch tensor"):
         nbody.check_force_args(n, np.zeros((3, n)), acc, acc[0], None, None, n)
+
+
+def test_scratch_bytes(lib):
+    """The workspace size of a context (no device needed): 0 for invalid arguments; at least
+    the fixed per-particle buffers (j-stream 64 B, block outputs 56 B, block list 4 B, criterion
+    16 B, energy 64 B, adjoint 96 B: 300 B per particle) and at most those plus 64 j-ranges of
+    partial sums (56 B per particle each) and small records; growing with n.  The ensemble's
+    likewise: at least its block list and criterion plus one partial plane set per cluster."""
+    import ctypes
+    lib.nb_scratch_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.nb_scratch_bytes.restype = ctypes.c_size_t
+    assert lib.nb_scratch_bytes(0, 0) == 0 and lib.nb_scratch_bytes(10, 9) == 0
+    prev = 0
+    for n in (1, 1000, 65536, 1 << 20):
+        for prec in range(5):
+            b = lib.nb_scratch_bytes(n, prec)
+            assert 300 * n <= b <= 300 * n + 64 * 56 * n + (1 << 20), (n, prec, b)
+        b = lib.nb_scratch_bytes(n, 0)
+        assert b > prev
+        prev = b
+    lib.nb_ens_scratch_bytes.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32]
+    lib.nb_ens_scratch_bytes.restype = ctypes.c_size_t
+    off = np.array([0, 100, 300, 4396], np.int32)
+    b = lib.nb_ens_scratch_bytes(3, off.ctypes.data_as(ctypes.c_void_p), 0)
+    tiles = [(100 + 255) // 256, (200 + 255) // 256, (4096 + 255) // 256]
+    planes = 8 * 7 * (tiles[0] * 100 + tiles[1] * 200 + tiles[2] * 4096)
+    assert 20 * 4396 + planes <= b <= 20 * 4396 + planes + (1 << 16), b
+    bad = np.array([0, 100, 100, 200], np.int32)
+    assert lib.nb_ens_scratch_bytes(3, bad.ctypes.data_as(ctypes.c_void_p), 0) == 0
+    assert lib.nb_ens_scratch_bytes(3, off.ctypes.data_as(ctypes.c_void_p), 3) == 0
