@@ -646,9 +646,6 @@ def main():
         chosen = autotune(ctx, cache_path=None, reps=1)
         log(f"[bench] tuned in {time.perf_counter() - t_tune:.1f} s: {chosen}")
     variant_full, variant_block = ctx.nb_get_variant(0), ctx.nb_get_variant(1)
-    # the device's FP32 FMA rate from the library's calibration kernel (before the timed region)
-    fma_tflops = ctx.nb_fma_rate()
-    log(f"[bench] measured FP32 FMA rate {fma_tflops:.1f} TFLOP/s")
 
     def step():
         st.x.copy_(x0)
@@ -660,6 +657,9 @@ def main():
     for _ in range(args.warmup):
         step()
     ctx.nb_sync()
+    # the device's FP32 FMA rate from the library's calibration kernel (warm clocks, untimed)
+    fma_tflops = ctx.nb_fma_rate()
+    log(f"[bench] measured FP32 FMA rate {fma_tflops:.1f} TFLOP/s")
 
     interactions = 0
     ctx.nb_profile(True)

@@ -269,8 +269,9 @@ nb_status nb_tune(nb_ctx *ctx, int32_t which, int32_t n_i, int32_t reps, nb_vari
 
 /* Calibration for measurement (not part of the method): the FP32 fused multiply-add rate of
  * the device in TFLOP/s (HOST output), from a kernel of 16 independent two-operand FMA chains
- * per work-item over 64 workgroups of 256 per compute unit, best of three timed launches on
- * the context's stream.  Requires a bound workspace; synchronising. */
+ * per work-item over 64 workgroups of 256 per compute unit, the multiplier a scalar or a vector
+ * operand, best of ten timed launches (after two untimed) on the context's stream.  Requires a
+ * bound workspace; synchronising. */
 nb_status nb_fma_rate(nb_ctx *ctx, double *tflops);
 
 /* Wait for the context's stream; returns a latched device error, if any. */

@@ -1471,16 +1471,20 @@ __global__ void __launch_bounds__(WG) fused_correct_level(StateRW s, const int32
 // ------------------------------------------------------------------------------------------
 constexpr int FMA_CHAINS = 16;
 
-__global__ void __launch_bounds__(WG) fma_probe(int32_t iters, float m, float *sink) {
+// VOPND: the multiplier is a vector register (m + dm * lane, dm = 0 at launch) instead of a
+// scalar operand.
+template <bool VOPND>
+__global__ void __launch_bounds__(WG) fma_probe(int32_t iters, float m, float dm, float *sink) {
     float x[FMA_CHAINS], acc[FMA_CHAINS];
 #pragma unroll
     for (int c = 0; c < FMA_CHAINS; ++c) {
         x[c] = (float)(threadIdx.x + c) * 1e-3f;
         acc[c] = (float)c;
     }
+    const float mv = VOPND ? m + dm * (float)threadIdx.x : m;
     for (int32_t it = 0; it < iters; ++it) {
 #pragma unroll
-        for (int c = 0; c < FMA_CHAINS; ++c) acc[c] = __builtin_fmaf(x[c], m, acc[c]);
+        for (int c = 0; c < FMA_CHAINS; ++c) acc[c] = __builtin_fmaf(x[c], mv, acc[c]);
     }
     float t = 0.0f;
 #pragma unroll

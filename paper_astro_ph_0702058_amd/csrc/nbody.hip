@@ -1020,21 +1020,22 @@ nb_status nb_fma_rate(nb_ctx *c, double *tflops) {
     if ((r = need(c, false)) != NB_OK) return r;
     if (!tflops) return fail(c, NB_EINVAL, "nb_fma_rate: host output required");
     hipStream_t s = c->stream;
-    const int32_t iters = 4096, grid = c->num_cu * 64;
+    const int32_t iters = 8192, grid = c->num_cu * 64;
     hipEvent_t e0, e1;
     HIP_OK(c, hipEventCreate(&e0));
     HIP_OK(c, hipEventCreate(&e1));
     double best = 0.0;
-    for (int rep = 0; rep < 4; ++rep) {  // the first launch warms up; the best of the rest
+    for (int rep = 0; rep < 12; ++rep) {  // both operand forms; the first two launches warm up
         HIP_OK(c, hipEventRecord(e0, s));
-        fma_probe<<<grid, WG, 0, s>>>(iters, 1e-7f, (float *)c->eout);
+        if (rep & 1) fma_probe<true><<<grid, WG, 0, s>>>(iters, 1e-7f, 0.0f, (float *)c->eout);
+        else fma_probe<false><<<grid, WG, 0, s>>>(iters, 1e-7f, 0.0f, (float *)c->eout);
         LAUNCH_OK(c);
         HIP_OK(c, hipEventRecord(e1, s));
         HIP_OK(c, hipEventSynchronize(e1));
         float ms = 0.f;
         HIP_OK(c, hipEventElapsedTime(&ms, e0, e1));
         const double flop = 2.0 * FMA_CHAINS * (double)iters * grid * WG;
-        if (rep > 0 && ms > 0.f) best = std::max(best, flop / (ms * 1e-3) / 1e12);
+        if (rep > 1 && ms > 0.f) best = std::max(best, flop / (ms * 1e-3) / 1e12);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
