@@ -163,6 +163,19 @@ nb_status nb_predict(nb_ctx *ctx, const int64_t *t);
 nb_status nb_force(nb_ctx *ctx, const int32_t *i_idx, const int32_t *n_i, int32_t n_i_max,
                    double *acc, double *jerk, double *pot);
 
+/* For callers that cannot allocate device memory or take it from the caller's workspace (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid allocation): nb_force with
+ * the same arguments and bitwise the same results, whose j-split partial sums go to a static
+ * device array of 64 MiB per GPU (held from the first nb_create on that GPU until the process
+ * ends) instead of the context's workspace.  Allocates nothing.  NB_EINVAL, before anything is
+ * enqueued, if the call's j-split needs more than the array holds (7 doubles per partial row;
+ * with a device count the largest count up to n_i_max is assumed): all block-step lists fit at
+ * n = 65536, a full-force call on 2^20 particles (16 j-ranges) does not.  The array's contents
+ * need no clearing (every partial row a call reads, the same call has written), but every call
+ * on one GPU shares it: calls that overlap on one GPU (other streams, other contexts) race. */
+nb_status nb_force_noalloc(nb_ctx *ctx, const int32_t *i_idx, const int32_t *n_i,
+                           int32_t n_i_max, double *acc, double *jerk, double *pot);
+
 /* Sec. 2 corrector of the selected block over its steps, in double precision: from the old
  * a0, k0 and the new acc/jerk (as written by nb_force on nb_active()'s list, leading dimension
  * n), a2 = -6 (a0 - a1)/dt^2 - (4 k0 + 2 k1)/dt, a3 = 12 (a0 - a1)/dt^3 + 6 (k0 + k1)/dt^2,

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -20,6 +21,37 @@
 #include "kernels.hpp"
 
 using namespace nbody;
+
+// ------------------------------------------------------------------------------------------
+// The j-split partial sums of nb_force_noalloc: one static device array per GPU (it lives as
+// long as the process), so that call never needs device memory from the caller or the
+// allocator.  Host code reaches it only through the address hipGetSymbolAddress returns for
+// the device (the array's name is a host-side stand-in there).
+// ------------------------------------------------------------------------------------------
+namespace {
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+std::mutex noalloc_mu;
+void *noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+bool noalloc_done[NOALLOC_MAX_DEVICES] = {};
+
+// Once per device, with that device current: the device address of its scratch array.
+void noalloc_setup(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return;
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (noalloc_done[device]) return;
+    noalloc_done[device] = true;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) noalloc_ptr[device] = p;
+}
+
+void *noalloc_scratch(int device) {
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    return noalloc_ptr[device];
+}
+}  // namespace
 
 namespace {
 
@@ -575,6 +607,7 @@ nb_status nb_create(nb_ctx **out, int32_t n, double eps, int32_t lmin, int32_t l
     c->n = n; c->eps = eps; c->lmin = lmin; c->lmax = lmax; c->prec = precision;
     if (hipGetDevice(&c->device) != hipSuccess) { delete c; return NB_EDEVICE; }
     c->num_cu = device_cus(c->device);
+    noalloc_setup(c->device);
     ctx_plan(c);
     c->scratch_need = ctx_layout(c, nullptr);
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -706,6 +739,40 @@ nb_status nb_force(nb_ctx *c, const int32_t *i_idx, const int32_t *n_i, int32_t 
     const int cls = (n_i == nullptr && n_i_max > c->n / 8) ? 0 : 1;
     if ((r = enqueue_force(c, cls == 0 ? c->var_full : c->var_block, cls, i_idx, n_i, n_i_max,
                            acc, jerk, pot, n_i_max, c->stream)) != NB_OK)
+        return r;
+    c->forced = true;
+    return NB_OK;
+}
+
+nb_status nb_force_noalloc(nb_ctx *c, const int32_t *i_idx, const int32_t *n_i,
+                           int32_t n_i_max, double *acc, double *jerk, double *pot) {
+    nb_status r;
+    if ((r = need(c)) != NB_OK) return r;
+    if (!c->predicted) return fail(c, NB_ESTATE, "nb_force_noalloc before nb_predict");
+    if (!acc || !jerk || !pot) return fail(c, NB_EINVAL, "nb_force_noalloc: output pointers required");
+    if (n_i_max < 0 || n_i_max > c->n)
+        return fail(c, NB_EINVAL, "nb_force_noalloc: n_i_max %d outside [0, %d]", n_i_max, c->n);
+    if (!i_idx && !n_i && n_i_max == 0) return NB_OK;
+    const int cls = (n_i == nullptr && n_i_max > c->n / 8) ? 0 : 1;
+    const Variant &v = cls == 0 ? c->var_full : c->var_block;
+    const int32_t smax = smax_of(c->prec);
+    // partial-sum rows of this call's plan (for a device count: of the largest count it allows)
+    int64_t rows = 0;
+    if (n_i) {
+        rows = partial_rows_upto(n_i_max, c->n, v, smax);
+    } else {
+        const ForcePlan pl = make_plan(n_i_max, c->n, WG * v.ipl, v.target, v.kmax, smax);
+        rows = pl.K > 1 ? (int64_t)pl.K * pl.P : 0;
+    }
+    const size_t bytes = (size_t)rows * 7 * sizeof(double);
+    if (bytes > NOALLOC_SCRATCH_BYTES)
+        return fail(c, NB_EINVAL,
+                    "nb_force_noalloc: this call's j-split needs %zu bytes of partial sums; the "
+                    "static array holds %zu (use nb_force)", bytes, NOALLOC_SCRATCH_BYTES);
+    double *part = (double *)noalloc_scratch(c->device);
+    if (!part) return fail(c, NB_EDEVICE, "nb_force_noalloc: no device address for the static array");
+    if ((r = enqueue_force(c, v, cls, i_idx, n_i, n_i_max, acc, jerk, pot, n_i_max, c->stream,
+                           part)) != NB_OK)
         return r;
     c->forced = true;
     return NB_OK;

@@ -52,7 +52,7 @@ EXPORTS = ["nb_create", "nb_destroy", "nb_set_stream", "nb_bind", "nb_init",
            "nb_ens_set_layout", "nb_ens_init", "nb_ens_run", "nb_ens_control", "nb_ens_energy",
            "nb_ens_last_error", "nb_shared_step", "nb_force_vjp", "nb_step_vjp",
            "nb_scratch_bytes", "nb_bind_scratch", "nb_ens_scratch_bytes", "nb_ens_bind_scratch",
-           "nb_ens_set_local", "nb_fma_rate"]
+           "nb_ens_set_local", "nb_fma_rate", "nb_force_noalloc"]
 
 _lib = None
 
@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH):
         "nb_ens_bind_scratch": [P, P, ctypes.c_size_t],
         "nb_ens_set_local": [P, I64, I32, I64],
         "nb_fma_rate": [P, ctypes.POINTER(D)],
+        "nb_force_noalloc": [P, P, P, I32, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -336,6 +337,16 @@ class Context:
         ii = ctypes.c_void_p(i_idx) if isinstance(i_idx, int) else _ptr(i_idx)
         nn = ctypes.c_void_p(n_i) if isinstance(n_i, int) else _ptr(n_i)
         self._check(self.lib.nb_force(self.h, ii, nn, n_i_max, _ptr(acc), _ptr(jerk), _ptr(pot)))
+
+    def nb_force_noalloc(self, acc, jerk, pot, i_idx=None, n_i=None, n_i_max=None):
+        """nb_force whose j-split partial sums live in the library's static device array
+        (allocates nothing); same arguments and results."""
+        n_i_max = acc.shape[1] if n_i_max is None else int(n_i_max)
+        check_force_args(self.n, acc, jerk, pot, i_idx, n_i, n_i_max)
+        ii = ctypes.c_void_p(i_idx) if isinstance(i_idx, int) else _ptr(i_idx)
+        nn = ctypes.c_void_p(n_i) if isinstance(n_i, int) else _ptr(n_i)
+        self._check(self.lib.nb_force_noalloc(self.h, ii, nn, n_i_max, _ptr(acc), _ptr(jerk),
+                                              _ptr(pot)))
 
     def nb_correct(self, acc, jerk, pot):
         """acc, jerk: (3, n) float64 GPU tensors (the block's rows first), pot: (n,)."""
