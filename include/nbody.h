@@ -202,6 +202,15 @@ nb_status nb_step(nb_ctx *ctx, double eta, int32_t nsteps, int32_t use_graph);
 nb_status nb_run(nb_ctx *ctx, double eta, int64_t t_end, int64_t max_steps, int32_t chunk,
                  int32_t use_graph);
 
+/* nb_run's path for small contexts: with n <= max_n (default 2048; 0: never), softening
+ * eps > 0 and the FP32, double-single or FP64 arithmetic, nb_run advances the particles with
+ * one resident workgroup that repeats the whole block step (the block of Sec. 2, the force of
+ * Eq. Force on it with every particle predicted as it is staged in LDS, the corrector and the
+ * new levels of Eq. timestep) up to `chunk` times per launch, instead of a chain of launches
+ * per step.  The same steps up to the summation order; nb_run does not write the j-particle
+ * stream then (call nb_predict before a later nb_force). */
+nb_status nb_set_resident(nb_ctx *ctx, int32_t max_n);
+
 /* Sec. 4.2 energy diagnostic, synchronising: kinetic sum m v^2 / 2 and softened potential
  * energy -1/2 sum_i sum_{j != i} m_i m_j s^(-1/2), in double precision, of the state predicted
  * to the last completed block time (exact at times where all particles are synchronised).

@@ -118,17 +118,15 @@ template <> __device__ __forceinline__ float eps_as<ModeF32>(double e2) { return
 template <> __device__ __forceinline__ ds eps_as<ModeDS>(double e2) { return ds_from_double(e2); }
 template <> __device__ __forceinline__ double eps_as<ModeF64>(double e2) { return e2; }
 
-// Next block of cluster [lo, hi) (Sec. 2: smallest t_i + dt_i, all particles attaining it, in
-// ascending order) into e.active[lo ...] and the cluster record; every work-item of the
-// workgroup gets the block size and time.  Returns false when the block lies beyond t_end (the
-// cluster is done).  Clusters of up to TN_CACHE particles keep t_i + dt_i in LDS for the
-// compaction (the loads of four particles per work-item are issued together).
-// Work-groups of BS work-items; tn_lds (TN_CACHE entries) may be NULL (no cache).
+// Next block among particles [lo, hi) by one workgroup of BS (Sec. 2: smallest t_i + dt_i, all
+// particles attaining it, in ascending order) into out[0 ...]; every work-item gets the block
+// size and time.  Returns false (n_act = 0) when the block lies beyond t_end.  Up to TN_CACHE
+// particles keep t_i + dt_i in LDS for the compaction (tn_lds, TN_CACHE entries, may be NULL;
+// the loads of several particles per work-item are issued together).
 template <int BS>
-__device__ bool ens_select(const EnsView &e, const StateRW &s, int32_t lo, int32_t hi,
-                           EnsCluster *cl, int64_t *tn_lds, int64_t *red, int32_t *wsum,
-                           int32_t &n_act, int64_t &t_next) {
-    const int32_t lmax = e.lmax;
+__device__ bool block_select(const int64_t *tick, const int32_t *level, int32_t lo, int32_t hi,
+                             int32_t lmax, int64_t t_end, int32_t *out, int64_t *tn_lds,
+                             int64_t *red, int32_t *wsum, int32_t &n_act, int64_t &t_next) {
     const bool cached = tn_lds != nullptr && hi - lo <= TN_CACHE;
     int64_t m = INT64_MAX;
     if (cached) {
@@ -136,7 +134,7 @@ __device__ bool ens_select(const EnsView &e, const StateRW &s, int32_t lo, int32
 #pragma unroll
         for (int r = 0; r < TN_CACHE / BS; ++r) {
             const int32_t i = lo + threadIdx.x + r * BS;
-            tn[r] = i < hi ? s.tick[i] + ((int64_t)1 << (lmax - s.level[i])) : INT64_MAX;
+            tn[r] = i < hi ? tick[i] + ((int64_t)1 << (lmax - level[i])) : INT64_MAX;
         }
 #pragma unroll
         for (int r = 0; r < TN_CACHE / BS; ++r) {
@@ -145,31 +143,44 @@ __device__ bool ens_select(const EnsView &e, const StateRW &s, int32_t lo, int32
         }
     } else {
         for (int32_t i = lo + threadIdx.x; i < hi; i += BS) {
-            const int64_t tn = s.tick[i] + ((int64_t)1 << (lmax - s.level[i]));
+            const int64_t tn = tick[i] + ((int64_t)1 << (lmax - level[i]));
             m = tn < m ? tn : m;
         }
     }
     const int64_t tn_min = block_min_i64<BS>(m, red);  // its barriers also publish tn_lds
-    if (tn_min > e.t_end) {
-        if (threadIdx.x == 0) { cl->done = 1; cl->n_act = 0; }
+    if (tn_min > t_end) {
         n_act = 0;
         return false;
     }
-    const int32_t na = cached
-        ? wg_compact<BS>(lo, hi, [&](int32_t i) { return tn_lds[i - lo] == tn_min; },
-                         e.active + lo, wsum)
+    n_act = cached
+        ? wg_compact<BS>(lo, hi, [&](int32_t i) { return tn_lds[i - lo] == tn_min; }, out, wsum)
         : wg_compact<BS>(
               lo, hi,
-              [&](int32_t i) { return s.tick[i] + ((int64_t)1 << (lmax - s.level[i])) == tn_min; },
-              e.active + lo, wsum);
-    if (threadIdx.x == 0) {
-        cl->t_next = tn_min;
-        cl->n_act = na;
-    }
-    n_act = na;
+              [&](int32_t i) { return tick[i] + ((int64_t)1 << (lmax - level[i])) == tn_min; },
+              out, wsum);
     t_next = tn_min;
     __syncthreads();  // the block list is complete before any work-item reads it
     return true;
+}
+
+// Next block of cluster [lo, hi) into e.active[lo ...] and the cluster record (block_select);
+// false when the cluster is done.
+template <int BS>
+__device__ bool ens_select(const EnsView &e, const StateRW &s, int32_t lo, int32_t hi,
+                           EnsCluster *cl, int64_t *tn_lds, int64_t *red, int32_t *wsum,
+                           int32_t &n_act, int64_t &t_next) {
+    const bool more = block_select<BS>(s.tick, s.level, lo, hi, e.lmax, e.t_end, e.active + lo,
+                                       tn_lds, red, wsum, n_act, t_next);
+    if (threadIdx.x == 0) {
+        if (more) {
+            cl->t_next = t_next;
+            cl->n_act = n_act;
+        } else {
+            cl->done = 1;
+            cl->n_act = 0;
+        }
+    }
+    return more;
 }
 
 // The 7 sums of block row q of cluster c over its K partial planes, in plane order (four
@@ -212,62 +223,87 @@ __device__ __forceinline__ void ens_correct_one(const EnsView &e, const StateRW 
     s.level[i] = next_level(dt, s.level[i], t_next, e.lmin, e.lmax);
 }
 
-// One block step of a cluster by its own workgroup (the block is ens_local_block): the force of
-// the block particles against all cluster particles, predicted to t_next as they are staged in
-// LDS, WGL at a time; S = WGL / 2^ceil(log2 n_act) (at most 64) adjacent lanes share a block
-// particle and combine their sums by wave shuffles; then the corrector and the new levels.
+// The force of a block on particles [lo, hi) by one workgroup of BS (Sec. 2 Eq. Force with
+// App. A softening, eps > 0): the block list `list` (global indices, n_act of them) against all
+// particles of [lo, hi), predicted to t_next as they are staged in LDS, BS at a time.  S = BS /
+// 2^ceil(log2 n_act) (at most 64, at least 1) adjacent lanes share a block particle and combine
+// their sums by wave shuffles; longer lists take chunks of BS particles.  The 7 sums of row q
+// (acc, jerk, and the potential sum taken positive) go to stage[k * ld + q].
+template <class M, int BS>
+__device__ void block_force_staged(const StateRW &s, int32_t lo, int32_t hi, const int32_t *list,
+                                   int32_t n_act, int64_t t_next, typename EpsOf<M>::T eps2,
+                                   typename M::Smem (&sm)[BS / TJ], double *stage, int64_t ld) {
+    const int32_t n_c = hi - lo;
+    int32_t p2 = 1;
+    while (p2 < n_act && p2 < BS) p2 <<= 1;
+    const int32_t Sl = BS / p2 > 64 ? 64 : BS / p2;
+    const int32_t ib = BS / Sl;  // block particles per chunk
+    const int32_t slice = (int32_t)threadIdx.x % Sl;
+    for (int32_t q0 = 0; q0 < n_act; q0 += ib) {
+        const int32_t q = q0 + (int32_t)threadIdx.x / Sl;
+        const bool has = q < n_act;
+        const int32_t g = has ? list[q] : lo;
+        const int32_t own = has ? g - lo : -1;  // own slot among [lo, hi) (none on padding)
+        double xp[3], vp[3];
+        predicted(s, g, t_next, xp, vp);
+        const typename M::I ii = M::make_i(xp, vp, s.m[g]);
+        typename M::Sum S = M::sum_zero();
+        for (int32_t t0 = 0; t0 < n_c; t0 += BS) {
+            __syncthreads();
+            const int32_t jl = t0 + (int32_t)threadIdx.x;
+            typename M::Smem &st = sm[threadIdx.x / TJ];
+            if (jl < n_c) {
+                double xj[3], vj[3];
+                predicted(s, lo + jl, t_next, xj, vj);
+                M::put(st, threadIdx.x % TJ, xj, vj, s.m[lo + jl]);
+            } else {  // padding: zero mass contributes nothing
+                const double z[3] = {0.0, 0.0, 0.0};
+                M::put(st, threadIdx.x % TJ, z, z, 0.0);
+            }
+            __syncthreads();
+            const int32_t jn = n_c - t0 < BS ? n_c - t0 : BS;
+            for (int b = 0; b * TJ < jn; ++b) {  // 256-slot sub-tiles, folded one at a time
+                const int32_t cnt = jn - b * TJ < TJ ? jn - b * TJ : TJ;
+                const int32_t rel = own - (t0 + b * TJ);
+                typename M::Tile T = M::tile_zero();
+                if (__ballot((uint32_t)rel < (uint32_t)cnt) != 0) {
+#pragma unroll 2
+                    for (int jj = slice; jj < cnt; jj += Sl)
+                        M::template interact<true, true>(ii, sm[b], jj, eps2, T, jj == rel);
+                } else {
+#pragma unroll 2
+                    for (int jj = slice; jj < cnt; jj += Sl)
+                        M::template interact<true>(ii, sm[b], jj, eps2, T);
+                }
+                M::fold(S, T);
+            }
+        }
+        for (int off = Sl >> 1; off > 0; off >>= 1) M::shfl_add(S, off);
+        if (has && slice == 0) {
+            const Out7 o = M::out(S);
+#pragma unroll
+            for (int k = 0; k < 7; ++k) stage[k * ld + q] = o.v[k];
+        }
+    }
+    __syncthreads();  // the sums are complete, and every prediction read of the state is done
+}
+
+// One block step of a cluster by its own workgroup (the block is ens_local_block): the force
+// (block_force_staged, sums staged in the cluster's first partial plane set), then the
+// corrector and the new levels.
 template <class M>
 __device__ void ens_block_step_local(const EnsView &e, const StateRW &s, int32_t c, int32_t lo,
                                      int32_t hi, int32_t n_act, int64_t t_next, double eta,
                                      typename M::Smem (&sm)[WGL / TJ], bool &bad, bool &clamp) {
-    const int32_t n_c = hi - lo;
-    int32_t p2 = 1;
-    while (p2 < n_act) p2 <<= 1;
-    const int32_t Sl = WGL / p2 > 64 ? 64 : WGL / p2;
-    const int32_t slice = (int32_t)threadIdx.x % Sl;
-    const int32_t q = (int32_t)threadIdx.x / Sl;
-    const bool has = q < n_act;
-    const int32_t g = has ? e.active[lo + q] : lo;
-    const int32_t own = has ? g - lo : -1;  // own slot in the cluster (none on padding)
-    const auto eps2 = eps_as<M>(e.eps2[c]);
-    double xp[3], vp[3];
-    predicted(s, g, t_next, xp, vp);
-    const typename M::I ii = M::make_i(xp, vp, s.m[g]);
-    typename M::Sum S = M::sum_zero();
-    for (int32_t t0 = 0; t0 < n_c; t0 += WGL) {
-        __syncthreads();
-        const int32_t jl = t0 + (int32_t)threadIdx.x;
-        typename M::Smem &st = sm[threadIdx.x / TJ];
-        if (jl < n_c) {
-            double xj[3], vj[3];
-            predicted(s, lo + jl, t_next, xj, vj);
-            M::put(st, threadIdx.x % TJ, xj, vj, s.m[lo + jl]);
-        } else {  // padding: zero mass contributes nothing
-            const double z[3] = {0.0, 0.0, 0.0};
-            M::put(st, threadIdx.x % TJ, z, z, 0.0);
-        }
-        __syncthreads();
-        const int32_t jn = n_c - t0 < WGL ? n_c - t0 : WGL;
-        for (int b = 0; b * TJ < jn; ++b) {  // 256-slot sub-tiles, folded one at a time
-            const int32_t cnt = jn - b * TJ < TJ ? jn - b * TJ : TJ;
-            const int32_t rel = own - (t0 + b * TJ);
-            typename M::Tile T = M::tile_zero();
-            if (__ballot((uint32_t)rel < (uint32_t)cnt) != 0) {
-#pragma unroll 2
-                for (int jj = slice; jj < cnt; jj += Sl)
-                    M::template interact<true, true>(ii, sm[b], jj, eps2, T, jj == rel);
-            } else {
-#pragma unroll 2
-                for (int jj = slice; jj < cnt; jj += Sl) M::template interact<true>(ii, sm[b], jj, eps2, T);
-            }
-            M::fold(S, T);
-        }
-    }
-    for (int off = Sl >> 1; off > 0; off >>= 1) M::shfl_add(S, off);
-    __syncthreads();  // every prediction read of the state precedes the corrector's writes
-    if (has && slice == 0) {
-        const Out7 o = M::out(S);
-        ens_correct_one(e, s, g, t_next, o.v, eta, bad, clamp);
+    double *stage = e.partial + e.part_off[c];
+    const int64_t ld = e.prow[c];
+    block_force_staged<M, WGL>(s, lo, hi, e.active + lo, n_act, t_next, eps_as<M>(e.eps2[c]), sm,
+                               stage, ld);
+    for (int32_t q = threadIdx.x; q < n_act; q += WGL) {
+        double o[7];
+#pragma unroll
+        for (int k = 0; k < 7; ++k) o[k] = stage[k * ld + q];
+        ens_correct_one(e, s, e.active[lo + q], t_next, o, eta, bad, clamp);
     }
     __syncthreads();  // the corrected times and levels precede the next selection
 }
@@ -358,6 +394,64 @@ __global__ void __launch_bounds__(WGL) ens_local(EnsView e, StateRW s, double et
     }
     if (bad) e.flags[0] = 1;
     if (clamp) e.flags[1] = 1;
+}
+
+// Block steps of one particle set by one resident workgroup, for sets so small that a block
+// step is far shorter than a chain of kernel launches: select the next block up to the
+// scheduler's t_end (block_select), its force (block_force_staged; the 7 sums of each block
+// row staged in `stage`, ld = n), the corrector and the new levels (Eq. timestep, power-of-two
+// rules), repeated up to `steps` times or until no block lies at or before t_end.  The
+// scheduler record is the context's (block time and size, step counters, latched flags).
+template <class M>
+__global__ void __launch_bounds__(WGL) run_resident(StateRW s, int32_t *active, double *stage,
+                                                    DevControl *ctl, double eps2, double eta,
+                                                    int32_t lmin, int32_t lmax, int32_t steps) {
+    __shared__ int64_t red[WGL / 64];
+    __shared__ int32_t wsum[WGL / 64];
+    __shared__ int64_t tn_lds[TN_CACHE];
+    __shared__ typename M::Smem sm[WGL / TJ];
+    const int32_t n = s.n;
+    const int64_t t_end = ctl->t_end;
+    if (ctl->done) return;  // every work-item reads the same record
+    if (threadIdx.x == 0) ctl->n_pending = 0;  // levels are current (assigned before this launch)
+    bool bad = false, clamp = false;
+    for (int32_t it = 0; it < steps; ++it) {
+        int32_t n_act = 0;
+        int64_t t_next = 0;
+        if (!block_select<WGL>(s.tick, s.level, 0, n, lmax, t_end, active, tn_lds, red, wsum,
+                               n_act, t_next)) {
+            if (threadIdx.x == 0) {
+                ctl->done = 1;
+                ctl->n_act = 0;
+            }
+            break;
+        }
+        block_force_staged<M, WGL>(s, 0, n, active, n_act, t_next, eps_as<M>(eps2), sm, stage, n);
+        for (int32_t q = threadIdx.x; q < n_act; q += WGL) {
+            const int32_t i = active[q];
+            const double a1[3] = {stage[q], stage[(int64_t)n + q], stage[2 * (int64_t)n + q]};
+            const double k1[3] = {stage[3 * (int64_t)n + q], stage[4 * (int64_t)n + q],
+                                  stage[5 * (int64_t)n + q]};
+            const double dt_old = (double)(t_next - s.tick[i]) * s.tick_len;
+            double num = 0.0, den = 0.0;
+            bad = bad || !correct_particle(s, i, dt_old, a1, k1, -stage[6 * (int64_t)n + q], t_next,
+                                           nullptr, &num, &den);
+            const double dt = den > 0.0 ? __builtin_sqrt(eta * num / den) : __builtin_inf();
+            bad = bad || __builtin_isnan(dt);
+            clamp = clamp || dt < s.tick_len;
+            s.level[i] = next_level(dt, s.level[i], t_next, lmin, lmax);
+        }
+        __syncthreads();  // corrected times and levels precede the next selection
+        if (threadIdx.x == 0) {
+            ctl->t_cur = t_next;
+            ctl->t_next = t_next;
+            ctl->n_act = n_act;
+            ctl->n_steps += 1;
+            ctl->n_active_sum += n_act;
+        }
+    }
+    if (bad) ctl->flag_nonfinite = 1;
+    if (clamp) ctl->flag_dtmin = 1;
 }
 
 // Exclusive prefix over clusters of their force work items (ens_item: i-blocks of WG / S block

@@ -102,6 +102,7 @@ struct nb_ctx {
 
     int32_t sched_groups = 1, sched_chunk = 1;
     int32_t fused_groups = 1, fused_chunk = 1;  // chunks of the fused step's count + predict
+    int32_t resident_max = 1024;         // nb_run: one resident workgroup up to this n
     Variant var_full{2, 2, 4096, 256};   // calls on (nearly) all particles
     Variant var_block{2, 2, 4096, 256};  // block-step calls (device-resident count)
     int32_t max_target = 4096;           // partial planes are sized for targets up to this
@@ -469,6 +470,34 @@ nb_status enqueue_step(nb_ctx *c, double eta, hipStream_t s) {
     return NB_OK;
 }
 
+// nb_run's resident path: contexts of at most resident_max softened particles in the FP32,
+// double-single or FP64 arithmetic.
+bool use_resident(const nb_ctx *c) {
+    return c->n <= c->resident_max && c->eps > 0.0 &&
+           (c->prec == NB_FP32 || c->prec == NB_DS || c->prec == NB_FP64);
+}
+
+nb_status enqueue_resident(nb_ctx *c, double eta, int32_t steps, hipStream_t s) {
+    const StateRW rw = state_rw(c);
+    const double e2 = c->eps * c->eps;
+    switch (c->prec) {
+        case NB_FP32:
+            run_resident<ModeF32><<<1, WGL, 0, s>>>(rw, c->active, c->acc1, c->ctl, e2, eta, c->lmin,
+                                                    c->lmax, steps);
+            break;
+        case NB_DS:
+            run_resident<ModeDS><<<1, WGL, 0, s>>>(rw, c->active, c->acc1, c->ctl, e2, eta, c->lmin,
+                                                   c->lmax, steps);
+            break;
+        default:
+            run_resident<ModeF64><<<1, WGL, 0, s>>>(rw, c->active, c->acc1, c->ctl, e2, eta, c->lmin,
+                                                    c->lmax, steps);
+            break;
+    }
+    LAUNCH_OK(c);
+    return NB_OK;
+}
+
 nb_status latched(nb_ctx *c) {
     DevControl h;
     HIP_OK(c, hipMemcpyAsync(&h, c->ctl, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -822,14 +851,26 @@ nb_status nb_run(nb_ctx *c, double eta, int64_t t_end, int64_t max_steps, int32_
     nb_status r;
     if ((r = need(c)) != NB_OK) return r;
     if (chunk < 1) return fail(c, NB_EINVAL, "chunk must be >= 1");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return fail(c, NB_EINVAL, "eta must be > 0");
     set_t_end<<<1, WG, 0, c->stream>>>(c->ctl, t_end);
     LAUNCH_OK(c);
+    const bool resident = use_resident(c) && !c->profile;
+    if (resident) {  // new levels of a block corrected by a separate nb_correct
+        sched_newlevel<<<grid_for(c->n, 2048), WG, 0, c->stream>>>(state_rw(c), c->active, c->crit,
+                                                                    eta, c->lmin, c->lmax, c->ctl);
+        LAUNCH_OK(c);
+    }
     int64_t done_steps = 0;
     for (;;) {
         int32_t k = chunk;
         if (max_steps > 0) k = (int32_t)std::min<int64_t>(k, max_steps - done_steps);
         if (k <= 0) break;
-        if ((r = nb_step(c, eta, k, use_graph)) != NB_OK) return r;
+        if (resident) {
+            if ((r = enqueue_resident(c, eta, k, c->stream)) != NB_OK) return r;
+            c->predicted = false;  // the j-particle stream was not written
+        } else if ((r = nb_step(c, eta, k, use_graph)) != NB_OK) {
+            return r;
+        }
         done_steps += k;
         DevControl h;
         HIP_OK(c, hipMemcpyAsync(&h, c->ctl, sizeof h, hipMemcpyDeviceToHost, c->stream));
@@ -1107,6 +1148,12 @@ nb_status nb_fma_rate(nb_ctx *c, double *tflops) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *tflops = best;
+    return NB_OK;
+}
+
+nb_status nb_set_resident(nb_ctx *c, int32_t max_n) {
+    if (!c || max_n < 0) return NB_EINVAL;
+    c->resident_max = max_n;
     return NB_OK;
 }
 

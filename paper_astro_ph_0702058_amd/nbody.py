@@ -52,7 +52,8 @@ EXPORTS = ["nb_create", "nb_destroy", "nb_set_stream", "nb_bind", "nb_init",
            "nb_ens_set_layout", "nb_ens_init", "nb_ens_run", "nb_ens_control", "nb_ens_energy",
            "nb_ens_last_error", "nb_shared_step", "nb_force_vjp", "nb_step_vjp",
            "nb_scratch_bytes", "nb_bind_scratch", "nb_ens_scratch_bytes", "nb_ens_bind_scratch",
-           "nb_ens_set_local", "nb_fma_rate", "nb_force_noalloc"]
+           "nb_ens_set_local", "nb_fma_rate", "nb_force_noalloc",
+           "nb_set_resident"]
 
 _lib = None
 
@@ -108,6 +109,7 @@ def load_library(path: str = LIB_PATH):
         "nb_ens_set_local": [P, I64, I32, I64],
         "nb_fma_rate": [P, ctypes.POINTER(D)],
         "nb_force_noalloc": [P, P, P, I32, P, P, P],
+        "nb_set_resident": [P, I32],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -364,6 +366,10 @@ class Context:
         t_ticks = int(round(float(t_end) * 2.0 ** self.lmax))
         self._check(self.lib.nb_run(self.h, float(eta), t_ticks, int(max_steps), int(chunk),
                                     int(bool(use_graph))))
+
+    def nb_set_resident(self, max_n):
+        """nb_run on contexts of at most max_n particles uses one resident workgroup (0: never)."""
+        self._check(self.lib.nb_set_resident(self.h, int(max_n)))
 
     def nb_energy(self):
         ek, ep = ctypes.c_double(), ctypes.c_double()

@@ -211,6 +211,74 @@ def test_plummer_1024_to_one_eighth(prec):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "ds", "fp32"])
+@pytest.mark.parametrize("n", [300, 1024, 1500])
+def test_resident_run_equals_launch_chain(prec, n):
+    """nb_run on a small context by one resident workgroup (nb_set_resident(2048); the default
+    is up to n = 1024) and by
+    the chain of launches per step (nb_set_resident(0)) from the same state, to t = 1/16 with
+    dt <= 1/8 (blocks from one particle up to every particle at t = 0 and the level-3 times):
+    FP64 and double-single take the same block steps with positions to 1e-12 (only summation
+    orders differ); FP32 the same steps within 2 % (levels are decided from forces that differ
+    by rounding) and the energy error of the same size.  A run cut by max_steps stops at exactly
+    that many steps on either path, and a separate nb_correct before nb_run has its new levels
+    assigned first."""
+    eps, nu = 1 / 256, 0.01
+    out = []
+    for resident in (2048, 0):
+        x, v, m, st, ctx = make(n, 27, eps, prec, 3)
+        ctx.nb_set_resident(resident)
+        ctx.nb_init(nu)
+        ek0, ep0 = ctx.nb_energy()
+        ctx.nb_run(nu, 1 / 16, chunk=64)
+        c = ctx.nb_read_control()
+        ek1, ep1 = ctx.nb_energy()
+        out.append((st.numpy(), c, abs((ek1 + ep1) / (ek0 + ep0) - 1)))
+        ctx.nb_run(nu, 1 / 8, max_steps=37, chunk=16)
+        c2 = ctx.nb_read_control()
+        assert c2.n_steps == c.n_steps + 37
+        ctx.close()
+    (ga, ca, da), (gb, cb, db) = out
+    print(f"n={n} {prec}: resident {ca.n_steps} steps dE/E {da:.3e}; chain {cb.n_steps} steps "
+          f"dE/E {db:.3e}", flush=True)
+    assert ca.t_cur == cb.t_cur == 1 << (LMAX - 4)
+    if prec == "fp32":
+        assert abs(ca.n_steps - cb.n_steps) <= 0.02 * cb.n_steps
+        assert da <= 3 * db + 1e-9 and db <= 3 * da + 1e-9
+    else:
+        assert ca.n_steps == cb.n_steps and ca.n_active_sum == cb.n_active_sum
+        assert np.array_equal(ga["level"], gb["level"]) and np.array_equal(ga["tick"], gb["tick"])
+        assert np.max(np.abs(ga["x"] - gb["x"])) < 1e-12
+
+
+def test_resident_run_after_separate_calls():
+    """A block corrected by the separate calls (nb_schedule_block, nb_predict, nb_force,
+    nb_correct) and then nb_run on the resident path: the pending new levels are assigned before
+    the first resident step, as the launch chain does; FP64 runs follow the oracle."""
+    import torch
+    n, eps, nu = 700, 1 / 256, 0.01
+    x, v, m, st, ctx = make(n, 28, eps, "fp64", 3)
+    ref = oracle.BlockIntegrator(x, v, m, eps=eps, nu=nu, lmin=3)
+    ctx.nb_init(nu)
+    acc = torch.zeros((3, n), dtype=torch.float64, device="cuda")
+    jerk = torch.zeros_like(acc); pot = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        ctx.nb_schedule_block(nu)
+        idx_addr, cnt_addr = ctx.nb_active()
+        ctx.nb_predict()
+        ctx.nb_force(acc, jerk, pot, i_idx=idx_addr, n_i=cnt_addr, n_i_max=n)
+        ctx.nb_correct(acc, jerk, pot)
+        ref.step()
+    ctx.nb_run(nu, 1 / 32, chunk=32)
+    ref.run_until(1 / 32)
+    c = ctx.nb_read_control()
+    g = st.numpy()
+    ctx.close()
+    assert c.n_steps == ref.n_steps and c.t_cur == ref.t
+    assert np.array_equal(g["level"], ref.level) and np.array_equal(g["tick"], ref.tick)
+    assert np.max(np.abs(g["x"] - ref.x)) < 1e-10
+
+
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_fused_step_equals_separate_calls(prec):
     """nb_step launches selection+prediction, force, reduction and correction+new levels; the
