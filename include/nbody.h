@@ -202,7 +202,7 @@ nb_status nb_step(nb_ctx *ctx, double eta, int32_t nsteps, int32_t use_graph);
 nb_status nb_run(nb_ctx *ctx, double eta, int64_t t_end, int64_t max_steps, int32_t chunk,
                  int32_t use_graph);
 
-/* nb_run's path for small contexts: with n <= max_n (default 2048; 0: never), softening
+/* nb_run's path for small contexts: with n <= max_n (default 1024; 0: never), softening
  * eps > 0 and the FP32, double-single or FP64 arithmetic, nb_run advances the particles with
  * one resident workgroup that repeats the whole block step (the block of Sec. 2, the force of
  * Eq. Force on it with every particle predicted as it is staged in LDS, the corrector and the
