@@ -73,6 +73,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="what", required=True)
     a = sub.add_parser("stats"); a.add_argument("csv"); a.add_argument("--cmd", required=True)
+    a.add_argument("--top", type=int, default=12, help="kernels listed, by total time")
     b = sub.add_parser("traffic"); b.add_argument("fetch"); b.add_argument("write")
     b.add_argument("--kernel", required=True); b.add_argument("--copy-bytes", type=float, required=True)
     b.add_argument("--json"); b.add_argument("--n", type=int, required=True)
@@ -86,7 +87,7 @@ def main(argv=None):
     c.add_argument("--ms", type=float, help="dispatch duration (ms) for the rates")
     args = ap.parse_args(argv)
     if args.what == "stats":
-        print(stats(args.csv, args.cmd))
+        print(stats(args.csv, args.cmd, args.top))
     elif args.what == "traffic":
         t = traffic(args.fetch, args.write, args.kernel, args.copy_bytes)
         fb, wb = t["FETCH_SIZE"]["bytes_per_dispatch"], t["WRITE_SIZE"]["bytes_per_dispatch"]
