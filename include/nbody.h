@@ -204,11 +204,13 @@ nb_status nb_run(nb_ctx *ctx, double eta, int64_t t_end, int64_t max_steps, int3
 
 /* nb_run's path for small contexts: with n <= max_n (default 1024; 0: never), softening
  * eps > 0 and the FP32, double-single or FP64 arithmetic, nb_run advances the particles with
- * one resident workgroup that repeats the whole block step (the block of Sec. 2, the force of
- * Eq. Force on it with every particle predicted as it is staged in LDS, the corrector and the
- * new levels of Eq. timestep) up to `chunk` times per launch, instead of a chain of launches
- * per step.  The same steps up to the summation order; nb_run does not write the j-particle
- * stream then (call nb_predict before a later nb_force). */
+ * one resident workgroup that keeps the FP64 state in LDS and repeats the whole block step (the
+ * block of Sec. 2, the force of Eq. Force on it with every particle predicted as it is staged,
+ * the corrector and the new levels of Eq. timestep) up to `chunk` times per launch, instead of
+ * a chain of launches per step; the state is written back at the end of each launch.  The same
+ * steps up to the summation order; nb_run does not write the j-particle stream then (call
+ * nb_predict before a later nb_force).  NB_EINVAL for max_n outside [0, 1024] (the largest
+ * state one workgroup's LDS holds). */
 nb_status nb_set_resident(nb_ctx *ctx, int32_t max_n);
 
 /* Sec. 4.2 energy diagnostic, synchronising: kinetic sum m v^2 / 2 and softened potential

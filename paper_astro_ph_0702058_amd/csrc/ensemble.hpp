@@ -396,60 +396,207 @@ __global__ void __launch_bounds__(WGL) ens_local(EnsView e, StateRW s, double et
     if (clamp) e.flags[1] = 1;
 }
 
-// Block steps of one particle set by one resident workgroup, for sets so small that a block
-// step is far shorter than a chain of kernel launches: select the next block up to the
-// scheduler's t_end (block_select), its force (block_force_staged; the 7 sums of each block
-// row staged in `stage`, ld = n), the corrector and the new levels (Eq. timestep, power-of-two
-// rules), repeated up to `steps` times or until no block lies at or before t_end.  The
-// scheduler record is the context's (block time and size, step counters, latched flags).
+// ------------------------------------------------------------------------------------------
+// Block steps of one small particle set by one resident workgroup, its whole state in LDS.
+// ------------------------------------------------------------------------------------------
+constexpr int RES_MAX = 1024;  // particles whose FP64 state (116 B each) one workgroup keeps in LDS
+constexpr int RES_NT = 2;      // j sub-tiles of TJ staged per pass
+static_assert(RES_MAX <= WGL, "the resident selection takes one particle per work-item");
+
+// Next block of a set of n <= WGL particles (one per work-item) by one workgroup of WGL: the
+// smallest t_i + dt_i (Sec. 2) and every particle attaining it, in ascending order, into
+// out[0 ...].  Three barriers: wave minima, then wave counts of the block, then the list.
+// Returns false (n_act = 0) when the block lies beyond t_end; red and cnt are LDS scratch of
+// WGL / 64 entries each, free again when this returns.
+__device__ bool resident_select(const int64_t *tick, const int32_t *level, int32_t n,
+                                int32_t lmax, int64_t t_end, int32_t *out, int64_t *red,
+                                int32_t *cnt, int32_t &n_act, int64_t &t_next) {
+    const int32_t i = threadIdx.x;
+    const int lane = i & 63, wave = i >> 6;
+    const int64_t tn = i < n ? tick[i] + ((int64_t)1 << (lmax - level[i])) : INT64_MAX;
+    int64_t m = tn;
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t o = __shfl_xor(m, off, 64);
+        m = o < m ? o : m;
+    }
+    if (lane == 0) red[wave] = m;
+    __syncthreads();
+    int64_t t_min = red[0];
+#pragma unroll
+    for (int w = 1; w < WGL / 64; ++w) t_min = red[w] < t_min ? red[w] : t_min;
+    if (t_min > t_end) {
+        n_act = 0;
+        return false;
+    }
+    const bool f = tn == t_min;
+    const uint64_t mask = __ballot(f);
+    if (lane == 0) cnt[wave] = __popcll(mask);
+    __syncthreads();
+    int32_t below = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < WGL / 64; ++w) {
+        const int32_t c = cnt[w];
+        below += w < wave ? c : 0;
+        total += c;
+    }
+    if (f) out[below + __popcll(mask & ((1ull << lane) - 1ull))] = i;
+    // equal on every work-item: kept in scalar registers
+    n_act = __builtin_amdgcn_readfirstlane(total);
+    t_next = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(t_min >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)t_min));
+    __syncthreads();  // the list is complete, and red and cnt may be written again
+    return true;
+}
+
+// The force of the block `list` (n_act <= n <= WGL particles, one pass: S lanes per block
+// particle with S * 2^ceil(log2 n_act) <= WGL) against all n particles predicted to t_next as
+// they are staged RES_NT sub-tiles at a time (Sec. 2 Eq. Force, App. A softening, j != i), then
+// the corrector and the new level of each block particle by the lane that holds its sums.
+// Waves whose slots are all past the block only stage.  The state is read only while staging
+// and predicting the i-particles, so the correctors need no barrier before their writes.
 template <class M>
-__global__ void __launch_bounds__(WGL) run_resident(StateRW s, int32_t *active, double *stage,
-                                                    DevControl *ctl, double eps2, double eta,
-                                                    int32_t lmin, int32_t lmax, int32_t steps) {
-    __shared__ int64_t red[WGL / 64];
-    __shared__ int32_t wsum[WGL / 64];
-    __shared__ int64_t tn_lds[TN_CACHE];
-    __shared__ typename M::Smem sm[WGL / TJ];
+__device__ void resident_force_correct(const StateRW &s, const int32_t *list, int32_t n_act,
+                                       int64_t t_next, typename EpsOf<M>::T eps2,
+                                       typename M::Smem (&sm)[RES_NT], double eta, int32_t lmin,
+                                       int32_t lmax, bool &bad, bool &clamp) {
     const int32_t n = s.n;
+    int32_t p2 = 1;
+    while (p2 < n_act) p2 <<= 1;
+    const int32_t Sl = WGL / p2 > 64 ? 64 : WGL / p2;
+    const int32_t q = (int32_t)threadIdx.x / Sl, slice = (int32_t)threadIdx.x % Sl;
+    const bool has = q < n_act;
+    const bool busy = (int32_t)(threadIdx.x & ~63u) / Sl < n_act;  // wave-uniform
+    const int32_t g = has ? list[q] : 0;
+    const int32_t own = has ? g : -1;  // own slot (none on padding)
+    double xp[3], vp[3];
+    predicted(s, g, t_next, xp, vp);
+    const typename M::I ii = M::make_i(xp, vp, s.m[g]);
+    typename M::Sum S = M::sum_zero();
+    for (int32_t t0 = 0; t0 < n; t0 += RES_NT * TJ) {
+        __syncthreads();  // the previous pass's tiles are consumed
+        if (threadIdx.x < RES_NT * TJ) {
+            const int32_t jl = t0 + (int32_t)threadIdx.x;
+            typename M::Smem &st = sm[threadIdx.x / TJ];
+            if (jl < n) {
+                double xj[3], vj[3];
+                predicted(s, jl, t_next, xj, vj);
+                M::put(st, threadIdx.x % TJ, xj, vj, s.m[jl]);
+            } else {  // padding: zero mass contributes nothing
+                const double z[3] = {0.0, 0.0, 0.0};
+                M::put(st, threadIdx.x % TJ, z, z, 0.0);
+            }
+        }
+        __syncthreads();
+        if (!busy) continue;
+        const int32_t jn = n - t0 < RES_NT * TJ ? n - t0 : RES_NT * TJ;
+        for (int b = 0; b * TJ < jn; ++b) {  // 256-slot sub-tiles, folded one at a time
+            const int32_t cnt = jn - b * TJ < TJ ? jn - b * TJ : TJ;
+            const int32_t rel = own - (t0 + b * TJ);
+            typename M::Tile T = M::tile_zero();
+            if (__ballot((uint32_t)rel < (uint32_t)cnt) != 0) {
+#pragma unroll 2
+                for (int jj = slice; jj < cnt; jj += Sl)
+                    M::template interact<true, true>(ii, sm[b], jj, eps2, T, jj == rel);
+            } else {
+#pragma unroll 2
+                for (int jj = slice; jj < cnt; jj += Sl)
+                    M::template interact<true>(ii, sm[b], jj, eps2, T);
+            }
+            M::fold(S, T);
+        }
+    }
+    if (!busy) return;
+    for (int off = Sl >> 1; off > 0; off >>= 1) M::shfl_add(S, off);
+    if (!has || slice != 0) return;
+    const Out7 o = M::out(S);
+    const double a1[3] = {o.v[0], o.v[1], o.v[2]}, k1[3] = {o.v[3], o.v[4], o.v[5]};
+    const double dt_old = (double)(t_next - s.tick[g]) * s.tick_len;
+    double num = 0.0, den = 0.0;
+    bad = bad || !correct_particle(s, g, dt_old, a1, k1, -o.v[6], t_next, nullptr, &num, &den);
+    const double dt = den > 0.0 ? __builtin_sqrt(eta * num / den) : __builtin_inf();
+    bad = bad || __builtin_isnan(dt);
+    clamp = clamp || dt < s.tick_len;
+    s.level[g] = next_level(dt, s.level[g], t_next, lmin, lmax);
+}
+
+// Block steps of one particle set of n <= RES_MAX by one resident workgroup, for sets so small
+// that a block step is far shorter than a chain of kernel launches.  The FP64 state (x, v, a,
+// k, m, tick, level) is loaded into LDS once per launch and written back at its end; each pass
+// of the loop selects the next block up to the scheduler's t_end (resident_select, into an
+// LDS list), forces and corrects it (resident_force_correct), repeated up to `steps` times or until
+// no block lies at or before t_end.  Potentials go straight to the state's pot, the last block
+// stepped to `active`.  The scheduler record is the context's (block time and size, step
+// counters, latched flags).
+template <class M>
+__global__ void __launch_bounds__(WGL) run_resident(StateRW g, int32_t *active, DevControl *ctl,
+                                                    double eps2, double eta, int32_t lmin,
+                                                    int32_t lmax, int32_t steps) {
+    __shared__ double lx[3 * RES_MAX], lv[3 * RES_MAX], la[3 * RES_MAX], lk[3 * RES_MAX];
+    __shared__ double lm[RES_MAX];
+    __shared__ int64_t ltick[RES_MAX];
+    __shared__ int32_t llevel[RES_MAX], lact[RES_MAX];
+    __shared__ int64_t red[WGL / 64];
+    __shared__ int32_t wcnt[WGL / 64];
+    __shared__ typename M::Smem sm[RES_NT];
+    const int32_t n = g.n;
+    if (n > RES_MAX || ctl->done) return;  // every work-item reads the same record
     const int64_t t_end = ctl->t_end;
-    if (ctl->done) return;  // every work-item reads the same record
-    if (threadIdx.x == 0) ctl->n_pending = 0;  // levels are current (assigned before this launch)
-    bool bad = false, clamp = false;
+    for (int32_t e = threadIdx.x; e < 3 * n; e += WGL) {
+        lx[e] = g.x[e];
+        lv[e] = g.v[e];
+        la[e] = g.a[e];
+        lk[e] = g.k[e];
+    }
+    for (int32_t i = threadIdx.x; i < n; i += WGL) {
+        lm[i] = g.m[i];
+        ltick[i] = g.tick[i];
+        llevel[i] = g.level[i];
+    }
+    StateRW s = g;
+    s.x = lx; s.v = lv; s.a = la; s.k = lk; s.m = lm; s.tick = ltick; s.level = llevel;
+    __syncthreads();
+    bool bad = false, clamp = false, done = false;
+    int32_t n_last = 0, stepped = 0;  // size of the last block stepped; block steps taken
+    int64_t t_last = 0, act_sum = 0;
     for (int32_t it = 0; it < steps; ++it) {
         int32_t n_act = 0;
         int64_t t_next = 0;
-        if (!block_select<WGL>(s.tick, s.level, 0, n, lmax, t_end, active, tn_lds, red, wsum,
-                               n_act, t_next)) {
-            if (threadIdx.x == 0) {
-                ctl->done = 1;
-                ctl->n_act = 0;
-            }
+        if (!resident_select(s.tick, s.level, n, lmax, t_end, lact, red, wcnt, n_act, t_next)) {
+            done = true;
             break;
         }
-        block_force_staged<M, WGL>(s, 0, n, active, n_act, t_next, eps_as<M>(eps2), sm, stage, n);
-        for (int32_t q = threadIdx.x; q < n_act; q += WGL) {
-            const int32_t i = active[q];
-            const double a1[3] = {stage[q], stage[(int64_t)n + q], stage[2 * (int64_t)n + q]};
-            const double k1[3] = {stage[3 * (int64_t)n + q], stage[4 * (int64_t)n + q],
-                                  stage[5 * (int64_t)n + q]};
-            const double dt_old = (double)(t_next - s.tick[i]) * s.tick_len;
-            double num = 0.0, den = 0.0;
-            bad = bad || !correct_particle(s, i, dt_old, a1, k1, -stage[6 * (int64_t)n + q], t_next,
-                                           nullptr, &num, &den);
-            const double dt = den > 0.0 ? __builtin_sqrt(eta * num / den) : __builtin_inf();
-            bad = bad || __builtin_isnan(dt);
-            clamp = clamp || dt < s.tick_len;
-            s.level[i] = next_level(dt, s.level[i], t_next, lmin, lmax);
-        }
+        resident_force_correct<M>(s, lact, n_act, t_next, eps_as<M>(eps2), sm, eta, lmin, lmax,
+                                  bad, clamp);
+        n_last = n_act;
+        t_last = t_next;
+        stepped += 1;
+        act_sum += n_act;
         __syncthreads();  // corrected times and levels precede the next selection
-        if (threadIdx.x == 0) {
-            ctl->t_cur = t_next;
-            ctl->t_next = t_next;
-            ctl->n_act = n_act;
-            ctl->n_steps += 1;
-            ctl->n_active_sum += n_act;
-        }
     }
+    // the scheduler record once per launch (every work-item holds the same counts)
+    if (threadIdx.x == 0) {
+        ctl->n_pending = 0;  // levels are current
+        if (stepped > 0) {
+            ctl->t_cur = t_last;
+            ctl->t_next = t_last;
+            ctl->n_steps += stepped;
+            ctl->n_active_sum += act_sum;
+        }
+        ctl->n_act = done ? 0 : n_last;
+        if (done) ctl->done = 1;
+    }
+    __syncthreads();
+    for (int32_t e = threadIdx.x; e < 3 * n; e += WGL) {
+        g.x[e] = lx[e];
+        g.v[e] = lv[e];
+        g.a[e] = la[e];
+        g.k[e] = lk[e];
+    }
+    for (int32_t i = threadIdx.x; i < n; i += WGL) {
+        g.tick[i] = ltick[i];
+        g.level[i] = llevel[i];
+    }
+    for (int32_t q = threadIdx.x; q < n_last; q += WGL) active[q] = lact[q];  // the last block
     if (bad) ctl->flag_nonfinite = 1;
     if (clamp) ctl->flag_dtmin = 1;
 }

@@ -473,7 +473,7 @@ nb_status enqueue_step(nb_ctx *c, double eta, hipStream_t s) {
 // nb_run's resident path: contexts of at most resident_max softened particles in the FP32,
 // double-single or FP64 arithmetic.
 bool use_resident(const nb_ctx *c) {
-    return c->n <= c->resident_max && c->eps > 0.0 &&
+    return c->n <= c->resident_max && c->n <= RES_MAX && c->eps > 0.0 &&
            (c->prec == NB_FP32 || c->prec == NB_DS || c->prec == NB_FP64);
 }
 
@@ -482,16 +482,16 @@ nb_status enqueue_resident(nb_ctx *c, double eta, int32_t steps, hipStream_t s) 
     const double e2 = c->eps * c->eps;
     switch (c->prec) {
         case NB_FP32:
-            run_resident<ModeF32><<<1, WGL, 0, s>>>(rw, c->active, c->acc1, c->ctl, e2, eta, c->lmin,
-                                                    c->lmax, steps);
+            run_resident<ModeF32><<<1, WGL, 0, s>>>(rw, c->active, c->ctl, e2, eta, c->lmin, c->lmax,
+                                                    steps);
             break;
         case NB_DS:
-            run_resident<ModeDS><<<1, WGL, 0, s>>>(rw, c->active, c->acc1, c->ctl, e2, eta, c->lmin,
-                                                   c->lmax, steps);
+            run_resident<ModeDS><<<1, WGL, 0, s>>>(rw, c->active, c->ctl, e2, eta, c->lmin, c->lmax,
+                                                   steps);
             break;
         default:
-            run_resident<ModeF64><<<1, WGL, 0, s>>>(rw, c->active, c->acc1, c->ctl, e2, eta, c->lmin,
-                                                    c->lmax, steps);
+            run_resident<ModeF64><<<1, WGL, 0, s>>>(rw, c->active, c->ctl, e2, eta, c->lmin, c->lmax,
+                                                    steps);
             break;
     }
     LAUNCH_OK(c);
@@ -1152,7 +1152,9 @@ nb_status nb_fma_rate(nb_ctx *c, double *tflops) {
 }
 
 nb_status nb_set_resident(nb_ctx *c, int32_t max_n) {
-    if (!c || max_n < 0) return NB_EINVAL;
+    if (!c) return NB_EINVAL;
+    if (max_n < 0 || max_n > RES_MAX)
+        return fail(c, NB_EINVAL, "nb_set_resident: max_n must lie in [0, %d]", RES_MAX);
     c->resident_max = max_n;
     return NB_OK;
 }

@@ -212,10 +212,10 @@ def test_plummer_1024_to_one_eighth(prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "ds", "fp32"])
-@pytest.mark.parametrize("n", [300, 1024, 1500])
+@pytest.mark.parametrize("n", [300, 1000, 1024])
 def test_resident_run_equals_launch_chain(prec, n):
-    """nb_run on a small context by one resident workgroup (nb_set_resident(2048); the default
-    is up to n = 1024) and by
+    """nb_run on a small context by one resident workgroup (nb_set_resident(1024), the default
+    and the largest state one workgroup keeps in LDS) and by
     the chain of launches per step (nb_set_resident(0)) from the same state, to t = 1/16 with
     dt <= 1/8 (blocks from one particle up to every particle at t = 0 and the level-3 times):
     FP64 and double-single take the same block steps with positions to 1e-12 (only summation
@@ -225,7 +225,7 @@ def test_resident_run_equals_launch_chain(prec, n):
     assigned first."""
     eps, nu = 1 / 256, 0.01
     out = []
-    for resident in (2048, 0):
+    for resident in (1024, 0):
         x, v, m, st, ctx = make(n, 27, eps, prec, 3)
         ctx.nb_set_resident(resident)
         ctx.nb_init(nu)
@@ -249,6 +249,18 @@ def test_resident_run_equals_launch_chain(prec, n):
         assert ca.n_steps == cb.n_steps and ca.n_active_sum == cb.n_active_sum
         assert np.array_equal(ga["level"], gb["level"]) and np.array_equal(ga["tick"], gb["tick"])
         assert np.max(np.abs(ga["x"] - gb["x"])) < 1e-12
+        assert np.max(np.abs(ga["pot"] - gb["pot"])) < 1e-12 * np.max(np.abs(gb["pot"]))
+
+
+def test_resident_limit_is_the_lds_state():
+    """nb_set_resident accepts limits up to 1024 particles (the FP64 state one workgroup keeps in
+    LDS) and refuses larger ones."""
+    x, v, m, st, ctx = make(64, 27, 1 / 256, "fp32", 3)
+    ctx.nb_set_resident(1024)
+    ctx.nb_set_resident(0)
+    with pytest.raises(RuntimeError, match="max_n"):
+        ctx.nb_set_resident(1025)
+    ctx.close()
 
 
 def test_resident_run_after_separate_calls():
