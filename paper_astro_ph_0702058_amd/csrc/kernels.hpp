@@ -1463,6 +1463,133 @@ __global__ void __launch_bounds__(WG) fused_correct_level(StateRW s, const int32
     }
 }
 
+// The block step's second pass and corrector in one launch: for each block row the
+// fixed-order sum of its K partial planes, exactly as force_reduce forms it (wave w of RW adds
+// the planes k = w mod RW into four running sums, the waves' totals added in wave order), then
+// the corrector, the new level and the histogram update of the block particle, as
+// fused_correct_level does them.  A unit is RC_ROWS consecutive block rows: lane c * RC_ROWS + r
+// of every wave takes sum c of row r; wave 0 gathers the 7 sums of row r into lane r, which
+// corrects it.  Units are dealt to the 8 XCDs in contiguous runs, so the halves of a 128-byte
+// line of a partial plane are read on one XCD.  With K = 1 the force wrote the sums to
+// acc/jerk/pot directly and only the corrector runs.
+constexpr int RC_ROWS = 8;
+
+template <bool FIXED>
+__global__ void __launch_bounds__(WG_REDUCE) reduce_correct_level(ForceCommon fc, int32_t ib,
+                                                                  StateRW s, double eta,
+                                                                  int32_t lmin, int32_t lmax,
+                                                                  DevControl *ctl) {
+    __shared__ double part[RW][64];
+    __shared__ int64_t ipart[FIXED ? RW : 1][64];
+    __shared__ int32_t ibad[FIXED ? RW : 1][64];
+    __shared__ int32_t dh[NLEV];
+    __shared__ int32_t any;
+    if (threadIdx.x < NLEV) dh[threadIdx.x] = 0;
+    if (threadIdx.x == 0) any = 0;
+    __syncthreads();
+    const int32_t n_act = ctl->n_act < fc.n_i_max ? ctl->n_act : fc.n_i_max;
+    const int64_t t_next = ctl->t_next;
+    if (n_act <= 0) return;
+    const ForcePlan pl = make_plan(n_act, fc.n, ib, fc.target, fc.kmax, fc.smax);
+    const int32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t c = lane / RC_ROWS, r = lane % RC_ROWS;  // c = 7: idle lanes
+    const int32_t U = (n_act + RC_ROWS - 1) / RC_ROWS;
+    const int32_t per = (int32_t)gridDim.x >> 3, x = blockIdx.x & 7, chunk = (U + 7) >> 3;
+    const int32_t u_end = (x + 1) * chunk < U ? (x + 1) * chunk : U;
+    for (int32_t u = x * chunk + (int32_t)(blockIdx.x >> 3); u < u_end; u += per) {
+        const int32_t q = u * RC_ROWS + r;
+        const bool live = c < 7 && q < n_act;
+        double t = 0.0;
+        if (pl.K == 1) {
+            if (w == 0 && live)
+                t = c < 3 ? fc.acc[c * (int64_t)fc.ld + q]
+                  : c < 6 ? fc.jerk[(c - 3) * (int64_t)fc.ld + q] : fc.pot[q];
+        } else {
+            const double *src = fc.partial + (int64_t)(c < 7 ? c : 0) * pl.P + q;
+            if constexpr (FIXED) {
+                int64_t sum = 0;
+                int32_t bad = 0;
+                if (live) {
+                    for (int32_t k = w; k < pl.K; k += RW) {
+                        const int64_t v = (int64_t)__double_as_longlong(src[(int64_t)k * 7 * pl.P]);
+                        bad |= v == INT64_MIN;
+                        ModeF32Fixed::add(sum, v, bad);
+                    }
+                }
+                ipart[w][lane] = sum;
+                ibad[w][lane] = bad;
+            } else {
+                double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+                if (live) {
+                    const int64_t st = (int64_t)RW * 7 * pl.P;
+                    int32_t k = w;
+                    for (; k + 3 * RW < pl.K; k += 4 * RW) {
+                        const double *b = src + (int64_t)k * 7 * pl.P;
+                        s0 += b[0]; s1 += b[st]; s2 += b[2 * st]; s3 += b[3 * st];
+                    }
+                    for (; k < pl.K; k += RW) s0 += src[(int64_t)k * 7 * pl.P];
+                }
+                part[w][lane] = ((s0 + s1) + s2) + s3;
+            }
+            __syncthreads();
+            if (w == 0 && live) {
+                if constexpr (FIXED) {
+                    int64_t sum = ipart[0][lane];
+                    int32_t bad = ibad[0][lane];
+#pragma unroll
+                    for (int k = 1; k < RW; ++k) {
+                        bad |= ibad[k][lane];
+                        ModeF32Fixed::add(sum, ipart[k][lane], bad);
+                    }
+                    const int F = c < 3 ? ModeF32Fixed::F_ACC : c < 6 ? ModeF32Fixed::F_JERK
+                                                                      : ModeF32Fixed::F_POT;
+                    t = bad ? __builtin_nan("") : __builtin_ldexp((double)sum, -F);
+                    if (c == 6) t = -t;
+                } else {
+                    t = part[0][lane];
+#pragma unroll
+                    for (int k = 1; k < RW; ++k) t += part[k][lane];
+                }
+            }
+        }
+        if (w == 0) {
+            if (live && !__builtin_isfinite(t)) ctl->flag_nonfinite = 1;
+            double v[7];
+#pragma unroll
+            for (int k = 0; k < 7; ++k) v[k] = __shfl(t, k * RC_ROWS + r, 64);
+            if (lane < RC_ROWS && q < n_act) {
+                const int32_t i = fc.ilist[q];
+                const double dt = (double)(t_next - s.tick[i]) * s.tick_len;
+                const double a1[3] = {v[0], v[1], v[2]}, k1[3] = {v[3], v[4], v[5]};
+                double num, den;
+                if (!correct_particle(s, i, dt, a1, k1, v[6], t_next, nullptr, &num, &den))
+                    ctl->flag_nonfinite = 1;
+                const double dtn = den > 0.0 ? __builtin_sqrt(eta * num / den) : __builtin_inf();
+                if (__builtin_isnan(dtn)) ctl->flag_nonfinite = 1;
+                else if (dtn < s.tick_len) ctl->flag_dtmin = 1;
+                const int32_t l0 = s.level[i];
+                const int32_t l1 = next_level(dtn, l0, t_next, lmin, lmax);
+                if (l1 != l0) {
+                    s.level[i] = l1;
+                    atomicAdd(&dh[l0 & (NLEV - 1)], -1);
+                    atomicAdd(&dh[l1 & (NLEV - 1)], 1);
+                    any = 1;
+                }
+            }
+        }
+        __syncthreads();  // part and ipart are written again by the next unit
+    }
+    __syncthreads();
+    if (any && threadIdx.x < NLEV && dh[threadIdx.x] != 0)
+        atomicAdd(&ctl->hist[threadIdx.x], dh[threadIdx.x]);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {  // nothing in this launch reads these
+        ctl->t_cur = t_next;
+        ctl->n_steps += 1;
+        ctl->n_active_sum += n_act;
+        ctl->n_pending = 0;
+    }
+}
+
 // ------------------------------------------------------------------------------------------
 // Calibration: the FP32 fused multiply-add issue rate (not part of the method).  Every
 // work-item runs FMA_CHAINS independent chains acc += x_c * m for `iters` iterations (two-operand

@@ -341,7 +341,8 @@ int64_t partial_rows_for(int32_t n, const Variant &v, int32_t smax) {
 // partial: the j-split partial planes (NULL: the context's own, in its workspace).
 nb_status enqueue_force(nb_ctx *c, const Variant &v, int cls, const int32_t *ilist,
                         const int32_t *n_i_dev, int32_t n_i_max, double *acc, double *jerk,
-                        double *pot, int32_t ld, hipStream_t s, double *partial = nullptr) {
+                        double *pot, int32_t ld, hipStream_t s, double *partial = nullptr,
+                        bool second_pass = true) {
     const int32_t ib = WG * v.ipl;
     const int32_t smax = smax_of(c->prec);
     ForceCommon fc{c->n, ilist, n_i_dev, n_i_max, v.target, v.kmax, acc, jerk, pot, ld,
@@ -398,6 +399,7 @@ nb_status enqueue_force(nb_ctx *c, const Variant &v, int cls, const int32_t *ili
         HIP_OK(c, hipEventRecord(e1, s));
         c->ev.push_back(nb_ctx::Timed{e0, e1, cls});
     }
+    if (!second_pass) return NB_OK;  // the caller sums the partials (reduce_correct_level)
     // second pass: a no-op when the plan has K == 1
     const int32_t units = ((n_i_max + 63) / 64) * 7;
     const int32_t rgrid = std::max(1, std::min(units, c->num_cu * 8));
@@ -461,11 +463,20 @@ nb_status enqueue_step(nb_ctx *c, double eta, hipStream_t s) {
     sched_scatter<<<g, WG, 0, s>>>(fv, c->ctl);
     LAUNCH_OK(c);
     if ((r = enqueue_force(c, c->var_block, 1, c->active, &c->ctl->n_act, c->n, c->acc1, c->jerk1,
-                           c->pot1, c->n, s)) != NB_OK)
+                           c->pot1, c->n, s, nullptr, false)) != NB_OK)
         return r;
-    fused_correct_level<<<grid_for(c->n, 2048), WG, 0, s>>>(state_rw(c), c->active, c->acc1, c->jerk1,
-                                                             c->pot1, c->n, eta, c->lmin, c->lmax,
-                                                             c->ctl);
+    // the j-split sums and the corrector in one launch; the same ForceCommon as the force
+    const Variant &v = c->var_block;
+    ForceCommon fc{c->n, c->active, &c->ctl->n_act, c->n, v.target, v.kmax, c->acc1, c->jerk1,
+                   c->pot1, c->n, c->partial, c->ctl, smax_of(c->prec)};
+    const int32_t units = (c->n + RC_ROWS - 1) / RC_ROWS;
+    const int32_t rgrid = (std::max(8, std::min(units, c->num_cu * 2)) + 7) & ~7;
+    if (c->prec == NB_FP32_FIXED)
+        reduce_correct_level<true><<<rgrid, WG_REDUCE, 0, s>>>(fc, WG * v.ipl, state_rw(c), eta,
+                                                                c->lmin, c->lmax, c->ctl);
+    else
+        reduce_correct_level<false><<<rgrid, WG_REDUCE, 0, s>>>(fc, WG * v.ipl, state_rw(c), eta,
+                                                                 c->lmin, c->lmax, c->ctl);
     LAUNCH_OK(c);
     return NB_OK;
 }
