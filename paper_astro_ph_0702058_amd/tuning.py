@@ -54,12 +54,15 @@ def autotune(ctx, cache_path: str | None = DEFAULT_CACHE, reps: int = 2, retune:
     return chosen
 
 
-def ensemble_autotune(ens, state, x0, v0, eta, t_probe=1.0 / 32, steps_per_launch=32):
-    """Choose the ensemble's force work layout by timing short runs from the initial state:
-    first the j-loop unroll (all clusters one tile per item), then, for each
-    size class of clusters (N < 512, 512 <= N < 2048, N >= 2048), the whole j-tiles per work
-    item.  The state is restored from (x0, v0) before every trial and after tuning.
-    Returns the chosen layout."""
+def ensemble_autotune(ens, state, x0, v0, eta, t_probe=0.25, steps_per_launch=32):
+    """Choose the ensemble's force work layout by timing runs from the initial state to
+    t_probe (default 1/4: the phase in which nearly every cluster is active and which takes
+    most of a run's time): first the j-loop unroll (all clusters one tile per item), then, for
+    each size class of clusters (N < 512, 512 <= N < 2048, N >= 2048), the whole j-tiles per
+    work item.  The winner is timed again against the library's default layout (one tile per
+    item, unroll 2) on the same probe and kept only if it is faster; the state is restored
+    from (x0, v0) before every trial and after tuning.  Returns the layout in effect with both
+    probe times and whether the search beat the default."""
     import time
     import numpy as np
     import torch
@@ -76,6 +79,8 @@ def ensemble_autotune(ens, state, x0, v0, eta, t_probe=1.0 / 32, steps_per_launc
         ens.nb_ens_run(eta, t_probe, steps_per_launch=steps_per_launch)
         return time.perf_counter() - t
 
+    default = (np.ones(ens.C, np.int32), 1, 2)
+    trial(*default)  # warm: graphs and caches of the default layout
     tpi = np.ones(ens.C, np.int32)
     combos = [(1, 2), (1, 1)]
     timed = {c: trial(tpi, *c) for c in combos}
@@ -92,8 +97,15 @@ def ensemble_autotune(ens, state, x0, v0, eta, t_probe=1.0 / 32, steps_per_launc
             if t < best:
                 best, choice = t, cand
         tpi[mask] = choice
+    # the search's winner against the default, each timed once more, in that order
+    t_best = trial(tpi, ipl, unroll)
+    t_default = trial(*default)
+    beats = t_best < t_default
+    if not beats:
+        tpi, ipl, unroll = default
     ens.nb_ens_set_layout(tpi, ipl, unroll)
     state.x.copy_(x0); state.v.copy_(v0)
     return {"ipl": int(ipl), "unroll": int(unroll),
             "tiles_per_item_by_class": [int(tpi[m][0]) if m.any() else None for m in classes],
-            "probe_seconds": best}
+            "probe_t_end": t_probe, "probe_seconds_chosen": t_best,
+            "probe_seconds_default": t_default, "beats_default": bool(beats)}
