@@ -252,6 +252,31 @@ def test_resident_run_equals_launch_chain(prec, n):
         assert np.max(np.abs(ga["pot"] - gb["pot"])) < 1e-12 * np.max(np.abs(gb["pot"]))
 
 
+@pytest.mark.parametrize("n", [1, 2, 3, 64, 257])
+def test_small_sets_follow_oracle_on_both_paths(n):
+    """Degenerate and ragged small sets (a lone particle, a pair, three bodies, one wave, one
+    tile plus one) run to t = 1/8 in FP64 by the resident workgroup and by the launch chain:
+    both take the oracle's block steps exactly, with its times and levels, and its positions to
+    the predictors' rounding.  A lone particle feels nothing: every step is the largest."""
+    eps, nu, lmin = 1 / 64, 0.01, 3
+    for resident in (1024, 0):
+        x, v, m, st, ctx = make(n, 29 + n, eps, "fp64", lmin)
+        ctx.nb_set_resident(resident)
+        ctx.nb_init(nu)
+        ctx.nb_run(nu, 1 / 8, chunk=64)
+        c = ctx.nb_read_control()
+        g = st.numpy()
+        ctx.close()
+        ref = oracle.BlockIntegrator(x, v, m, eps=eps, nu=nu, lmin=lmin)
+        ref.run_until(1 / 8)
+        label = f"n={n} resident={resident}"
+        assert c.n_steps == ref.n_steps and c.t_cur == ref.t, (label, c, ref.n_steps, ref.t)
+        assert np.array_equal(g["tick"], ref.tick) and np.array_equal(g["level"], ref.level), label
+        assert np.max(np.abs(g["x"] - ref.x)) < 1e-10, label
+        if n == 1:
+            assert c.n_steps == 1 and np.all(g["level"] == lmin), label
+
+
 def test_resident_limit_is_the_lds_state():
     """nb_set_resident accepts limits up to 1024 particles (the FP64 state one workgroup keeps in
     LDS) and refuses larger ones."""
