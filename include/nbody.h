@@ -185,9 +185,11 @@ nb_status nb_force_noalloc(nb_ctx *ctx, const int32_t *i_idx, const int32_t *n_i
 nb_status nb_correct(nb_ctx *ctx, const double *acc, const double *jerk, const double *pot);
 
 /* One whole block step, nsteps times, with bitwise the result of nb_schedule_block, nb_predict,
- * nb_force on the block (library-owned outputs) and nb_correct, in five launches: the block
- * count fused with the predictor, the ordered block list, the force, its j-split reduction,
- * and the corrector fused with the new levels.  Particles on one level share their time (the
+ * nb_force on the block (library-owned outputs) and nb_correct, in three launches: the block
+ * selection fused with the predictor, the force, and its j-split reduction fused with the
+ * corrector and the new levels.  The block list this builds (nb_active) holds the same
+ * particles as the separate calls' but in no fixed order across chunks of the particle range;
+ * no result depends on that order.  Particles on one level share their time (the
  * rules above keep t_i a multiple of dt_i), so the block time is the first multiple of the
  * finest occupied step after the current time, read from a per-level count the step keeps on
  * the device; a particle found behind it latches an error (NB_ESTATE at the next synchronising

@@ -40,6 +40,9 @@ struct DevControl {
     int32_t flag_sched;     // latched: a particle's next time preceded the block time
     int32_t pad_;
     int32_t hist[64];       // particles per level
+    // fused selection: block members appended so far (low word) and chunks finished (high
+    // word); zero between steps
+    uint64_t sel;
 };
 
 // ------------------------------------------------------------------------------------------
@@ -1085,7 +1088,7 @@ __global__ void __launch_bounds__(WG) reset_control(DevControl *ctl) {
         ctl->t_cur = 0; ctl->t_next = 0; ctl->t_end = INT64_MAX; ctl->n_steps = 0;
         ctl->n_active_sum = 0; ctl->n_act = 0; ctl->flags = 0; ctl->t_cand = 0;
         ctl->n_pending = 0; ctl->done = 0; ctl->flag_nonfinite = 0; ctl->flag_dtmin = 0;
-        ctl->flag_sched = 0;
+        ctl->flag_sched = 0; ctl->sel = 0;
     }
 }
 
@@ -1352,8 +1355,8 @@ __global__ void __launch_bounds__(WG) sched_scatter(SchedView v, DevControl *ctl
 }
 
 // ------------------------------------------------------------------------------------------
-// Fused block step (Sec. 2), the launch sequence of the composite step call: count + predict,
-// ordered scatter (sched_scatter), force, reduction, correct + new levels.  Particles on one
+// Fused block step (Sec. 2), the launch sequence of the composite step call: select + predict,
+// force, then the reduction with the corrector and the new levels.  Particles on one
 // level share their time: the power-of-two rules keep each t_i a multiple of dt_i and every
 // particle is corrected at every multiple of its step, so t_i is the last multiple of dt_i not
 // after the current time.  The next block time is therefore the first multiple of the finest
@@ -1361,7 +1364,7 @@ __global__ void __launch_bounds__(WG) sched_scatter(SchedView v, DevControl *ctl
 // to it.  A per-level histogram in the control record gives the finest level without a pass
 // over all particles, so one pass both counts the block members of each chunk and predicts
 // every particle; the corrector assigns the new levels at once and posts the level changes to
-// the histogram.  The block list is the same ascending list the separate calls build.
+// the histogram.
 // ------------------------------------------------------------------------------------------
 constexpr int NLEV = 64;   // levels 0 .. lmax <= 52
 
@@ -1379,12 +1382,21 @@ __global__ void __launch_bounds__(WG) hist_build(const int32_t *level, int32_t n
     if (threadIdx.x < NLEV && h[threadIdx.x] != 0) atomicAdd(&ctl->hist[threadIdx.x], h[threadIdx.x]);
 }
 
-// One workgroup per chunk of v.chunk consecutive particles: block time from the histogram, the
-// chunk's count of block members (for sched_scatter), and the prediction of every particle.
+// One workgroup per chunk of v.chunk consecutive particles: the block time from the histogram,
+// the prediction of every particle, and the chunk's block members appended to the block list.
+// The chunk reserves its slots with one 64-bit atomic add on the control record (its member
+// count to the low word, one finished chunk to the high word); the chunk whose add completes
+// the high word knows the block size and writes the block record, then clears the word for the
+// next step.  Members are in ascending order within a chunk and chunks in the order their adds
+// land: a member's force and corrector do not depend on its place in the list (every row is
+// summed alone, in an order set by the block size), so the states are those of the ordered
+// list the separate calls build.
 template <int MODE>
-__global__ void __launch_bounds__(WG) fused_count_predict(SchedView v, StateView s, JStreamView js,
-                                                          DevControl *ctl) {
+__global__ void __launch_bounds__(WG) fused_select_predict(SchedView v, StateView s,
+                                                           JStreamView js, DevControl *ctl) {
     __shared__ int64_t red[WG / 64];
+    __shared__ int32_t wsum[WG / 64];
+    __shared__ int32_t sbase;
     int32_t lfine = -1;
     for (int32_t l = v.lmax; l >= 0; --l)
         if (ctl->hist[l] > 0) {
@@ -1405,13 +1417,36 @@ __global__ void __launch_bounds__(WG) fused_count_predict(SchedView v, StateView
             predict_store<MODE>(s, js, i, t_next);
         }
     }
-    c = wg_sum_i64(c, red);
+    c = wg_sum_i64(c, red);  // equal on every work-item
     if (threadIdx.x == 0) {
-        v.cnt[blockIdx.x] = (int32_t)c;
-        if (blockIdx.x == 0) {  // nothing else in this launch reads these two
+        const uint64_t old = atomicAdd((unsigned long long *)&ctl->sel,
+                                       (unsigned long long)((1ull << 32) | (uint64_t)c));
+        sbase = (int32_t)(old & 0xffffffffull);
+        if ((int32_t)(old >> 32) == v.groups - 1) {  // every other chunk has added
+            ctl->n_act = take ? sbase + (int32_t)c : 0;
+            if (take) ctl->t_next = t_next;
             ctl->t_cand = t_next;
             ctl->done = take ? 0 : 1;
+            ctl->n_pending = 0;
+            atomicExch((unsigned long long *)&ctl->sel, 0ull);
         }
+    }
+    __syncthreads();
+    if (c == 0) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t base = sbase;
+    for (int32_t i0 = lo; i0 < hi; i0 += WG) {
+        const int32_t i = i0 + threadIdx.x;
+        const bool f = i < hi && (v.tick[i] + ((int64_t)1 << (v.lmax - v.level[i]))) == t_next;
+        const uint64_t mask = __ballot(f);
+        const int32_t below = __popcll(mask & ((1ull << lane) - 1ull));
+        __syncthreads();
+        if (lane == 0) wsum[wave] = __popcll(mask);
+        __syncthreads();
+        int32_t off = base;
+        for (int w = 0; w < wave; ++w) off += wsum[w];
+        if (f) v.active[off + below] = i;
+        for (int w = 0; w < WG / 64; ++w) base += wsum[w];
     }
 }
 

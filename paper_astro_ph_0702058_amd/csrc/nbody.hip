@@ -445,8 +445,8 @@ nb_status enqueue_fused_prelude(nb_ctx *c, double eta, hipStream_t s) {
     return NB_OK;
 }
 
-// One block step as five launches: count + predict, ordered scatter, force, reduction,
-// correct + new levels.
+// One block step as three launches: selection + predict, force, reduction + correct + new
+// levels.
 nb_status enqueue_step(nb_ctx *c, double eta, hipStream_t s) {
     nb_status r;
     const StateView sv = state_view(c);
@@ -454,13 +454,11 @@ nb_status enqueue_step(nb_ctx *c, double eta, hipStream_t s) {
     const int32_t g = c->fused_groups;
     switch (c->prec) {
         case NB_FP32:
-        case NB_FP32_FIXED: fused_count_predict<0><<<g, WG, 0, s>>>(fv, sv, c->js, c->ctl); break;
-        case NB_DS: fused_count_predict<1><<<g, WG, 0, s>>>(fv, sv, c->js, c->ctl); break;
-        case NB_FP32_ALL: fused_count_predict<3><<<g, WG, 0, s>>>(fv, sv, c->js, c->ctl); break;
-        default: fused_count_predict<2><<<g, WG, 0, s>>>(fv, sv, c->js, c->ctl); break;
+        case NB_FP32_FIXED: fused_select_predict<0><<<g, WG, 0, s>>>(fv, sv, c->js, c->ctl); break;
+        case NB_DS: fused_select_predict<1><<<g, WG, 0, s>>>(fv, sv, c->js, c->ctl); break;
+        case NB_FP32_ALL: fused_select_predict<3><<<g, WG, 0, s>>>(fv, sv, c->js, c->ctl); break;
+        default: fused_select_predict<2><<<g, WG, 0, s>>>(fv, sv, c->js, c->ctl); break;
     }
-    LAUNCH_OK(c);
-    sched_scatter<<<g, WG, 0, s>>>(fv, c->ctl);
     LAUNCH_OK(c);
     if ((r = enqueue_force(c, c->var_block, 1, c->active, &c->ctl->n_act, c->n, c->acc1, c->jerk1,
                            c->pot1, c->n, s, nullptr, false)) != NB_OK)

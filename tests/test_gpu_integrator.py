@@ -351,6 +351,29 @@ def test_fused_step_equals_separate_calls(prec):
         assert np.array_equal(a[key], b[key]), key
 
 
+def test_fused_block_list_holds_the_oracle_block():
+    """The fused step appends each chunk's block members at an offset reserved by an atomic
+    add, so its list is ordered within chunks only: after every one of 25 single steps at
+    N = 5000 (five chunks of the particle range) the list holds exactly the oracle's block,
+    each member once, and the count, time and state follow the oracle (FP64)."""
+    n, eps, nu, lmin = 5000, 1 / 256, 0.01, 3
+    x, v, m, st, ctx = make(n, 30, eps, "fp64", lmin)
+    ctx.nb_init(nu)
+    ref = oracle.BlockIntegrator(x, v, m, eps=eps, nu=nu, lmin=lmin)
+    for s in range(25):
+        ctx.nb_step(nu, 1, use_graph=(s % 2 == 1))
+        t, blk = ref.step()
+        c = ctx.nb_read_control()
+        idx_addr, _ = ctx.nb_active()
+        lst = nbody.read_device_int32(idx_addr, c.n_act)
+        assert c.t_cur == t and c.n_act == len(blk), (s, c.t_cur, t, c.n_act, len(blk))
+        assert np.array_equal(np.sort(lst), np.sort(np.asarray(blk))), s
+    g = st.numpy()
+    assert np.array_equal(g["tick"], ref.tick) and np.array_equal(g["level"], ref.level)
+    assert np.max(np.abs(g["x"] - ref.x)) < 1e-11
+    ctx.close()
+
+
 def test_fused_steps_mix_with_separate_calls():
     """Separate calls between fused steps (a block corrected by nb_correct and not yet levelled)
     are picked up by the next nb_step; the run follows the oracle step for step."""
