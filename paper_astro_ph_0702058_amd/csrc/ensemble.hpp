@@ -8,7 +8,8 @@
 //              cluster; i- and j-particles are predicted to the cluster's block time as they
 //              are loaded (Sec. 2 predictor, FP64); small blocks share each i among several
 //              lanes (wave-shuffle reduction); partial sums go to the cluster's partial planes
-//   ens_local  one workgroup of 1024 per cluster: fixed-order sum of the partials, the
+//   ens_local  one workgroup of 1024 per cluster (largest clusters first): fixed-order sum of
+//              the partials, the
 //              corrector and the new step of each block particle (Eq. timestep), then the
 //              cluster's next block (smallest t_i + dt_i)
 // No workgroup ever waits for another: the cluster-local work needs only its own workgroup's
@@ -29,6 +30,7 @@ struct EnsView {
     const int32_t *off;         // C + 1 particle offsets
     const int32_t *K;           // j-ranges per i-block of each cluster
     const int32_t *tpi;         // whole tiles per j-range
+    const int32_t *order;       // clusters by decreasing size: ens_local's workgroup order
     const int64_t *part_off;    // start of each cluster's partial planes
     const int32_t *prow;        // rows of one partial plane of each cluster
     const double *eps2;         // softening^2 of each cluster (> 0)
@@ -325,8 +327,10 @@ __global__ void __launch_bounds__(WGL) ens_local(EnsView e, StateRW s, double et
     __shared__ int32_t wsum[WGL / 64];
     __shared__ int64_t tn_lds[TN_CACHE];
     __shared__ typename M::Smem sm[WGL / TJ];
-    const int32_t c = blockIdx.x;
-    if (c >= e.C) return;
+    if ((int32_t)blockIdx.x >= e.C) return;
+    // largest clusters first: the first wave of workgroups takes the longest ones and the
+    // later, short ones fill in behind them
+    const int32_t c = e.order[blockIdx.x];
     const int32_t lo = e.off[c], hi = e.off[c + 1];
     EnsCluster *cl = e.cl + c;
     if (phase == 0) {

@@ -130,10 +130,11 @@ struct nb_ens {
     hipStream_t stream = nullptr, cap_stream = nullptr;
     nb_state st{};
     bool bound = false, initialised = false;
-    std::vector<int32_t> off_h, tpi_h, K_h, prow_h;
+    std::vector<int32_t> off_h, tpi_h, K_h, prow_h, order_h;
     std::vector<int64_t> part_off_h;
     std::vector<double> eps2_h;
     int32_t *off = nullptr, *K = nullptr, *tpi = nullptr, *prow = nullptr, *active = nullptr;
+    int32_t *order = nullptr;
     int32_t *flags = nullptr;
     int64_t *part_off = nullptr;
     double *eps2 = nullptr, *partial = nullptr, *crit = nullptr, *ek = nullptr, *ep = nullptr;
@@ -1184,7 +1185,8 @@ namespace {
 
 EnsView ens_view(const nb_ens *e, int64_t t_end) {
     EnsView v;
-    v.C = e->C; v.off = e->off; v.K = e->K; v.tpi = e->tpi; v.part_off = e->part_off;
+    v.C = e->C; v.off = e->off; v.K = e->K; v.tpi = e->tpi; v.order = e->order;
+    v.part_off = e->part_off;
     v.prow = e->prow; v.eps2 = e->eps2; v.cl = e->cl; v.active = e->active;
     v.partial = e->partial; v.crit = e->crit; v.flags = e->flags;
     v.lmin = e->lmin; v.lmax = e->lmax; v.tick_len = std::ldexp(1.0, -e->lmax); v.t_end = t_end;
@@ -1304,6 +1306,12 @@ void ens_plan(nb_ens *e, int32_t n_clusters, const int32_t *offsets, int32_t pre
         e->prow_h[c] = n_c;
         e->part_off_h[c + 1] = e->part_off_h[c] + (int64_t)((n_c + TJ - 1) / TJ) * 7 * n_c;
     }
+    // the cluster-local kernel's workgroup order: decreasing size (ties by index)
+    e->order_h.resize(n_clusters);
+    for (int32_t c = 0; c < n_clusters; ++c) e->order_h[c] = c;
+    std::stable_sort(e->order_h.begin(), e->order_h.end(), [&](int32_t a, int32_t b) {
+        return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
+    });
     e->unroll = 2;
     ens_derive(e);
 }
@@ -1318,6 +1326,7 @@ size_t ens_layout(nb_ens *e, char *base) {
     e->K = k.take<int32_t>(C);
     e->tpi = k.take<int32_t>(C);
     e->prow = k.take<int32_t>(C);
+    e->order = k.take<int32_t>(C);
     e->part_off = k.take<int64_t>(C + 1);
     e->eps2 = k.take<double>(C);
     e->cl = k.take<EnsCluster>(C);
@@ -1392,6 +1401,7 @@ nb_status nb_ens_bind_scratch(nb_ens *e, void *scratch, size_t bytes) {
     const size_t C = (size_t)e->C;
     EHIP_OK(e, hipMemcpyAsync(e->off, e->off_h.data(), (C + 1) * sizeof(int32_t), hipMemcpyHostToDevice, e->stream));
     EHIP_OK(e, hipMemcpyAsync(e->prow, e->prow_h.data(), C * sizeof(int32_t), hipMemcpyHostToDevice, e->stream));
+    EHIP_OK(e, hipMemcpyAsync(e->order, e->order_h.data(), C * sizeof(int32_t), hipMemcpyHostToDevice, e->stream));
     EHIP_OK(e, hipMemcpyAsync(e->part_off, e->part_off_h.data(), (C + 1) * sizeof(int64_t), hipMemcpyHostToDevice, e->stream));
     EHIP_OK(e, hipMemcpyAsync(e->eps2, e->eps2_h.data(), C * sizeof(double), hipMemcpyHostToDevice, e->stream));
     EHIP_OK(e, hipMemcpyAsync(e->K, e->K_h.data(), C * sizeof(int32_t), hipMemcpyHostToDevice, e->stream));
