@@ -344,9 +344,10 @@ nb_status nb_ens_set_stream(nb_ens *ens, void *hip_stream);
 nb_status nb_ens_bind(nb_ens *ens, const nb_state *state);
 
 /* Force work layout (the autotuner's knobs): whole 256-particle j-tiles per work item for
- * each cluster (HOST array of n_clusters values >= 1, or NULL to keep), i-particles per
- * work-item (must be 1: small blocks instead share each i among several lanes) and j-loop
- * unroll (1 or 2).  Synchronising. */
+ * each cluster (HOST array of n_clusters values >= 1, or NULL to keep; default: the fewest
+ * that leave each cluster at most 4 j-ranges, so its own workgroup sums at most 4 partial
+ * planes per block particle), i-particles per work-item (must be 1: block particles instead
+ * share lanes, nb_ens_set_split) and j-loop unroll (1 or 2, default 2).  Synchronising. */
 nb_status nb_ens_set_layout(nb_ens *ens, const int32_t *tiles_per_item, int32_t ipl,
                             int32_t unroll);
 
@@ -359,6 +360,13 @@ nb_status nb_ens_set_layout(nb_ens *ens, const int32_t *tiles_per_item, int32_t 
  * (every block through the GPU-wide force), 64, 2^21.  Synchronising. */
 nb_status nb_ens_set_local(nb_ens *ens, int64_t local_limit, int32_t local_steps,
                            int64_t local_work);
+
+/* Force work-item size (an autotuner knob): every block particle of a force item is shared by
+ * at least smin lanes (a power of two in [1, 64]; default 8), each taking every smin-th j of a
+ * tile, so an item holds at most 256 / smin block particles.  Smaller items balance a global
+ * step whose clusters' blocks differ in size by orders of magnitude; the sums combine the
+ * lanes' parts by wave shuffles in a fixed order.  NB_EINVAL otherwise.  Synchronising. */
+nb_status nb_ens_set_split(nb_ens *ens, int32_t smin);
 
 /* Sec. 2 start of run for every cluster: full force at time 0, initial steps from
  * Eq. initTimestep with this eta, times 0. */

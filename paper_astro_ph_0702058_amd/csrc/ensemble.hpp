@@ -48,9 +48,18 @@ struct EnsView {
     int64_t local_limit;
     int32_t local_steps;
     int64_t local_work;
+    int32_t smin;               // fewest lanes per block particle in a force item (power of 2)
 };
 
+// Lanes per block particle of a cluster's force items: the lane split of its block, at least
+// smin (smaller items, for balance across the GPU).
+__host__ __device__ __forceinline__ int32_t ens_split(int32_t n_act, int32_t smin) {
+    const int32_t S = lane_split(n_act, true);
+    return S < smin ? smin : S;
+}
+
 constexpr int WGL = 1024;  // workgroup of the cluster-local kernel
+constexpr int ENS_KMAX = 4; // j-ranges per cluster of the default force layout
 
 // A cluster's selected block is forced by its own workgroup (and never by ens_force) when it
 // holds at most WGL particles and at most `limit` interactions.
@@ -605,9 +614,12 @@ __global__ void __launch_bounds__(WGL) run_resident(StateRW g, int32_t *active, 
     if (clamp) ctl->flag_dtmin = 1;
 }
 
-// Exclusive prefix over clusters of their force work items (ens_item: i-blocks of WG / S block
-// particles times K j-ranges), start[0..C], formed by one workgroup of BS in its LDS: each work-item takes a contiguous run of clusters, the runs'
-// totals are scanned across the wave (shuffles) and across waves (wsum).
+// Exclusive prefix of the clusters' force work items (ens_item: i-blocks of WG / S block
+// particles times K j-ranges) in the size order (largest cluster first, so the largest items
+// go to the first wave of workgroups and the small ones fill in behind), start[0..C] indexed by
+// place in that order, formed by one workgroup of BS in its LDS: each work-item takes a
+// contiguous run of places, the runs' totals are scanned across the wave (shuffles) and across
+// waves (wsum).
 template <int BS>
 __device__ void ens_item_prefix(const EnsView &e, int32_t *start, int32_t *wsum) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -615,12 +627,13 @@ __device__ void ens_item_prefix(const EnsView &e, int32_t *start, int32_t *wsum)
     const int32_t c0 = (int32_t)threadIdx.x * per;
     const int32_t c1 = c0 + per < e.C ? c0 + per : e.C;
     int32_t own = 0;
-    for (int32_t c = c0; c < c1; ++c) {
+    for (int32_t k = c0; k < c1; ++k) {  // k: place in the size order, cluster e.order[k]
+        const int32_t c = e.order[k];
         const int32_t na = e.cl[c].n_act;
-        const int32_t ibc = WG / lane_split(na, true);  // i-block of an item (ens_item), any BS
+        const int32_t ibc = WG / ens_split(na, e.smin);  // i-block of an item (ens_item), any BS
         const bool global = na > 0 && !ens_local_block(na, e.off[c + 1] - e.off[c], e.local_limit);
         const int32_t items = global ? ((na + ibc - 1) / ibc) * e.K[c] : 0;
-        start[c] = items;
+        start[k] = items;
         own += items;
     }
     int32_t inc = own;  // inclusive scan over the wave
@@ -632,16 +645,16 @@ __device__ void ens_item_prefix(const EnsView &e, int32_t *start, int32_t *wsum)
     __syncthreads();
     int32_t run = inc - own;
     for (int w = 0; w < wave; ++w) run += wsum[w];
-    for (int32_t c = c0; c < c1; ++c) {
-        const int32_t items = start[c];
-        start[c] = run;
+    for (int32_t k = c0; k < c1; ++k) {
+        const int32_t items = start[k];
+        start[k] = run;
         run += items;
     }
     if (threadIdx.x == BS - 1) start[e.C] = run;
     __syncthreads();
 }
 
-// Cluster of item w: the last c with start[c] <= w.
+// Place (in the size order) of the cluster of item w: the last k with start[k] <= w.
 __device__ __forceinline__ int32_t ens_item_cluster(const int32_t *start, int32_t C, int32_t w) {
     int32_t lo = 0, hi = C - 1;
     while (lo < hi) {
@@ -663,7 +676,7 @@ __device__ void ens_item(const EnsView &e, const StateRW &st, int32_t c, int32_t
     const int32_t p0 = e.off[c], n_c = e.off[c + 1] - p0;
     const int32_t n_act = e.cl[c].n_act;
     const int64_t tb = e.cl[c].t_next;
-    const int32_t Sl = lane_split(n_act, true);
+    const int32_t Sl = ens_split(n_act, e.smin);
     const int32_t slice = (int32_t)threadIdx.x % Sl;
     const int32_t ntiles = (n_c + TJ - 1) / TJ;
     const auto eps2 = eps_as<M>(e.eps2[c]);
@@ -722,8 +735,8 @@ __global__ void __launch_bounds__(WG) ens_force(EnsView e, StateRW st) {
     ens_item_prefix<WG>(e, start, wsum);
     const int32_t total = start[e.C];
     for (int32_t w = blockIdx.x; w < total; w += gridDim.x) {
-        const int32_t c = ens_item_cluster(start, e.C, w);
-        ens_item<M, UNR>(e, st, c, w - start[c], sm);
+        const int32_t k = ens_item_cluster(start, e.C, w);
+        ens_item<M, UNR>(e, st, e.order[k], w - start[k], sm);
     }
 }
 

@@ -145,6 +145,7 @@ struct nb_ens {
     // blocks the clusters' own workgroups advance (see ens_local_block)
     int64_t local_limit = 0, local_work = 1 << 21;
     int32_t local_steps = 64;
+    int32_t smin = 8;  // fewest lanes per block particle in a force item
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     double g_eta = -1.0;
@@ -1191,6 +1192,7 @@ EnsView ens_view(const nb_ens *e, int64_t t_end) {
     v.partial = e->partial; v.crit = e->crit; v.flags = e->flags;
     v.lmin = e->lmin; v.lmax = e->lmax; v.tick_len = std::ldexp(1.0, -e->lmax); v.t_end = t_end;
     v.local_limit = e->local_limit; v.local_steps = e->local_steps; v.local_work = e->local_work;
+    v.smin = e->smin;
     return v;
 }
 
@@ -1207,7 +1209,8 @@ void ens_derive(nb_ens *e) {
         const int32_t n_c = e->off_h[c + 1] - e->off_h[c];
         const int32_t ntiles = (n_c + TJ - 1) / TJ;
         e->K_h[c] = (ntiles + e->tpi_h[c] - 1) / e->tpi_h[c];
-        items += (int64_t)((n_c + WG - 1) / WG) * e->K_h[c];
+        const int32_t ib = WG / e->smin;  // largest i-block of an item
+        items += (int64_t)((n_c + ib - 1) / ib) * e->K_h[c];
     }
     e->grid_force = (int32_t)std::max<int64_t>(1, std::min<int64_t>(items, (int64_t)e->num_cu * 8));
 }
@@ -1297,7 +1300,13 @@ bool ens_args_ok(int32_t n_clusters, const int32_t *offsets, int32_t precision) 
 void ens_plan(nb_ens *e, int32_t n_clusters, const int32_t *offsets, int32_t precision) {
     e->C = n_clusters; e->ntot = offsets[n_clusters]; e->prec = precision;
     e->off_h.assign(offsets, offsets + n_clusters + 1);
-    e->tpi_h.assign(n_clusters, 1);
+    // default layout: the fewest whole tiles per item that leave each cluster at most
+    // ENS_KMAX j-ranges (few partial planes for the cluster's own workgroup to sum)
+    e->tpi_h.resize(n_clusters);
+    for (int32_t c = 0; c < n_clusters; ++c) {
+        const int32_t ntiles = (offsets[c + 1] - offsets[c] + TJ - 1) / TJ;
+        e->tpi_h[c] = std::max(1, (ntiles + ENS_KMAX - 1) / ENS_KMAX);
+    }
     e->prow_h.resize(n_clusters);
     e->part_off_h.resize(n_clusters + 1);
     e->part_off_h[0] = 0;
@@ -1455,6 +1464,18 @@ nb_status nb_ens_set_layout(nb_ens *e, const int32_t *tiles_per_item, int32_t ip
     ens_derive(e);
     ens_drop_graph(e);
     return ens_upload_tables(e);
+}
+
+nb_status nb_ens_set_split(nb_ens *e, int32_t smin) {
+    if (!e) return NB_EINVAL;
+    if (smin < 1 || smin > 64 || (smin & (smin - 1)) != 0)
+        return fail(e, NB_EINVAL, "nb_ens_set_split: smin must be a power of two in [1, 64]");
+    EHIP_OK(e, hipSetDevice(e->device));
+    EHIP_OK(e, hipStreamSynchronize(e->stream));
+    e->smin = smin;
+    ens_derive(e);
+    ens_drop_graph(e);
+    return NB_OK;
 }
 
 nb_status nb_ens_set_local(nb_ens *e, int64_t local_limit, int32_t local_steps,

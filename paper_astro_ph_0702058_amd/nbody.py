@@ -53,7 +53,7 @@ EXPORTS = ["nb_create", "nb_destroy", "nb_set_stream", "nb_bind", "nb_init",
            "nb_ens_last_error", "nb_shared_step", "nb_force_vjp", "nb_step_vjp",
            "nb_scratch_bytes", "nb_bind_scratch", "nb_ens_scratch_bytes", "nb_ens_bind_scratch",
            "nb_ens_set_local", "nb_fma_rate", "nb_force_noalloc",
-           "nb_set_resident"]
+           "nb_set_resident", "nb_ens_set_split"]
 
 _lib = None
 
@@ -107,6 +107,7 @@ def load_library(path: str = LIB_PATH):
         "nb_bind_scratch": [P, P, ctypes.c_size_t],
         "nb_ens_bind_scratch": [P, P, ctypes.c_size_t],
         "nb_ens_set_local": [P, I64, I32, I64],
+        "nb_ens_set_split": [P, I32],
         "nb_fma_rate": [P, ctypes.POINTER(D)],
         "nb_force_noalloc": [P, P, P, I32, P, P, P],
         "nb_set_resident": [P, I32],
@@ -537,6 +538,10 @@ class Ensemble:
         interactions per cluster per global step (local_limit = 0: never)."""
         self._check(self.lib.nb_ens_set_local(self.h, int(local_limit), int(local_steps),
                                               int(local_work)))
+
+    def nb_ens_set_split(self, smin):
+        """Every block particle of a force item shared by at least smin lanes (power of 2)."""
+        self._check(self.lib.nb_ens_set_split(self.h, int(smin)))
 
     def nb_ens_init(self, eta):
         self._check(self.lib.nb_ens_init(self.h, float(eta)))

@@ -57,12 +57,14 @@ def autotune(ctx, cache_path: str | None = DEFAULT_CACHE, reps: int = 2, retune:
 def ensemble_autotune(ens, state, x0, v0, eta, t_probe=0.25, steps_per_launch=32):
     """Choose the ensemble's force work layout by timing runs from the initial state to
     t_probe (default 1/4: the phase in which nearly every cluster is active and which takes
-    most of a run's time): first the j-loop unroll (all clusters one tile per item), then, for
-    each size class of clusters (N < 512, 512 <= N < 2048, N >= 2048), the whole j-tiles per
-    work item.  The winner is timed again against the library's default layout (one tile per
-    item, unroll 2) on the same probe and kept only if it is faster; the state is restored
-    from (x0, v0) before every trial and after tuning.  Returns the layout in effect with both
-    probe times and whether the search beat the default."""
+    most of a run's time): first the fewest lanes per block particle of a force item (smin,
+    which bounds an item's size), then the j-loop unroll, then, for each size class of clusters
+    (N < 512, 512 <= N < 2048, N >= 2048), the whole j-tiles per work item halved or doubled
+    from the default's.  The winner is timed again against the library's default layout (at
+    most 4 j-ranges per cluster, smin 8, unroll 2) on the same probe and kept only if it is
+    faster; the state is
+    restored from (x0, v0) before every trial and after tuning.  Returns the layout in effect
+    with both probe times and whether the search beat the default."""
     import time
     import numpy as np
     import torch
@@ -70,8 +72,9 @@ def ensemble_autotune(ens, state, x0, v0, eta, t_probe=0.25, steps_per_launch=32
     sizes = np.diff(ens.offsets)
     classes = [sizes < 512, (sizes >= 512) & (sizes < 2048), sizes >= 2048]
 
-    def trial(tpi, ipl, unroll):
+    def trial(tpi, smin, ipl, unroll):
         ens.nb_ens_set_layout(tpi, ipl, unroll)
+        ens.nb_ens_set_split(smin)
         state.x.copy_(x0); state.v.copy_(v0)
         ens.nb_ens_init(eta)
         torch.cuda.synchronize()
@@ -79,33 +82,39 @@ def ensemble_autotune(ens, state, x0, v0, eta, t_probe=0.25, steps_per_launch=32
         ens.nb_ens_run(eta, t_probe, steps_per_launch=steps_per_launch)
         return time.perf_counter() - t
 
-    default = (np.ones(ens.C, np.int32), 1, 2)
+    # the library's default: at most 4 j-ranges per cluster, 8 lanes per block particle
+    ntiles = (sizes + 255) // 256
+    default = (np.maximum(1, (ntiles + 3) // 4).astype(np.int32), 8, 1, 2)
     trial(*default)  # warm: graphs and caches of the default layout
-    tpi = np.ones(ens.C, np.int32)
-    combos = [(1, 2), (1, 1)]
-    timed = {c: trial(tpi, *c) for c in combos}
-    ipl, unroll = min(timed, key=timed.get)
-    best = timed[(ipl, unroll)]
-    for mask in classes:
+    tpi = default[0].copy()
+    timed = {sm: trial(tpi, sm, 1, 2) for sm in (2, 4, 8, 16)}
+    smin = min(timed, key=timed.get)
+    best = timed[smin]
+    t1 = trial(tpi, smin, 1, 1)
+    unroll = 1 if t1 < best else 2
+    best = min(best, t1)
+    for mask in classes:  # per size class: the default's tiles per item halved or doubled
         if not mask.any():
             continue
-        choice = 1
-        for cand in (2, 4, 8):
+        for scale in (0.5, 2.0):
             t2 = tpi.copy()
-            t2[mask] = cand
-            t = trial(t2, ipl, unroll)
+            t2[mask] = np.maximum(1, np.rint(tpi[mask] * scale)).astype(np.int32)
+            if np.array_equal(t2, tpi):
+                continue
+            t = trial(t2, smin, 1, unroll)
             if t < best:
-                best, choice = t, cand
-        tpi[mask] = choice
+                best, tpi = t, t2
     # the search's winner against the default, each timed once more, in that order
-    t_best = trial(tpi, ipl, unroll)
+    t_best = trial(tpi, smin, 1, unroll)
     t_default = trial(*default)
     beats = t_best < t_default
     if not beats:
-        tpi, ipl, unroll = default
-    ens.nb_ens_set_layout(tpi, ipl, unroll)
+        tpi, smin, _, unroll = default
+    ens.nb_ens_set_layout(tpi, 1, unroll)
+    ens.nb_ens_set_split(smin)
     state.x.copy_(x0); state.v.copy_(v0)
-    return {"ipl": int(ipl), "unroll": int(unroll),
-            "tiles_per_item_by_class": [int(tpi[m][0]) if m.any() else None for m in classes],
+    return {"smin": int(smin), "ipl": 1, "unroll": int(unroll),
+            "tiles_per_item_by_class": [sorted(set(int(t) for t in tpi[m])) if m.any() else None
+                                        for m in classes],
             "probe_t_end": t_probe, "probe_seconds_chosen": t_best,
             "probe_seconds_default": t_default, "beats_default": bool(beats)}

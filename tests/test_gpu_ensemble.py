@@ -21,7 +21,7 @@ def build(sizes, seed0=100):
 
 
 def run_ensemble(sizes, eps, eta, t_end, prec, lmin=3, layout=None, graph=True, spl=8,
-                 local=None):
+                 local=None, split=None):
     xs, vs, ms = build(sizes)
     st = nbody.DeviceState(np.concatenate(xs), np.concatenate(vs), np.concatenate(ms))
     ens = nbody.Ensemble(sizes, eps, lmin=lmin, lmax=LMAX, precision=prec)
@@ -30,6 +30,8 @@ def run_ensemble(sizes, eps, eta, t_end, prec, lmin=3, layout=None, graph=True, 
         ens.nb_ens_set_layout(**layout)
     if local:
         ens.nb_ens_set_local(**local)
+    if split:
+        ens.nb_ens_set_split(split)
     ens.nb_ens_init(eta)
     e0 = ens.nb_ens_energy()
     ens.nb_ens_run(eta, t_end, steps_per_launch=spl, max_steps=200000, use_graph=graph)
@@ -80,13 +82,19 @@ def test_ensemble_whole_tiles_and_tiny_clusters():
 
 
 def test_ensemble_layouts_agree():
-    """Different work layouts (tiles per item, unroll) only reorder sums."""
+    """Different work layouts (tiles per item, unroll, lanes per block particle) only reorder
+    sums: FP64 runs take the same block steps with positions to 1e-12."""
     sizes = [70, 600, 1300]
     eps = [1.0 / n for n in sizes]
     outs = []
-    for layout in (dict(tiles_per_item=1, ipl=1, unroll=2), dict(tiles_per_item=4, ipl=1, unroll=1),
-                   dict(tiles_per_item=[1, 2, 3], ipl=1, unroll=2)):
-        *_, g, ctl, e0, e1 = run_ensemble(sizes, eps, 0.02, 1 / 32, "fp64", layout=layout)
+    for layout, split in ((dict(tiles_per_item=1, ipl=1, unroll=2), None),
+                          (dict(tiles_per_item=4, ipl=1, unroll=1), None),
+                          (dict(tiles_per_item=[1, 2, 3], ipl=1, unroll=2), None),
+                          (dict(tiles_per_item=1, ipl=1, unroll=2), 1),
+                          (dict(tiles_per_item=2, ipl=1, unroll=2), 16),
+                          (dict(tiles_per_item=1, ipl=1, unroll=1), 64)):
+        *_, g, ctl, e0, e1 = run_ensemble(sizes, eps, 0.02, 1 / 32, "fp64", layout=layout,
+                                          split=split)
         outs.append((g, [c.n_steps for c in ctl]))
     for g, steps in outs[1:]:
         assert steps == outs[0][1]
