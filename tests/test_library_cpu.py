@@ -164,3 +164,24 @@ def test_scratch_bytes(lib):
     bad = np.array([0, 100, 100, 200], np.int32)
     assert lib.nb_ens_scratch_bytes(3, bad.ctypes.data_as(ctypes.c_void_p), 0) == 0
     assert lib.nb_ens_scratch_bytes(3, off.ctypes.data_as(ctypes.c_void_p), 3) == 0
+
+
+def test_bench_oracle_reference_cache(tmp_path):
+    """The benchmark's cache of oracle reference rows: a stored reference comes back bitwise for
+    the same input and rows, and any change of input, softening or rows misses."""
+    import bench
+    rng = np.random.default_rng(3)
+    x, v = rng.normal(size=(50, 3)), rng.normal(size=(50, 3))
+    m = np.full(50, 1 / 50)
+    idx = np.arange(0, 50, 7, dtype=np.int64)
+    ref = (rng.normal(size=(idx.size, 3)), rng.normal(size=(idx.size, 3)), rng.normal(size=idx.size))
+    d = str(tmp_path)
+    assert bench.load_oracle_reference(d, x, v, m, 0.01, idx) is None
+    bench.save_oracle_reference(d, x, v, m, 0.01, idx, ref)
+    got = bench.load_oracle_reference(d, x, v, m, 0.01, idx)
+    assert all(np.array_equal(a, b) for a, b in zip(got, ref))
+    x2 = x.copy(); x2[3, 1] += 1e-12
+    assert bench.load_oracle_reference(d, x2, v, m, 0.01, idx) is None
+    assert bench.load_oracle_reference(d, x, v, m, 0.02, idx) is None
+    assert bench.load_oracle_reference(d, x, v, m, 0.01, idx[1:]) is None
+    assert bench.load_oracle_reference("", x, v, m, 0.01, idx) is None
