@@ -26,15 +26,15 @@ class SharedRunner:
         self.ctx.nb_bind(self.state)
         self.t0 = torch.zeros(1, dtype=torch.int64, device="cuda")
 
-    def _load(self, x, v, a=None, k=None):
+    def _load(self, x, v):
         st = self.state
         st.x.copy_(x); st.v.copy_(v)
-        if a is not None:
-            st.a.copy_(a); st.k.copy_(k)
+
+    def _restore(self, snap):
+        self.state.xvak.copy_(snap)  # x, v, a, k in one copy
 
     def _snapshot(self):
-        st = self.state
-        return (st.x.clone(), st.v.clone(), st.a.clone(), st.k.clone())
+        return self.state.xvak.clone()
 
     def forward(self, x0, v0, m):
         """Run from (x0, v0, m); returns (x, v) at the end and the checkpoints."""
@@ -65,13 +65,13 @@ class SharedRunner:
                    for s in range(len(checkpoints))]
         for seg in reversed(range(len(checkpoints))):
             # recompute the states before each step of the segment
-            self._load(*checkpoints[seg])
+            self._restore(checkpoints[seg])
             states = [checkpoints[seg]]
             for _ in range(seg_len[seg] - 1):
                 self.ctx.nb_shared_step(self.dt, 1)
                 states.append(self._snapshot())
             for s in reversed(states):
-                self._load(*s)
+                self._restore(s)
                 self.ctx.nb_step_vjp(self.dt, xb, vb, ab, kb, mb)
         # the initial force a0, k0 = F(x0, v0, m)
         self._load(x0, v0)

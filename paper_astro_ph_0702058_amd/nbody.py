@@ -201,7 +201,8 @@ def check_force_args(n, acc, jerk, pot, i_idx, n_i, n_i_max):
 
 class DeviceState:
     """FP64 master state on the GPU as torch tensors, structure-of-arrays:
-    x, v, a, k: (3, n) float64; m, pot: (n,) float64; tick: (n,) int64; level: (n,) int32."""
+    x, v, a, k: (3, n) float64 (the planes of one (4, 3, n) buffer, xvak); m, pot: (n,)
+    float64; tick: (n,) int64; level: (n,) int32."""
 
     def __init__(self, x, v, m, device="cuda"):
         torch = _torch()
@@ -210,11 +211,13 @@ class DeviceState:
         self.n = x.shape[0]
         dev = torch.device(device)
         f64 = dict(dtype=torch.float64, device=dev)
-        self.x = torch.tensor(np.ascontiguousarray(x.T), **f64)
-        self.v = torch.tensor(np.ascontiguousarray(v.T), **f64)
+        # x, v, a, k are the four (3, n) planes of one buffer, so that the whole dynamical
+        # state is saved or restored by one device copy (xvak)
+        self.xvak = torch.zeros((4, 3, self.n), **f64)
+        self.x, self.v, self.a, self.k = self.xvak.unbind(0)
+        self.x.copy_(torch.from_numpy(np.ascontiguousarray(x.T)))
+        self.v.copy_(torch.from_numpy(np.ascontiguousarray(v.T)))
         self.m = torch.tensor(np.asarray(m, np.float64), **f64)
-        self.a = torch.zeros((3, self.n), **f64)
-        self.k = torch.zeros((3, self.n), **f64)
         self.pot = torch.zeros(self.n, **f64)
         self.tick = torch.zeros(self.n, dtype=torch.int64, device=dev)
         self.level = torch.zeros(self.n, dtype=torch.int32, device=dev)
