@@ -235,11 +235,29 @@ Variant default_variant(int32_t n, int prec, int num_cu, bool block) {
     // with the j-split capped at 64 ranges; block
     // steps (N = 65536 run, every block size from 1 to N) take one i per work-item, unroll 2
     // and 16 items per compute unit (more, shorter items at every block size)
-    (void)n; (void)prec;
     v.ipl = 1;
     v.unroll = 2;
     v.target = num_cu * (block ? BLOCK_ITEMS_PER_CU : FULL_ITEMS_PER_CU);
     v.kmax = block ? 1 << 16 : FULL_KMAX;  // K is also bounded by the tile count
+    if (block || (prec != NB_FP32 && prec != NB_FP32_FIXED)) return v;
+    // smaller full-force calls, the tuner's choices on MI355X (force + reduction per call):
+    // N = 4096 / 8192 unroll 4 (0.033 / 0.068 ms against 0.034 / 0.072); 16384 two i per
+    // work-item, unroll 1 (0.198 against 0.222-0.240 ms); 32768 the same at 128 items per CU
+    // (0.69 against 0.81 ms); 65536 16 items per CU, the j-split bounded by the tiles only
+    // (2.51-2.57 against 2.81-2.83 ms); 131072 64 items per CU (9.77 against 10.73 ms); from
+    // 262144 the defaults above
+    if (n < 12288) {
+        v.unroll = prec == NB_FP32 ? 4 : 2;
+    } else if (n < 49152) {
+        v.ipl = 2;
+        v.unroll = 1;
+        if (n >= 24576) v.target = num_cu * 128;
+    } else if (n < 98304) {
+        v.target = num_cu * 16;
+        v.kmax = 1 << 16;
+    } else if (n < 196608) {
+        v.target = num_cu * 64;
+    }
     return v;
 }
 
