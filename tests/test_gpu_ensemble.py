@@ -101,6 +101,21 @@ def test_ensemble_layouts_agree():
         assert np.max(np.abs(g["x"] - outs[0][0]["x"])) < 1e-12
 
 
+def test_ensemble_split_is_a_power_of_two():
+    """nb_ens_set_split takes powers of two from 1 to 64 and refuses anything else."""
+    sizes = [70, 300]
+    xs, vs, ms = build(sizes)
+    st = nbody.DeviceState(np.concatenate(xs), np.concatenate(vs), np.concatenate(ms))
+    ens = nbody.Ensemble(sizes, [1 / 70, 1 / 300], lmin=3, lmax=LMAX, precision="fp32")
+    ens.nb_ens_bind(st)
+    for ok in (1, 2, 8, 64):
+        ens.nb_ens_set_split(ok)
+    for bad in (0, 3, 12, 128, -4):
+        with pytest.raises(RuntimeError, match="smin"):
+            ens.nb_ens_set_split(bad)
+    ens.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_ensemble_local_steps_agree(prec):
     """Which blocks a cluster's own workgroup advances only changes summation orders: no local
