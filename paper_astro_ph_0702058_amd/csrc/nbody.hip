@@ -240,22 +240,15 @@ Variant default_variant(int32_t n, int prec, int num_cu, bool block) {
     v.target = num_cu * (block ? BLOCK_ITEMS_PER_CU : FULL_ITEMS_PER_CU);
     v.kmax = block ? 1 << 16 : FULL_KMAX;  // K is also bounded by the tile count
     if (block || (prec != NB_FP32 && prec != NB_FP32_FIXED)) return v;
-    // smaller full-force calls, the tuner's choices on MI355X (force + reduction per call):
-    // N = 4096 / 8192 unroll 4 (0.033 / 0.068 ms against 0.034 / 0.072); 16384 two i per
-    // work-item, unroll 1 (0.198 against 0.222-0.240 ms); 32768 the same at 128 items per CU
-    // (0.69 against 0.81 ms); 65536 16 items per CU, the j-split bounded by the tiles only
-    // (2.51-2.57 against 2.81-2.83 ms); 131072 64 items per CU (9.77 against 10.73 ms); from
-    // 262144 the defaults above
-    if (n < 12288) {
-        v.unroll = prec == NB_FP32 ? 4 : 2;
-    } else if (n < 49152) {
-        v.ipl = 2;
-        v.unroll = 1;
-        if (n >= 24576) v.target = num_cu * 128;
-    } else if (n < 98304) {
+    // full-force calls of 2^16 and 2^17 particles (force + reduction per call, warm clocks, the
+    // two variants timed alternately on one MI355X): N = 65536 at 16 items per CU with the
+    // j-split bounded by the tiles only, 2.565 against 2.726 ms; 131072 at 64 items per CU,
+    // 10.07 against 11.20 ms.  From 4096 to 32768 the tuner's other choices were within 3 % of
+    // the defaults above once the clocks were warm, and from 262144 the defaults win.
+    if (n >= 49152 && n < 98304) {
         v.target = num_cu * 16;
         v.kmax = 1 << 16;
-    } else if (n < 196608) {
+    } else if (n >= 98304 && n < 196608) {
         v.target = num_cu * 64;
     }
     return v;
@@ -1083,6 +1076,26 @@ nb_status nb_tune(nb_ctx *c, int32_t which, int32_t n_i, int32_t reps, nb_varian
     HIP_OK(c, hipEventCreate(&e1));
     nb_variant bestv = which == 0 ? c->var_full : c->var_block;
     double bms = 1e300;
+    // warm the clocks first (at least 100 ms of the current variant, at most 2000 launches):
+    // timed from a cold start, the first variants of the sweep would run at a lower clock
+    {
+        float warm = 0.f;
+        for (int i = 0; i < 2000 && warm < 100.f; ++i) {
+            HIP_OK(c, hipEventRecord(e0, s));
+            if (which == 0)
+                r = enqueue_force(c, bestv, 0, nullptr, nullptr, n_i, c->acc1, c->jerk1, c->pot1,
+                                  c->n, s);
+            else
+                r = enqueue_force(c, bestv, 1, nullptr, c->tune_n, c->n, c->acc1, c->jerk1,
+                                  c->pot1, c->n, s);
+            if (r != NB_OK) { c->profile = was_profiling; return r; }
+            HIP_OK(c, hipEventRecord(e1, s));
+            HIP_OK(c, hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_OK(c, hipEventElapsedTime(&ms, e0, e1));
+            warm += ms;
+        }
+    }
     const int ipls[] = {1, 2, 4}, unrs[] = {1, 2, 4};
     const int32_t targets[] = {c->num_cu * 4, c->num_cu * 8, c->num_cu * 16, c->num_cu * 32,
                                c->num_cu * 64, c->num_cu * 128, c->num_cu * FULL_ITEMS_PER_CU};
