@@ -1450,59 +1450,11 @@ __global__ void __launch_bounds__(WG) fused_select_predict(SchedView v, StateVie
     }
 }
 
-// Corrector of the block with the new level of each member (Eq. timestep, power-of-two
-// rules) assigned at once, and the level changes posted to the histogram.
-__global__ void __launch_bounds__(WG) fused_correct_level(StateRW s, const int32_t *active,
-                                                          const double *acc, const double *jerk,
-                                                          const double *pot, int32_t ld,
-                                                          double eta, int32_t lmin, int32_t lmax,
-                                                          DevControl *ctl) {
-    __shared__ int32_t dh[NLEV];
-    __shared__ int32_t any;
-    if (threadIdx.x < NLEV) dh[threadIdx.x] = 0;
-    if (threadIdx.x == 0) any = 0;
-    __syncthreads();
-    const int32_t n_act = ctl->n_act;
-    const int64_t t_next = ctl->t_next;
-    for (int32_t q = blockIdx.x * WG + threadIdx.x; q < n_act; q += gridDim.x * WG) {
-        const int32_t i = active[q];
-        const double dt = (double)(t_next - s.tick[i]) * s.tick_len;
-        double a1[3], k1[3], num, den;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            a1[c] = acc[c * (int64_t)ld + q];
-            k1[c] = jerk[c * (int64_t)ld + q];
-        }
-        if (!correct_particle(s, i, dt, a1, k1, pot[q], t_next, nullptr, &num, &den))
-            ctl->flag_nonfinite = 1;
-        const double dtn = den > 0.0 ? __builtin_sqrt(eta * num / den) : __builtin_inf();
-        if (__builtin_isnan(dtn)) ctl->flag_nonfinite = 1;
-        else if (dtn < s.tick_len) ctl->flag_dtmin = 1;
-        const int32_t l0 = s.level[i];
-        const int32_t l1 = next_level(dtn, l0, t_next, lmin, lmax);
-        if (l1 != l0) {
-            s.level[i] = l1;
-            atomicAdd(&dh[l0 & (NLEV - 1)], -1);
-            atomicAdd(&dh[l1 & (NLEV - 1)], 1);
-            any = 1;
-        }
-    }
-    __syncthreads();
-    if (any && threadIdx.x < NLEV && dh[threadIdx.x] != 0)
-        atomicAdd(&ctl->hist[threadIdx.x], dh[threadIdx.x]);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && n_act > 0) {  // nothing in this launch reads these
-        ctl->t_cur = t_next;
-        ctl->n_steps += 1;
-        ctl->n_active_sum += n_act;
-        ctl->n_pending = 0;
-    }
-}
-
 // The block step's second pass and corrector in one launch: for each block row the
 // fixed-order sum of its K partial planes, exactly as force_reduce forms it (wave w of RW adds
 // the planes k = w mod RW into four running sums, the waves' totals added in wave order), then
-// the corrector, the new level and the histogram update of the block particle, as
-// fused_correct_level does them.  A unit is RC_ROWS consecutive block rows: lane c * RC_ROWS + r
+// the corrector (Sec. 2) with the block particle's new level assigned at once (Eq. timestep,
+// power-of-two rules) and the level change posted to the per-level histogram.  A unit is RC_ROWS consecutive block rows: lane c * RC_ROWS + r
 // of every wave takes sum c of row r; wave 0 gathers the 7 sums of row r into lane r, which
 // corrects it.  Units are dealt to the 8 XCDs in contiguous runs, so the halves of a 128-byte
 // line of a partial plane are read on one XCD.  With K = 1 the force wrote the sums to
