@@ -278,8 +278,8 @@ def bench_run(args, emit=True):
                 "note": "committed FP64 oracle run of the same initial conditions"}
     if not args.no_cpu_baseline:
         import oracle
+        t_a = time.perf_counter()  # the oracle's init (the N^2 force) is part of the sample
         it = oracle.BlockIntegrator(x0, v0, m, eps=eps, nu=nu, lmin=lmin)
-        t_a = time.perf_counter()
         while time.perf_counter() - t_a < args.cpu_seconds and it.time < t_end:
             it.step()
         el = time.perf_counter() - t_a
@@ -887,7 +887,12 @@ def other_configs(args):
 
     sub.precision, sub.variants = "fp32", "none"
     sub.run = "n1024_t0.125"
-    out["n1024_t0.125"] = run_summary(bench_run(sub, emit=False))
+    sub.no_cpu_baseline = False  # the oracle runs this whole workload in well under a second
+    r = bench_run(sub, emit=False)
+    out["n1024_t0.125"] = run_summary(r)
+    if "cpu_baseline" in r:
+        out["n1024_t0.125"]["cpu_oracle_end_to_end"] = r["cpu_baseline"]
+    sub.no_cpu_baseline = True
     sub.run, sub.variants = "n65536_t1", "ds"
     out["n65536_t1"] = run_summary(bench_run(sub, emit=False))
     sub.variants, sub.clusters, sub.t_end, sub.tune = "none", 512, 1.0, False
