@@ -45,6 +45,7 @@ def run_ensemble(sizes, eps, eta, t_end, prec, lmin=3, layout=None, graph=True, 
 def check_against_oracle_runs(sizes, t_end, prec="fp64"):
     """eps = 1/N_c, eta = 0.02: every cluster follows its own oracle run step for step
     (levels, ticks, positions, energies)."""
+    assert float(t_end * 8).is_integer(), "the oracle's energy needs synchronised particles"
     eps = [1.0 / n for n in sizes]
     xs, vs, ms, g, ctl, e0, e1 = run_ensemble(sizes, eps, 0.02, t_end, prec)
     off = np.concatenate([[0], np.cumsum(sizes)])
@@ -72,6 +73,14 @@ def test_ensemble_double_single_matches_independent_oracle_runs():
     """The double-single interaction (forces to about 1e-14 of the FP64 oracle's) keeps every
     cluster on its oracle run step for step as well, to t = 1/8."""
     check_against_oracle_runs([64, 257, 700, 1000], 0.125, "ds")
+
+
+def test_ensemble_cluster_beyond_the_selection_cache():
+    """A cluster larger than the 4096 particles whose t_i + dt_i the cluster-local selection
+    keeps in LDS (it then reads them again for the compaction), beside a small one, to t = 1/8
+    (every particle synchronised, where the oracle's energy applies): both follow their oracle
+    runs step for step."""
+    check_against_oracle_runs([5000, 64], 1 / 8)
 
 
 def test_ensemble_whole_tiles_and_tiny_clusters():
