@@ -100,7 +100,7 @@ def bench_ensemble(args, emit=True):
     def step():
         st.x.copy_(x0); st.v.copy_(v0)
         ens.nb_ens_init(eta)
-        ens.nb_ens_run(eta, args.t_end, steps_per_launch=32)
+        ens.nb_ens_run(eta, args.t_end, steps_per_launch=args.ens_spl)
 
     for _ in range(args.warmup):
         step()
@@ -612,6 +612,8 @@ def main():
                     help="nb_set_resident for the run and timed workloads (default: the "
                          "library's; 0: always the launch chain)")
     ap.add_argument("--clusters", type=int, default=512)
+    ap.add_argument("--ens-spl", type=int, default=128,
+                    help="ensemble: global steps per graph replay (one host check per replay)")
     ap.add_argument("--ens-local", default="",
                     help="ensemble local blocks: LIMIT,STEPS,WORK (nb_ens_set_local; default: "
                          "the library's)")

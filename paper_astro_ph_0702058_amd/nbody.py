@@ -549,7 +549,7 @@ class Ensemble:
     def nb_ens_init(self, eta):
         self._check(self.lib.nb_ens_init(self.h, float(eta)))
 
-    def nb_ens_run(self, eta, t_end, steps_per_launch=16, max_steps=0, use_graph=True):
+    def nb_ens_run(self, eta, t_end, steps_per_launch=128, max_steps=0, use_graph=True):
         t_ticks = int(round(float(t_end) * 2.0 ** self.lmax))
         self._check(self.lib.nb_ens_run(self.h, float(eta), t_ticks, int(steps_per_launch),
                                         int(max_steps), int(bool(use_graph))))

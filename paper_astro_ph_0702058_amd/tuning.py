@@ -54,7 +54,7 @@ def autotune(ctx, cache_path: str | None = DEFAULT_CACHE, reps: int = 2, retune:
     return chosen
 
 
-def ensemble_autotune(ens, state, x0, v0, eta, t_probe=0.25, steps_per_launch=32):
+def ensemble_autotune(ens, state, x0, v0, eta, t_probe=0.25, steps_per_launch=128):
     """Choose the ensemble's force work layout by timing runs from the initial state to
     t_probe (default 1/4: the phase in which nearly every cluster is active and which takes
     most of a run's time): first the fewest lanes per block particle of a force item (smin,
