@@ -264,12 +264,15 @@ nb_status nb_step_vjp(nb_ctx *ctx, double dt, double *xbar, double *vbar, double
 
 /* Force-kernel launch variant: i-particles held per work-item (ipl), unroll of the j-loop,
  * desired number of equal work items per launch (target; the j-range is split K ways when the
- * i-blocks alone are fewer) and the largest split (kmax).  Compiled: fp32 ipl in {1, 2} with
- * unroll in {1, 2, 4}, and ipl = 4 with unroll in {1, 2}; fixed-point ipl in {1, 2} with unroll
- * in {1, 2}; ds, fp64 and all-single ipl = 1 and unroll in {1, 2}.  Any choice computes the
- * same sums up to rounding order (fixed-point: bitwise the same). */
+ * i-blocks alone are fewer), the largest split (kmax), and the fewest j-tiles of 256 in a work
+ * item whose j-records the float modes read with wave-uniform scalar loads (scalar_tiles, at
+ * least 1; shorter items stage the j-records in LDS; FP64 always stages them; in
+ * nb_set_variant, 0 keeps the current value).  Compiled: fp32 ipl in {1, 2} with unroll in
+ * {1, 2, 4}, and ipl = 4 with unroll in {1, 2}; fixed-point ipl in {1, 2} with unroll in {1, 2};
+ * ds, fp64 and all-single ipl = 1 and unroll in {1, 2}.  Any choice computes the same sums up to
+ * rounding order (fixed-point: bitwise the same); scalar_tiles never changes a result. */
 typedef struct {
-    int32_t ipl, unroll, target, kmax;
+    int32_t ipl, unroll, target, kmax, scalar_tiles;
 } nb_variant;
 
 /* The variant used for force calls on (nearly) all particles (which = 0: nb_init, nb_force
@@ -284,9 +287,9 @@ nb_status nb_get_variant(nb_ctx *ctx, int32_t which, nb_variant *out);
  * work-item, or up to 128 with two). */
 nb_status nb_set_variant(nb_ctx *ctx, int32_t which, const nb_variant *v);
 
-/* Autotuner: launch every available variant on the first n_i particles against the
- * predicted stream (which = 0: count passed from the host; which = 1: count read from device
- * memory, as block steps do), `reps` timed launches each after one untimed, keep the fastest
+/* Autotuner: launch every available variant (scalar_tiles 1, 4 or 16 in the float modes) on
+ * the first n_i particles against the predicted stream (which = 0: count passed from the host;
+ * which = 1: count read from device memory, as block steps do), `reps` timed launches each after one untimed, keep the fastest
  * for `which`, and return it in *best with its mean time in milliseconds (HOST outputs, either
  * may be NULL).  Overwrites the library's own force outputs only.  Synchronising; requires a
  * prior nb_predict(). */

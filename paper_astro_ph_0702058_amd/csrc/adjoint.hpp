@@ -107,36 +107,40 @@ template <> __device__ __forceinline__ double fma_t<double>(double a, double b, 
 //   gx += r3 (m_p Aq - m_q A) + (m_p c1q - m_q c1) d + (m_p c2q - m_q c2) u + c3 (m_p Bq - m_q B)
 //   gu += r3 (m_p Bq - m_q B) + (m_p c2q - m_q c2) d
 // and gm gains phi at (-d, -u) with q's adjoints: -(Aq.d + Bq.u) r3 - c3 Bq.d.
+// p's adjoints come in negated (nA = -A, nB = -B) and the mass sum is kept negated (ngm = -gm):
+// round-to-nearest is odd-symmetric, so every value is exactly the one the signs above give,
+// and each product with a negated operand is a plain two-operand multiply or FMA rather than
+// one carrying a negation modifier (which takes the slower three-operand encoding).
 template <class T>
 __device__ __forceinline__ void vjp_pair(T dx, T dy, T dz, T ux, T uy, T uz, T rinv, T mp, T mq,
-                                         const T A[3], const T B[3], const T Aq[3],
-                                         const T Bq[3], T gx[3], T gu[3], T &gm) {
+                                         const T nA[3], const T nB[3], const T Aq[3],
+                                         const T Bq[3], T gx[3], T gu[3], T &ngm) {
     const T r2 = rinv * rinv, r3 = rinv * r2, r5 = r3 * r2, r7 = r5 * r2;
     const T du = fma_t(dz, uz, fma_t(dy, uy, dx * ux));
     const T m3r5 = T(-3) * r5;
     const T c3 = m3r5 * du;
     const T f15 = (T(15) * r7) * du;
-    const T Ad = fma_t(A[2], dz, fma_t(A[1], dy, A[0] * dx));
-    const T Bd = fma_t(B[2], dz, fma_t(B[1], dy, B[0] * dx));
-    const T Bu = fma_t(B[2], uz, fma_t(B[1], uy, B[0] * ux));
-    const T c1 = fma_t(f15, Bd, m3r5 * (Ad + Bu));
-    const T c2 = m3r5 * Bd;
+    const T nAd = fma_t(nA[2], dz, fma_t(nA[1], dy, nA[0] * dx));  // -A.d
+    const T nBd = fma_t(nB[2], dz, fma_t(nB[1], dy, nB[0] * dx));  // -B.d
+    const T nBu = fma_t(nB[2], uz, fma_t(nB[1], uy, nB[0] * ux));  // -B.u
+    const T nc1 = fma_t(f15, nBd, m3r5 * (nAd + nBu));             // -c1
+    const T nc2 = m3r5 * nBd;                                       // -c2
     const T Adq = fma_t(Aq[2], dz, fma_t(Aq[1], dy, Aq[0] * dx));
     const T Bdq = fma_t(Bq[2], dz, fma_t(Bq[1], dy, Bq[0] * dx));
     const T Buq = fma_t(Bq[2], uz, fma_t(Bq[1], uy, Bq[0] * ux));
     const T c1q = fma_t(f15, Bdq, m3r5 * (Adq + Buq));
     const T c2q = m3r5 * Bdq;
-    const T C1 = fma_t(mp, c1q, -(mq * c1));
-    const T C2 = fma_t(mp, c2q, -(mq * c2));
+    const T C1 = fma_t(mp, c1q, mq * nc1);
+    const T C2 = fma_t(mp, c2q, mq * nc2);
     const T d[3] = {dx, dy, dz}, u[3] = {ux, uy, uz};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const T Ab = fma_t(mp, Aq[k], -(mq * A[k]));
-        const T Bb = fma_t(mp, Bq[k], -(mq * B[k]));
+        const T Ab = fma_t(mp, Aq[k], mq * nA[k]);
+        const T Bb = fma_t(mp, Bq[k], mq * nB[k]);
         gx[k] = fma_t(r3, Ab, fma_t(C1, d[k], fma_t(C2, u[k], fma_t(c3, Bb, gx[k]))));
         gu[k] = fma_t(r3, Bb, fma_t(C2, d[k], gu[k]));
     }
-    gm = fma_t(-(Adq + Buq), r3, fma_t(-c3, Bdq, gm));
+    ngm = fma_t(Adq + Buq, r3, fma_t(c3, Bdq, ngm));
 }
 
 struct VjpArgs {
@@ -157,10 +161,37 @@ struct VjpSmem {
     T A[3][TJ], B[3][TJ];
 };
 
+// One staged tile of the force VJP for one particle p (position xp, velocity vp, mass mp,
+// negated adjoints nA, nB).  SOFT (eps > 0): every separation is positive, and only a tile
+// holding p's own slot (MASK, slot rel) needs a test, taken in a copy of the loop that masks
+// that slot; without softening every pair at zero separation (the self pair among them) adds
+// nothing.  Padding slots carry zero mass and zero adjoints and add exact zeros.
+template <class T, bool SOFT, bool MASK>
+__device__ __forceinline__ void vjp_tile(const VjpSmem<T> &sm, int32_t rel, double xp, double yp,
+                                         double zp, T vxp, T vyp, T vzp, T mp, T eps2,
+                                         const T nA[3], const T nB[3], T gx[3], T gu[3],
+                                         T &ngm) {
+#pragma unroll 1
+    for (int jj = 0; jj < TJ; ++jj) {
+        const T dx = (T)(sm.x[jj] - xp), dy = (T)(sm.y[jj] - yp), dz = (T)(sm.z[jj] - zp);
+        const T ux = sm.vx[jj] - vxp, uy = sm.vy[jj] - vyp, uz = sm.vz[jj] - vzp;
+        const T s = dx * dx + dy * dy + dz * dz + eps2;
+        T rinv;
+        if (std::is_same<T, float>::value) rinv = (T)__builtin_amdgcn_rsqf((float)s);
+        else rinv = (T)rsqrt_f64((double)s);
+        if (MASK && jj == rel) rinv = T(0);
+        if (!SOFT && !(s > T(0))) rinv = T(0);
+        const T Aq[3] = {sm.A[0][jj], sm.A[1][jj], sm.A[2][jj]};
+        const T Bq[3] = {sm.B[0][jj], sm.B[1][jj], sm.B[2][jj]};
+        vjp_pair<T>(dx, dy, dz, ux, uy, uz, rinv, mp, sm.m[jj], nA, nB, Aq, Bq, gx, gu, ngm);
+    }
+}
+
 // Force VJP over all particles; j-split into K ranges, partial sums (7 per particle: x_bar,
 // v_bar, m_bar) per range, summed by vjp_reduce.  MODE 0: float arithmetic on separations
-// formed in double (tile sums folded into double); MODE 2: double throughout.
-template <int MODE>
+// formed in double (tile sums folded into double); MODE 2: double throughout.  SOFT: eps > 0
+// in the arithmetic type.
+template <int MODE, bool SOFT>
 __global__ void __launch_bounds__(WG) force_vjp_kernel(VjpArgs a) {
     using T = typename std::conditional<MODE == 0, float, double>::type;
     __shared__ VjpSmem<T> sm;
@@ -170,6 +201,7 @@ __global__ void __launch_bounds__(WG) force_vjp_kernel(VjpArgs a) {
         const int32_t iblk = w / pl.K, ks = w - (w / pl.K) * pl.K;
         const int32_t p = iblk * WG + (int32_t)threadIdx.x;
         const int32_t pc = p < n ? p : 0;
+        const int32_t own = p < n ? p : -1;  // p's own j-slot (none on padding lanes)
         const double xp = a.px[pc], yp = a.py[pc], zp = a.pz[pc];
         T vxp, vyp, vzp, mp;
         if (MODE == 0) {
@@ -178,11 +210,14 @@ __global__ void __launch_bounds__(WG) force_vjp_kernel(VjpArgs a) {
         } else {
             vxp = a.vx[pc]; vyp = a.vy[pc]; vzp = a.vz[pc]; mp = a.pm[pc];
         }
-        T A[3], B[3];
+        T nA[3], nB[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            A[k] = (T)a.ab[k * (int64_t)n + pc];
-            B[k] = (T)a.kb[k * (int64_t)n + pc];
+            nA[k] = -(T)a.ab[k * (int64_t)n + pc];
+            nB[k] = -(T)a.kb[k * (int64_t)n + pc];
+            // opaque to the optimiser, which would otherwise fold the negation back into
+            // modifiers on the products inside the pair loop
+            asm volatile("" : "+v"(nA[k]), "+v"(nB[k]));
         }
         double S[7] = {0, 0, 0, 0, 0, 0, 0};
         const T eps2 = (T)a.eps2;
@@ -210,26 +245,19 @@ __global__ void __launch_bounds__(WG) force_vjp_kernel(VjpArgs a) {
                 }
             }
             __syncthreads();
-            T gx[3] = {0, 0, 0}, gu[3] = {0, 0, 0}, gm = 0;
-            for (int jj = 0; jj < TJ; ++jj) {
-                const T dx = (T)(sm.x[jj] - xp), dy = (T)(sm.y[jj] - yp), dz = (T)(sm.z[jj] - zp);
-                const T ux = sm.vx[jj] - vxp, uy = sm.vy[jj] - vyp, uz = sm.vz[jj] - vzp;
-                const T s = dx * dx + dy * dy + dz * dz + eps2;
-                T rinv;
-                if (MODE == 0) rinv = __builtin_amdgcn_rsqf((float)s);
-                else rinv = (T)rsqrt_f64((double)s);
-                // the self pair and padding (zero mass, zero adjoints) contribute nothing
-                if (t * TJ + jj == p || !(s > T(0))) rinv = T(0);
-                const T Aq[3] = {sm.A[0][jj], sm.A[1][jj], sm.A[2][jj]};
-                const T Bq[3] = {sm.B[0][jj], sm.B[1][jj], sm.B[2][jj]};
-                vjp_pair<T>(dx, dy, dz, ux, uy, uz, rinv, mp, sm.m[jj], A, B, Aq, Bq, gx, gu, gm);
-            }
+            T gx[3] = {0, 0, 0}, gu[3] = {0, 0, 0}, ngm = 0;
+            const int32_t rel = own - t * TJ;
+            // a tile holding some lane's own slot takes the masked loop (wave-uniform branch)
+            if (SOFT && __ballot((uint32_t)rel < (uint32_t)TJ) != 0)
+                vjp_tile<T, SOFT, true>(sm, rel, xp, yp, zp, vxp, vyp, vzp, mp, eps2, nA, nB, gx, gu, ngm);
+            else
+                vjp_tile<T, SOFT, false>(sm, rel, xp, yp, zp, vxp, vyp, vzp, mp, eps2, nA, nB, gx, gu, ngm);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 S[k] += (double)gx[k];
                 S[3 + k] += (double)gu[k];
             }
-            S[6] += (double)gm;
+            S[6] -= (double)ngm;
         }
         if (p < n) {
             double *base = a.partial + (int64_t)ks * 7 * pl.P + p;

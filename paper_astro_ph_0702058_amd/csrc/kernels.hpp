@@ -102,6 +102,7 @@ struct ForceCommon {
     double *partial;         // K > 1: [K][7][P]
     DevControl *ctl;         // latched flags (may be NULL)
     int32_t smax;            // largest lane split of the arithmetic mode
+    int32_t scalar_min;      // fewest j-tiles per item read with scalar loads (float modes)
 };
 
 // Sum record written per i-particle: acc (3), jerk (3), accumulated m/r (1).
@@ -738,8 +739,8 @@ __device__ void force_items_split(const typename M::Args &pa, const ForceCommon 
 
 // Sums of the IPL i-particles of a work-item over the j-tiles [t0, t1): the j-records read
 // once per wave with scalar loads (every lane takes the same j).  The latency of each load is
-// exposed to its wave, so this pays only on long j-ranges (SCALAR_MIN_TILES tiles or more).
-constexpr int32_t SCALAR_MIN_TILES = 16;
+// exposed to its wave, so the launch takes this path only for items of at least
+// ForceCommon::scalar_min tiles (chosen per launch class by measurement).
 
 // Sums over j in [ja, je) with scalar j-loads; MASK: some lane's own slot own[p] lies inside.
 template <class M, int IPL, int UNR, bool SOFT, bool MASK>
@@ -897,7 +898,7 @@ __global__ void __launch_bounds__(WG) force_kernel(typename M::Args pa, ForceCom
         const int32_t t0 = ks * pl.tps;
         const int32_t t1 = t0 + pl.tps < pl.ntiles ? t0 + pl.tps : pl.ntiles;
         if constexpr (ModeTraits<M>::SCALAR_J) {
-            if (pl.tps >= SCALAR_MIN_TILES)
+            if (pl.tps >= fc.scalar_min)
                 block_sums_scalar<M, IPL, UNR, SOFT>(pa, fc.n, t0, t1, ii, own, S, eps2);
             else
                 block_sums_lds<M, IPL, UNR, SOFT>(pa, fc.n, sm, t0, t1, ii, own, S, eps2);

@@ -103,8 +103,8 @@ struct nb_ctx {
     int32_t sched_groups = 1, sched_chunk = 1;
     int32_t fused_groups = 1, fused_chunk = 1;  // chunks of the fused step's count + predict
     int32_t resident_max = 1024;         // nb_run: one resident workgroup up to this n
-    Variant var_full{2, 2, 4096, 256};   // calls on (nearly) all particles
-    Variant var_block{2, 2, 4096, 256};  // block-step calls (device-resident count)
+    Variant var_full{2, 2, 4096, 256, 16};   // calls on (nearly) all particles
+    Variant var_block{2, 2, 4096, 256, 16};  // block-step calls (device-resident count)
     int32_t max_target = 4096;           // partial planes are sized for targets up to this
     int32_t *tune_n = nullptr;           // device count used while tuning
 
@@ -239,6 +239,11 @@ Variant default_variant(int32_t n, int prec, int num_cu, bool block) {
     v.unroll = 2;
     v.target = num_cu * (block ? BLOCK_ITEMS_PER_CU : FULL_ITEMS_PER_CU);
     v.kmax = block ? 1 << 16 : FULL_KMAX;  // K is also bounded by the tile count
+    // scalar j-loads from 1 tile per item in full-force calls and from 4 in block steps
+    // (interleaved runs on one MI355X against 16 tiles: the shared-step gradient at N = 16384,
+    // whose full forces are one-tile items, 54.3 against 56.1 ms; the N = 65536 block-step run
+    // 2.73 against 2.79 s, where 1 tile gave 2.80 s and 8 tiles 2.75 s)
+    v.scalar_tiles = block ? 4 : 1;
     if (block || (prec != NB_FP32 && prec != NB_FP32_FIXED)) return v;
     // full-force calls of 2^16 and 2^17 particles (force + reduction per call, warm clocks, the
     // two variants timed alternately on one MI355X): N = 65536 at 16 items per CU with the
@@ -359,7 +364,7 @@ nb_status enqueue_force(nb_ctx *c, const Variant &v, int cls, const int32_t *ili
     const int32_t ib = WG * v.ipl;
     const int32_t smax = smax_of(c->prec);
     ForceCommon fc{c->n, ilist, n_i_dev, n_i_max, v.target, v.kmax, acc, jerk, pot, ld,
-                   partial ? partial : c->partial, c->ctl, smax};
+                   partial ? partial : c->partial, c->ctl, smax, v.scalar_tiles};
     int32_t grid;
     if (n_i_dev) {
         // the count is known only on the device: enough workgroups for any count up to n_i_max
@@ -479,7 +484,7 @@ nb_status enqueue_step(nb_ctx *c, double eta, hipStream_t s) {
     // the j-split sums and the corrector in one launch; the same ForceCommon as the force
     const Variant &v = c->var_block;
     ForceCommon fc{c->n, c->active, &c->ctl->n_act, c->n, v.target, v.kmax, c->acc1, c->jerk1,
-                   c->pot1, c->n, c->partial, c->ctl, smax_of(c->prec)};
+                   c->pot1, c->n, c->partial, c->ctl, smax_of(c->prec), v.scalar_tiles};
     const int32_t units = (c->n + RC_ROWS - 1) / RC_ROWS;
     const int32_t rgrid = (std::max(8, std::min(units, c->num_cu * 2)) + 7) & ~7;
     if (c->prec == NB_FP32_FIXED)
@@ -965,8 +970,15 @@ static nb_status enqueue_force_vjp(nb_ctx *c, const double *ab, const double *kb
     if ((int64_t)pl.K * pl.P > c->partial_rows)  // the workspace is sized for this plan
         return fail(c, NB_ESTATE, "force VJP plan exceeds the partial planes");
     const int32_t grid = std::max(1, std::min(pl.items, 1 << 20));
-    if (c->prec == NB_FP32) force_vjp_kernel<0><<<grid, WG, 0, s>>>(a);
-    else force_vjp_kernel<2><<<grid, WG, 0, s>>>(a);
+    // softened: every separation is positive in the arithmetic type, only the self pair masked
+    const bool soft = c->prec == NB_FP32 ? (float)a.eps2 > 0.0f : a.eps2 > 0.0;
+    if (c->prec == NB_FP32) {
+        if (soft) force_vjp_kernel<0, true><<<grid, WG, 0, s>>>(a);
+        else force_vjp_kernel<0, false><<<grid, WG, 0, s>>>(a);
+    } else {
+        if (soft) force_vjp_kernel<2, true><<<grid, WG, 0, s>>>(a);
+        else force_vjp_kernel<2, false><<<grid, WG, 0, s>>>(a);
+    }
     LAUNCH_OK(c);
     vjp_reduce<<<grid_for(c->n, 4096), WG, 0, s>>>(c->n, c->partial, a.target, a.kmax, xb, vb, mb,
                                                    accumulate);
@@ -1041,6 +1053,7 @@ nb_status nb_step_vjp(nb_ctx *c, double dt, double *xbar, double *vbar, double *
 static bool variant_valid(const nb_ctx *c, const nb_variant &v) {
     if (!variant_compiled(c->prec, v)) return false;
     if (v.target < 1 || v.target > c->max_target || v.kmax < 1 || v.kmax > (1 << 16)) return false;
+    if (v.scalar_tiles < 1 || v.scalar_tiles > (1 << 16)) return false;
     return partial_rows_for(c->n, v, smax_of(c->prec)) <= c->partial_rows;
 }
 
@@ -1050,12 +1063,17 @@ nb_status nb_get_variant(nb_ctx *c, int32_t which, nb_variant *out) {
     return NB_OK;
 }
 
-nb_status nb_set_variant(nb_ctx *c, int32_t which, const nb_variant *v) {
-    if (!c || !v || which < 0 || which > 1) return NB_EINVAL;
+nb_status nb_set_variant(nb_ctx *c, int32_t which, const nb_variant *vin) {
+    if (!c || !vin || which < 0 || which > 1) return NB_EINVAL;
+    Variant &cur = which == 0 ? c->var_full : c->var_block;
+    nb_variant vv = *vin;
+    if (vv.scalar_tiles == 0) vv.scalar_tiles = cur.scalar_tiles;  // keep the current value
+    const nb_variant *v = &vv;
     if (!variant_valid(c, *v))
-        return fail(c, NB_EINVAL, "variant ipl=%d unroll=%d target=%d kmax=%d not available",
-                    v->ipl, v->unroll, v->target, v->kmax);
-    (which == 0 ? c->var_full : c->var_block) = *v;
+        return fail(c, NB_EINVAL,
+                    "variant ipl=%d unroll=%d target=%d kmax=%d scalar_tiles=%d not available",
+                    v->ipl, v->unroll, v->target, v->kmax, v->scalar_tiles);
+    cur = *v;
     drop_graph(c);
     return NB_OK;
 }
@@ -1096,34 +1114,39 @@ nb_status nb_tune(nb_ctx *c, int32_t which, int32_t n_i, int32_t reps, nb_varian
             warm += ms;
         }
     }
-    const int ipls[] = {1, 2, 4}, unrs[] = {1, 2, 4};
+    const int ipls[] = {1, 2, 4}, unrs[] = {1, 2, 4}, scal[] = {1, 4, 16};
     const int32_t targets[] = {c->num_cu * 4, c->num_cu * 8, c->num_cu * 16, c->num_cu * 32,
                                c->num_cu * 64, c->num_cu * 128, c->num_cu * FULL_ITEMS_PER_CU};
+    // the scalar-load threshold matters only in the float modes (FP64 always stages LDS tiles)
+    const int nscal = (c->prec == NB_FP64) ? 1 : 3;
+    const int32_t keep_scal = bestv.scalar_tiles;
     for (int ipl : ipls)
         for (int unr : unrs)
-            for (int32_t tg : targets) {
-                const nb_variant v{ipl, unr, tg,
-                                   tg > c->num_cu * BLOCK_ITEMS_PER_CU ? FULL_KMAX : 1 << 16};
-                if (!variant_valid(c, v)) continue;
-                float tot = 0.f;
-                for (int rep = 0; rep <= reps; ++rep) {  // the first launch is not timed
-                    HIP_OK(c, hipEventRecord(e0, s));
-                    if (which == 0)
-                        r = enqueue_force(c, v, 0, nullptr, nullptr, n_i, c->acc1, c->jerk1,
-                                          c->pot1, c->n, s);
-                    else
-                        r = enqueue_force(c, v, 1, nullptr, c->tune_n, c->n, c->acc1, c->jerk1,
-                                          c->pot1, c->n, s);
-                    if (r != NB_OK) { c->profile = was_profiling; return r; }
-                    HIP_OK(c, hipEventRecord(e1, s));
-                    HIP_OK(c, hipEventSynchronize(e1));
-                    float ms = 0.f;
-                    HIP_OK(c, hipEventElapsedTime(&ms, e0, e1));
-                    if (rep > 0) tot += ms;
+            for (int32_t tg : targets)
+                for (int si = 0; si < nscal; ++si) {
+                    const nb_variant v{ipl, unr, tg,
+                                       tg > c->num_cu * BLOCK_ITEMS_PER_CU ? FULL_KMAX : 1 << 16,
+                                       nscal == 1 ? keep_scal : scal[si]};
+                    if (!variant_valid(c, v)) continue;
+                    float tot = 0.f;
+                    for (int rep = 0; rep <= reps; ++rep) {  // the first launch is not timed
+                        HIP_OK(c, hipEventRecord(e0, s));
+                        if (which == 0)
+                            r = enqueue_force(c, v, 0, nullptr, nullptr, n_i, c->acc1, c->jerk1,
+                                              c->pot1, c->n, s);
+                        else
+                            r = enqueue_force(c, v, 1, nullptr, c->tune_n, c->n, c->acc1,
+                                              c->jerk1, c->pot1, c->n, s);
+                        if (r != NB_OK) { c->profile = was_profiling; return r; }
+                        HIP_OK(c, hipEventRecord(e1, s));
+                        HIP_OK(c, hipEventSynchronize(e1));
+                        float ms = 0.f;
+                        HIP_OK(c, hipEventElapsedTime(&ms, e0, e1));
+                        if (rep > 0) tot += ms;
+                    }
+                    const double avg = tot / reps;
+                    if (avg < bms) { bms = avg; bestv = v; }
                 }
-                const double avg = tot / reps;
-                if (avg < bms) { bms = avg; bestv = v; }
-            }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->profile = was_profiling;

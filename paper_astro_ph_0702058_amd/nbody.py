@@ -39,9 +39,14 @@ class nb_control(ctypes.Structure):
                 ("n_act", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
+def _variant_dict(v):
+    return dict(ipl=v.ipl, unroll=v.unroll, target=v.target, kmax=v.kmax,
+                scalar_tiles=v.scalar_tiles)
+
+
 class nb_variant(ctypes.Structure):
     _fields_ = [("ipl", ctypes.c_int32), ("unroll", ctypes.c_int32), ("target", ctypes.c_int32),
-                ("kmax", ctypes.c_int32)]
+                ("kmax", ctypes.c_int32), ("scalar_tiles", ctypes.c_int32)]
 
 
 EXPORTS = ["nb_create", "nb_destroy", "nb_set_stream", "nb_bind", "nb_init",
@@ -388,11 +393,13 @@ class Context:
     def nb_get_variant(self, which):
         v = nb_variant()
         self._check(self.lib.nb_get_variant(self.h, int(which), ctypes.byref(v)))
-        return dict(ipl=v.ipl, unroll=v.unroll, target=v.target, kmax=v.kmax)
+        return _variant_dict(v)
 
     def nb_set_variant(self, which, variant):
+        """`variant`: ipl, unroll, target, kmax and optionally scalar_tiles (absent or 0: the
+        context's current value)."""
         v = nb_variant(int(variant["ipl"]), int(variant["unroll"]), int(variant["target"]),
-                       int(variant["kmax"]))
+                       int(variant["kmax"]), int(variant.get("scalar_tiles", 0)))
         self._check(self.lib.nb_set_variant(self.h, int(which), ctypes.byref(v)))
 
     def nb_tune(self, which, n_i, reps=2):
@@ -401,7 +408,7 @@ class Context:
         v, ms = nb_variant(), ctypes.c_double()
         self._check(self.lib.nb_tune(self.h, int(which), int(n_i), int(reps), ctypes.byref(v),
                                      ctypes.byref(ms)))
-        return dict(ipl=v.ipl, unroll=v.unroll, target=v.target, kmax=v.kmax), ms.value
+        return _variant_dict(v), ms.value
 
     def nb_shared_step(self, dt, nsteps=1):
         self._check(self.lib.nb_shared_step(self.h, float(dt), int(nsteps)))

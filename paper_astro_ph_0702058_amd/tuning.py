@@ -37,9 +37,9 @@ def autotune(ctx, cache_path: str | None = DEFAULT_CACHE, reps: int = 2, retune:
     chosen = {}
     for which, n_i in ((0, ctx.n), (1, expected_block_size(ctx.n))):
         key = _key(ctx, which, n_i)
-        if key in cache:
+        if key in cache and "scalar_tiles" in cache[key]["variant"]:
             ctx.nb_set_variant(which, cache[key]["variant"])
-            chosen[which] = cache[key]["variant"]
+            chosen[which] = ctx.nb_get_variant(which)
             continue
         v, ms = ctx.nb_tune(which, n_i, reps)
         cache[key] = {"variant": v, "ms": ms}

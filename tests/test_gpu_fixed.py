@@ -1,9 +1,9 @@
 """Order-independent single precision (fp32fixed): float sums over aligned 64-j sub-blocks added
 into int64 fixed point.  Its forces must be bitwise identical for every launch variant (i per
 lane 1 or 2, unroll 1 or 2), every work-item target (which changes the j-split K, for short
-lists the lane split, and whether an item of 16 or more j-tiles reads its j-records with scalar
-loads or an item of fewer stages them in LDS), and between the full-force and block-step launch
-classes; they must
+lists the lane split), whether an item reads its j-records with scalar loads or stages them in
+LDS (scalar_tiles 1 or 16 against items of 1 to 20 tiles), and between the full-force and
+block-step launch classes; they must
 meet the single-precision tolerances against the oracle, also on a sample that reaches the
 halo, where accelerations and jerks are small (the fixed-point steps, 2^-44 for acc and pot and
 2^-42 for the jerk, add rounding of about one step times sqrt(N/64): near 1e-11 absolute at
@@ -19,8 +19,8 @@ from _parity import check, reference
 
 pytestmark = pytest.mark.gpu
 
-VARIANTS = [dict(ipl=i, unroll=u, target=t, kmax=65536)
-            for i in (1, 2) for u in (1, 2) for t in (8, 256, 4096)]
+VARIANTS = [dict(ipl=i, unroll=u, target=t, kmax=65536, scalar_tiles=s)
+            for i in (1, 2) for u in (1, 2) for t in (8, 256, 4096) for s in (1, 16)]
 
 
 def forces(ctx, n, idx, which):

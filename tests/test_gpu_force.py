@@ -204,11 +204,13 @@ def test_force_all_single_matches_rounded_inputs(eps):
 def test_force_scalar_load_and_lds_paths(prec):
     """All i at N = 4999 (19 full j-tiles and a ragged tail of 135), once with 8 work items
     (one j-range of 20 tiles per item: the float modes read the j-records with scalar loads)
-    and once with 400 (20 i-blocks of 256 against 20 j-ranges of one tile: LDS tiles; one
-    lane per i in both).  Both meet the tolerances against
-    the oracle (fp32all: against the oracle on float-rounded inputs); they differ only in how
-    the per-tile sums are grouped, so they agree to 1e-11 relative (fp32all, whose sums stay
-    in float: 1e-6; fp32fixed: bitwise)."""
+    and once with 400 (20 i-blocks of 256 against 20 j-ranges of one tile: LDS tiles with the
+    scalar-load threshold at 16 tiles, scalar loads with it at 1, the ragged last tile read
+    that way too; one lane per i throughout).  All meet the tolerances against
+    the oracle (fp32all: against the oracle on float-rounded inputs); the first two differ only
+    in how the per-tile sums are grouped, so they agree to 1e-11 relative (fp32all, whose sums
+    stay in float: 1e-6; fp32fixed: bitwise); the last two group them alike and agree
+    bitwise."""
     import torch
     n, eps = 4999, 1 / 256
     x, v, m = plummer(n, 34)
@@ -217,8 +219,9 @@ def test_force_scalar_load_and_lds_paths(prec):
     with nbody.Context(n, eps, precision=prec) as ctx:
         ctx.nb_bind(st)
         ctx.nb_predict(torch.zeros(1, dtype=torch.int64, device="cuda"))
-        for target in (8, 400):
-            ctx.nb_set_variant(0, dict(ipl=1, unroll=2, target=target, kmax=64))
+        for target, st_min in ((8, 16), (400, 16), (400, 1)):
+            ctx.nb_set_variant(0, dict(ipl=1, unroll=2, target=target, kmax=64,
+                                       scalar_tiles=st_min))
             acc = torch.zeros((3, n), dtype=torch.float64, device="cuda")
             jerk = torch.zeros_like(acc)
             pot = torch.zeros(n, dtype=torch.float64, device="cuda")
@@ -231,7 +234,7 @@ def test_force_scalar_load_and_lds_paths(prec):
     else:
         ref, scale = reference(x, v, m, eps * eps)
     tol_key = "fp32" if prec == "fp32fixed" else prec
-    for r, label in zip(res, ("scalar-load path", "LDS path")):
+    for r, label in zip(res, ("scalar-load path", "LDS path", "one-tile scalar-load path")):
         check(tol_key, r, ref, scale, f"N={n} {label}")
     for c in range(3):
         if prec == "fp32fixed":
@@ -239,3 +242,4 @@ def test_force_scalar_load_and_lds_paths(prec):
         else:
             lim = 1e-6 if prec == "fp32all" else 1e-11
             assert rms_rel(res[0][c], res[1][c]) <= lim, (c, rms_rel(res[0][c], res[1][c]))
+        assert np.array_equal(res[1][c], res[2][c]), c

@@ -18,9 +18,12 @@ CASES = [("fp32",) + c for c in F32] + [("ds",) + c for c in OTHER] + [("fp64",)
 @pytest.mark.parametrize("prec,ipl,unr", CASES)
 @pytest.mark.parametrize("target", [8, 1024])
 @pytest.mark.parametrize("count", [37, 700])
-def test_variant_parity(prec, ipl, unr, target, count):
+@pytest.mark.parametrize("scalar_tiles", [1, 16])
+def test_variant_parity(prec, ipl, unr, target, count, scalar_tiles):
     """700 listed i: whole i-blocks of the variant; 37: the lane split, which every variant
-    takes for lists shorter than a workgroup."""
+    takes for lists shorter than a workgroup.  N = 3001 is 12 j-tiles: with scalar_tiles 1 the
+    float modes read every item's j-records with scalar loads (a one-tile item at target 1024,
+    the ragged last tile included), with 16 every item stages LDS tiles."""
     n = 3001
     x, v, m = plummer(n, 31)
     eps = 1 / 256
@@ -29,7 +32,7 @@ def test_variant_parity(prec, ipl, unr, target, count):
     with nbody.Context(n, eps, precision=prec) as ctx:
         ctx.nb_bind(st)
         ctx.nb_predict(torch.zeros(1, dtype=torch.int64, device="cuda"))
-        var = dict(ipl=ipl, unroll=unr, target=target, kmax=65536)
+        var = dict(ipl=ipl, unroll=unr, target=target, kmax=65536, scalar_tiles=scalar_tiles)
         ctx.nb_set_variant(1, var)
         assert ctx.nb_get_variant(1) == var
         ii = torch.as_tensor(idx, device="cuda")
@@ -41,7 +44,8 @@ def test_variant_parity(prec, ipl, unr, target, count):
     ref, scale = reference(x, v, m, eps * eps, idx=idx)
     got = (acc[:, :idx.size].cpu().numpy().T, jerk[:, :idx.size].cpu().numpy().T,
            pot[:idx.size].cpu().numpy())
-    check(prec, got, ref, scale, f"ipl={ipl} unroll={unr} target={target} count={count}")
+    check(prec, got, ref, scale,
+          f"ipl={ipl} unroll={unr} target={target} count={count} scalar_tiles={scalar_tiles}")
     assert np.all(acc[:, idx.size:].cpu().numpy() == 0)   # rows beyond the count untouched
 
 
@@ -56,6 +60,13 @@ def test_set_variant_rejects_unavailable():
             ctx.nb_set_variant(0, dict(ipl=1, unroll=2, target=10 ** 7, kmax=256))
         with pytest.raises(nbody.NBodyError):
             ctx.nb_set_variant(0, dict(ipl=1, unroll=2, target=64, kmax=10 ** 6))
+        with pytest.raises(nbody.NBodyError):
+            ctx.nb_set_variant(0, dict(ipl=1, unroll=2, target=64, kmax=256, scalar_tiles=-1))
+        # absent (or 0): the context keeps its current scalar-load threshold
+        before = ctx.nb_get_variant(0)["scalar_tiles"]
+        ctx.nb_set_variant(0, dict(ipl=1, unroll=2, target=64, kmax=256))
+        assert ctx.nb_get_variant(0) == dict(ipl=1, unroll=2, target=64, kmax=256,
+                                             scalar_tiles=before)
 
 
 def test_tuner_picks_a_working_variant():
