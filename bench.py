@@ -587,7 +587,7 @@ def main():
     ap.add_argument("--lmin", type=int, default=3)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "ds", "fp64", "fp32all"])
-    ap.add_argument("--variants", default="ds,fp64,fp32fixed",
+    ap.add_argument("--variants", default="ds,fp64,fp32fixed,fp32all",
                     help="other interaction arithmetics to time once (comma list, or 'none')")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
