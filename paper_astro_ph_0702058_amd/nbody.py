@@ -385,9 +385,13 @@ class Context:
         self._check(self.lib.nb_energy(self.h, ctypes.byref(ek), ctypes.byref(ep)))
         return ek.value, ep.value
 
-    def nb_read_control(self) -> Control:
+    def nb_read_control(self, check: bool = True) -> Control:
+        """The scheduler record.  check=False: return it even when a latched device flag
+        (NB_EDTMIN or NB_ENONFINITE) makes the call report an error; `flags` then says which."""
         c = nb_control()
-        self._check(self.lib.nb_read_control(self.h, ctypes.byref(c)))
+        st = self.lib.nb_read_control(self.h, ctypes.byref(c))
+        if check or st not in (NB_OK, NB_EDTMIN, NB_ENONFINITE):
+            self._check(st)
         return Control(c.t_cur, c.t_next, c.t_end, c.n_steps, c.n_active_sum, c.n_act, c.flags)
 
     def nb_get_variant(self, which):

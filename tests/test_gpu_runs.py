@@ -29,6 +29,9 @@ dt <= 1/8, integrated to t = 1 by the device-resident loop.
    the bulk fixes: the total number of particle steps within 5 %, the block-step count within
    25 %, and the energy error within a factor 10 of the oracle's (at eps = 1e-3 it is the
    integrator's, from close encounters, not the arithmetic's).
+4. The paper's all-single arithmetic (float positions, so separations lose their digits to the
+   positions' rounding) cannot run this configuration as the oracle does: its blocks fragment
+   (20 times the block steps by t = 1/64) and a step request falls below 2^-26 by t = 1/2.
 """
 import json
 import os
@@ -160,6 +163,38 @@ def test_run_to_t1_against_oracle_run(prec):
         assert abs(c.n_active_sum - ref["n_active_sum"]) <= 0.05 * ref["n_active_sum"]
         assert abs(c.n_steps - ref["n_steps"]) <= 0.25 * ref["n_steps"]
         assert abs(de) <= 10 * abs(ref["de_rel"])
+
+
+def test_all_single_run_fragments_its_blocks():
+    """The paper's all-single arithmetic (float positions, separations and sums) on the same
+    run: rounding noise in a and k, divided by dt^2 and dt^3 in the corrector's derivative
+    estimates, sends some particles' step criterion far below their neighbours', so the
+    blocks fragment.  To t = 1/64 it takes more than 10 times the block steps of the FP64 run
+    (587, the oracle's count) for particle steps within 1.3 times; by t = 1/2 some request
+    falls below 2^-26, which the run reports as NB_EDTMIN (clamped, run completed), and the
+    scheduler record read with check=False says how far it got."""
+    x, v, m = plummer(N, SEED)
+    counts = {}
+    for prec in ("fp64", "fp32all"):
+        st = nbody.DeviceState(x, v, m)
+        with nbody.Context(N, EPS, lmin=LMIN, lmax=LMAX, precision=prec) as ctx:
+            ctx.nb_bind(st)
+            ctx.nb_init(NU)
+            ctx.nb_run(NU, 1 / 64, chunk=256, use_graph=True)
+            c = ctx.nb_read_control()
+            counts[prec] = (c.n_steps, c.n_active_sum)
+            if prec == "fp32all":
+                with pytest.raises(nbody.NBodyError) as e:
+                    ctx.nb_run(NU, 0.5, chunk=256, use_graph=True)
+                    ctx.nb_sync()
+                assert e.value.status == nbody.NB_EDTMIN
+                late = ctx.nb_read_control(check=False)
+    print(f"to t=1/64: {counts}; all-single to t=1/2: {late.n_steps} block steps, "
+          f"flags {late.flags}", flush=True)
+    assert counts["fp64"][0] == 587
+    assert counts["fp32all"][0] > 10 * counts["fp64"][0]
+    assert counts["fp32all"][1] < 1.3 * counts["fp64"][1]
+    assert late.flags & 2 and late.t_cur == 2 ** (LMAX - 1)
 
 
 def test_block_forces_at_full_size():
