@@ -80,6 +80,7 @@ def test_tuner_picks_a_working_variant():
         chosen = autotune(ctx, cache_path=None, reps=1)
         assert set(chosen) == {0, 1}
         assert ctx.nb_get_variant(0) == chosen[0] and ctx.nb_get_variant(1) == chosen[1]
+        assert all(chosen[w]["scalar_tiles"] in (1, 4, 16) for w in (0, 1))
         assert expected_block_size(n) == round(0.2 * n ** 0.81)
         idx = sample_indices(n, 200, 4)
         acc = torch.zeros((3, n), dtype=torch.float64, device="cuda")
