@@ -59,9 +59,16 @@ def gpu_grad(x0, v0, m, target, eps, dt, nsteps, ce, prec):
             x.detach().cpu().numpy().T)
 
 
-def test_force_vjp_matches_autograd():
-    """nb_force_vjp in FP64 against autograd of the plain-torch force."""
-    n, eps = 300, 1 / 64
+@pytest.mark.parametrize("prec,eps", [("fp64", 1 / 64), ("fp64", 0.0), ("fp32", 1 / 64),
+                                      ("fp32", 0.0)])
+def test_force_vjp_matches_autograd(prec, eps):
+    """nb_force_vjp against autograd of the plain-torch force in FP64, at N = 300 (one whole
+    and one ragged i-block; the self pair in a masked tile), softened (only the tile holding a
+    particle's own slot tests for it) and unsoftened (every pair at zero separation skipped).
+    FP64: 1e-11 of the largest component.  FP32 (float pair terms, tile sums in double): each
+    pair term carries a few float roundings (about 1e-7 relative) and the largest terms come
+    from the closest pairs, so 2e-6 of the largest component (printed: the measured error)."""
+    n = 300
     x, v, m = plummer(n, 41)
     rng = np.random.default_rng(2)
     A = rng.normal(size=(n, 3)); B = rng.normal(size=(n, 3))
@@ -70,16 +77,20 @@ def test_force_vjp_matches_autograd():
     a, k = torch_force(xt, vt, mt, eps * eps)
     ((a * torch.tensor(A)).sum() + (k * torch.tensor(B)).sum()).backward()
     st = nbody.DeviceState(x, v, m)
-    with nbody.Context(n, eps, precision="fp64") as ctx:
+    with nbody.Context(n, eps, precision=prec) as ctx:
         ctx.nb_bind(st)
         ctx.nb_predict(torch.zeros(1, dtype=torch.int64, device="cuda"))
         xb = torch.zeros((3, n), dtype=torch.float64, device="cuda")
         vb = torch.zeros_like(xb); mb = torch.zeros(n, dtype=torch.float64, device="cuda")
         ctx.nb_force_vjp(soa(A), soa(B), xb, vb, mb)
         ctx.nb_sync()
-    for got, ref in ((xb.cpu().numpy().T, xt.grad.numpy()), (vb.cpu().numpy().T, vt.grad.numpy()),
-                     (mb.cpu().numpy(), mt.grad.numpy())):
-        assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+    tol = 1e-11 if prec == "fp64" else 2e-6
+    for name, got, ref in (("x", xb.cpu().numpy().T, xt.grad.numpy()),
+                           ("v", vb.cpu().numpy().T, vt.grad.numpy()),
+                           ("m", mb.cpu().numpy(), mt.grad.numpy())):
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        print(f"{prec} eps={eps} {name}_bar: {err:.2e} of the largest component", flush=True)
+        assert err <= tol, (name, err)
 
 
 @pytest.mark.parametrize("ce", [1, 4, 5])
