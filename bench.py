@@ -299,12 +299,11 @@ def bench_run(args, emit=True):
         log(f"[bench] {prec}: {vr['n_steps']} steps, {vr['wall']:.3f} s, dE/E {variants[prec]['de_rel']:.3e}")
     result["variants"] = variants
     if g_run:
-        g = g_run
-        if g:
-            result["oracle_reference_run"] = {
-                "de_rel": g["de_rel"], "n_steps": g["n_steps"], "mean_block": g["mean_block"],
-                "seconds": g["seconds"], "threads": g["threads"],
-                "note": "committed FP64 oracle run of the same initial conditions"}
+        result["oracle_reference_run"] = {
+            "de_rel": g_run["de_rel"], "n_steps": g_run["n_steps"],
+            "mean_block": g_run["mean_block"], "seconds": g_run["seconds"],
+            "threads": g_run["threads"],
+            "note": "committed FP64 oracle run of the same initial conditions"}
     if not args.no_cpu_baseline:
         import oracle
         t_a = time.perf_counter()  # the oracle's init (the N^2 force) is part of the sample
