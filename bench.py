@@ -96,6 +96,18 @@ def bench_ensemble(args, emit=True):
         from paper_astro_ph_0702058_amd.tuning import ensemble_autotune
         layout = ensemble_autotune(ens, st, x0, v0, eta)
         log(f"[bench] ensemble layout {layout}")
+    lanes = None
+    if args.ens_lanes == "probe":
+        # untimed, like the tuner: a run to t = 1/4 picks the 8 clusters with the most block
+        # steps for a lane of their own
+        from paper_astro_ph_0702058_amd.tuning import ensemble_lanes
+        t_p = time.perf_counter()
+        lane = ensemble_lanes(ens, st, x0, v0, eta)
+        lanes = {"lanes": int(lane.max()) + 1, "lane0_clusters": np.flatnonzero(lane == 0).tolist(),
+                 "assignment": "the 8 clusters with the most block steps in a probe run to "
+                               "t = 1/4 (untimed) in lane 0, the rest in lane 1",
+                 "probe_s": time.perf_counter() - t_p}
+        log(f"[bench] ensemble lanes: {lanes}")
 
     def step():
         st.x.copy_(x0); st.v.copy_(v0)
@@ -129,7 +141,7 @@ def bench_ensemble(args, emit=True):
                                f"(total {int(sizes.sum())}), eps=1/N_c, eta=0.02, t -> {args.t_end}",
                    "clusters": args.clusters, "particles": int(sizes.sum()),
                    "local_blocks": args.ens_local or "default",
-                   "interactions_per_run": inter, "layout": layout,
+                   "interactions_per_run": inter, "layout": layout, "lanes": lanes,
                    "max_block_steps": max(c.n_steps for c in ctl),
                    "mean_block_steps": float(np.mean([c.n_steps for c in ctl])),
                    "dE_over_E_max": float(de.max()), "dE_over_E_median": float(np.median(de))},
@@ -640,6 +652,9 @@ def main():
                     help="nb_set_resident for the run and timed workloads (default: the "
                          "library's; 0: always the launch chain)")
     ap.add_argument("--clusters", type=int, default=512)
+    ap.add_argument("--ens-lanes", default="probe", choices=["probe", "one"],
+                    help="ensemble: two independent lanes chosen by an untimed probe run "
+                         "(default), or one lane")
     ap.add_argument("--ens-spl", type=int, default=128,
                     help="ensemble: global steps per graph replay (one host check per replay)")
     ap.add_argument("--ens-local", default="",
@@ -932,7 +947,8 @@ def other_configs(args):
     out["ensemble_512"] = {"wall_s": r["ms_per_step"] / 1e3, "interactions_per_s": r["value"],
                            "frac_fp32_peak": r["roofline"]["frac"],
                            "max_block_steps": r["config"]["max_block_steps"],
-                           "dE_over_E_median": r["config"]["dE_over_E_median"]}
+                           "dE_over_E_median": r["config"]["dE_over_E_median"],
+                           "lanes": (r["config"]["lanes"] or {}).get("lanes", 1)}
     r = bench_adjoint(sub, emit=False)
     out["adjoint_n16384"] = {"ms_per_gradient": r["ms_per_step"], "interactions_per_s": r["value"]}
     return out

@@ -364,6 +364,17 @@ nb_status nb_ens_set_layout(nb_ens *ens, const int32_t *tiles_per_item, int32_t 
 nb_status nb_ens_set_local(nb_ens *ens, int64_t local_limit, int32_t local_steps,
                            int64_t local_work);
 
+/* Independent lanes: lane_of (HOST array of n_clusters values in [0, lanes); NULL allowed
+ * when lanes == 1) assigns every cluster to one of `lanes` groups (1 to 3, each non-empty;
+ * default 1).  nb_ens_run then advances each lane by global steps of its own clusters only, its
+ * graph replayed on a stream of its own (created by the library at the default priority), so a
+ * lane whose clusters need few block steps is not held to the step count of another, and one
+ * lane's kernels overlap another's.  The clusters are independent, so every result is bitwise
+ * the same for any assignment; work queued later on the ensemble's stream waits for all lanes.
+ * The assignment that pays is one that gives the clusters with the most block steps a lane of
+ * their own.  NB_EINVAL otherwise.  Synchronising. */
+nb_status nb_ens_set_lanes(nb_ens *ens, int32_t lanes, const int32_t *lane_of);
+
 /* Force work-item size (an autotuner knob): every block particle of a force item is shared by
  * at least smin lanes (a power of two in [1, 64]; default 8), each taking every smin-th j of a
  * tile, so an item holds at most 256 / smin block particles.  Smaller items balance a global

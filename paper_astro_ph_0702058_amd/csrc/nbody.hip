@@ -124,6 +124,10 @@ struct nb_ctx {
     std::string err;
 };
 
+// Most independent lanes of an ensemble: each runs on a stream of its own, and a process gets
+// four hardware queues, one of which the caller's stream keeps.
+constexpr int ENS_MAX_LANES = 3;
+
 struct nb_ens {
     int32_t C = 0, ntot = 0, lmin = 0, lmax = 0, prec = 0;
     int device = 0, num_cu = 256;
@@ -151,6 +155,17 @@ struct nb_ens {
     double g_eta = -1.0;
     int64_t g_tend = -1;
     int32_t g_steps = 0;
+    // independent lanes (nb_ens_set_lanes): lane l advances the clusters at places
+    // [lane_start_h[l], lane_start_h[l + 1]) of order_h by a graph of its own on a stream of its
+    // own, so its global steps follow only its clusters' block times
+    int32_t lanes = 1;
+    std::vector<int32_t> size_order_h, lane_start_h;
+    hipStream_t lane_stream[ENS_MAX_LANES] = {};
+    hipEvent_t lane_event[ENS_MAX_LANES] = {};
+    hipEvent_t lane_join = nullptr;
+    hipGraphExec_t lane_gexec[ENS_MAX_LANES] = {};
+    hipGraph_t lane_graph[ENS_MAX_LANES] = {};
+    EnsCluster *lane_host[ENS_MAX_LANES] = {};  // pinned copies of the cluster records
     std::string err;
 };
 
@@ -1243,9 +1258,14 @@ nb_status nb_sync(nb_ctx *c) {
 // ------------------------------------------------------------------------------------------
 namespace {
 
-EnsView ens_view(const nb_ens *e, int64_t t_end) {
+// lane < 0: every cluster; else the clusters of that lane (a slice of the order table)
+EnsView ens_view(const nb_ens *e, int64_t t_end, int lane = -1) {
     EnsView v;
     v.C = e->C; v.off = e->off; v.K = e->K; v.tpi = e->tpi; v.order = e->order;
+    if (lane >= 0) {
+        v.C = e->lane_start_h[lane + 1] - e->lane_start_h[lane];
+        v.order = e->order + e->lane_start_h[lane];
+    }
     v.part_off = e->part_off;
     v.prow = e->prow; v.eps2 = e->eps2; v.cl = e->cl; v.active = e->active;
     v.partial = e->partial; v.crit = e->crit; v.flags = e->flags;
@@ -1298,20 +1318,21 @@ void ens_launch_force(nb_ens *e, const EnsView &v, hipStream_t s) {
 
 // local = false: every block goes through ens_force (the start of a run)
 nb_status ens_enqueue_local(nb_ens *e, double eta, int32_t phase, int64_t t_end, hipStream_t s,
-                            bool local = true) {
-    EnsView v = ens_view(e, t_end);
+                            bool local = true, int lane = -1) {
+    EnsView v = ens_view(e, t_end, lane);
     if (!local) v.local_limit = 0;
     switch (e->prec) {
-        case NB_FP32: ens_local<ModeF32><<<e->C, WGL, 0, s>>>(v, ens_state(e), eta, phase); break;
-        case NB_DS: ens_local<ModeDS><<<e->C, WGL, 0, s>>>(v, ens_state(e), eta, phase); break;
-        default: ens_local<ModeF64><<<e->C, WGL, 0, s>>>(v, ens_state(e), eta, phase); break;
+        case NB_FP32: ens_local<ModeF32><<<v.C, WGL, 0, s>>>(v, ens_state(e), eta, phase); break;
+        case NB_DS: ens_local<ModeDS><<<v.C, WGL, 0, s>>>(v, ens_state(e), eta, phase); break;
+        default: ens_local<ModeF64><<<v.C, WGL, 0, s>>>(v, ens_state(e), eta, phase); break;
     }
     ELAUNCH_OK(e);
     return NB_OK;
 }
 
-nb_status ens_enqueue_force(nb_ens *e, int64_t t_end, hipStream_t s, bool local = true) {
-    EnsView v = ens_view(e, t_end);
+nb_status ens_enqueue_force(nb_ens *e, int64_t t_end, hipStream_t s, bool local = true,
+                            int lane = -1) {
+    EnsView v = ens_view(e, t_end, lane);
     if (!local) v.local_limit = 0;
     switch (e->prec) {
         case NB_FP32: ens_launch_force<ModeF32>(e, v, s); break;
@@ -1325,10 +1346,10 @@ nb_status ens_enqueue_force(nb_ens *e, int64_t t_end, hipStream_t s, bool local 
 // One global step: the force of every cluster's selected block that is not a local block,
 // then one workgroup per cluster corrects it, selects the next block and advances the cluster
 // by its local blocks.
-nb_status ens_enqueue_step(nb_ens *e, double eta, int64_t t_end, hipStream_t s) {
-    nb_status r = ens_enqueue_force(e, t_end, s);
+nb_status ens_enqueue_step(nb_ens *e, double eta, int64_t t_end, hipStream_t s, int lane = -1) {
+    nb_status r = ens_enqueue_force(e, t_end, s, true, lane);
     if (r != NB_OK) return r;
-    return ens_enqueue_local(e, eta, 2, t_end, s);
+    return ens_enqueue_local(e, eta, 2, t_end, s, true, lane);
 }
 
 nb_status ens_upload_tables(nb_ens *e) {
@@ -1343,6 +1364,12 @@ void ens_drop_graph(nb_ens *e) {
     if (e->graph) (void)hipGraphDestroy(e->graph);
     e->gexec = nullptr;
     e->graph = nullptr;
+    for (int l = 0; l < ENS_MAX_LANES; ++l) {
+        if (e->lane_gexec[l]) (void)hipGraphExecDestroy(e->lane_gexec[l]);
+        if (e->lane_graph[l]) (void)hipGraphDestroy(e->lane_graph[l]);
+        e->lane_gexec[l] = nullptr;
+        e->lane_graph[l] = nullptr;
+    }
     e->g_steps = 0;
 }
 
@@ -1380,6 +1407,9 @@ void ens_plan(nb_ens *e, int32_t n_clusters, const int32_t *offsets, int32_t pre
     std::stable_sort(e->order_h.begin(), e->order_h.end(), [&](int32_t a, int32_t b) {
         return offsets[a + 1] - offsets[a] > offsets[b + 1] - offsets[b];
     });
+    e->size_order_h = e->order_h;
+    e->lanes = 1;
+    e->lane_start_h = {0, n_clusters};
     e->unroll = 2;
     ens_derive(e);
 }
@@ -1414,6 +1444,96 @@ nb_status ens_flags(nb_ens *e) {
     if (f[0]) return fail(e, NB_ENONFINITE, "non-finite force or state on device");
     if (f[1]) return fail(e, NB_EDTMIN, "time step below 2^-%d requested (clamped)", e->lmax);
     return NB_OK;
+}
+
+// nb_ens_run with independent lanes: each lane replays its own graph of global steps on its own
+// stream, and the host checks a lane's clusters as soon as that lane's replay and the copy of
+// the cluster records behind it have finished, then relaunches it, so no lane waits for another.
+// The lanes start after the work already queued on the context's stream, which in turn waits
+// for all of them before any later call.
+nb_status ens_run_lanes(nb_ens *e, double eta, int64_t t_end, int32_t spl, int64_t max_steps,
+                        int32_t use_graph) {
+    const int L = e->lanes;
+    if (use_graph && (!e->lane_gexec[0] || e->g_eta != eta || e->g_tend != t_end ||
+                      e->g_steps != spl)) {
+        ens_drop_graph(e);
+        for (int l = 0; l < L; ++l) {
+            EHIP_OK(e, hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal));
+            nb_status rs = NB_OK;
+            for (int32_t i = 0; i < spl && rs == NB_OK; ++i)
+                rs = ens_enqueue_step(e, eta, t_end, e->cap_stream, l);
+            hipGraph_t g = nullptr;
+            hipError_t ec = hipStreamEndCapture(e->cap_stream, &g);
+            if (rs != NB_OK) { if (g) (void)hipGraphDestroy(g); return rs; }
+            if (ec != hipSuccess) return fail(e, NB_EDEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+            e->lane_graph[l] = g;
+            EHIP_OK(e, hipGraphInstantiate(&e->lane_gexec[l], g, nullptr, nullptr, 0));
+        }
+        e->g_eta = eta; e->g_tend = t_end; e->g_steps = spl;
+    }
+    EHIP_OK(e, hipEventRecord(e->lane_join, e->stream));
+    for (int l = 0; l < L; ++l) EHIP_OK(e, hipStreamWaitEvent(e->lane_stream[l], e->lane_join, 0));
+    int64_t done_steps[ENS_MAX_LANES] = {}, prev[ENS_MAX_LANES];
+    bool finished[ENS_MAX_LANES] = {};
+    for (int l = 0; l < L; ++l) prev[l] = -1;
+    auto launch = [&](int l) -> nb_status {
+        const hipStream_t s = e->lane_stream[l];
+        if (use_graph) {
+            EHIP_OK(e, hipGraphLaunch(e->lane_gexec[l], s));
+        } else {
+            for (int32_t i = 0; i < spl; ++i) {
+                const nb_status r = ens_enqueue_step(e, eta, t_end, s, l);
+                if (r != NB_OK) return r;
+            }
+        }
+        done_steps[l] += spl;
+        EHIP_OK(e, hipMemcpyAsync(e->lane_host[l], e->cl, e->C * sizeof(EnsCluster),
+                                  hipMemcpyDeviceToHost, s));
+        EHIP_OK(e, hipEventRecord(e->lane_event[l], s));
+        return NB_OK;
+    };
+    nb_status err = NB_OK;
+    for (int l = 0; l < L && err == NB_OK; ++l) err = launch(l);
+    int left = L;
+    while (err == NB_OK && left > 0) {
+        for (int l = 0; l < L && err == NB_OK; ++l) {
+            if (finished[l]) continue;
+            const hipError_t q = hipEventQuery(e->lane_event[l]);
+            if (q == hipErrorNotReady) continue;
+            if (q != hipSuccess) {
+                err = fail(e, NB_EDEVICE, "lane %d: %s", l, hipGetErrorString(q));
+                break;
+            }
+            bool all = true;
+            int64_t total = 0;
+            for (int32_t k = e->lane_start_h[l]; k < e->lane_start_h[l + 1]; ++k) {
+                const EnsCluster &x = e->lane_host[l][e->order_h[k]];
+                all = all && x.done;
+                total += x.n_steps;
+            }
+            if (all || (max_steps > 0 && done_steps[l] >= max_steps)) {
+                finished[l] = true;
+                --left;
+                continue;
+            }
+            // every global step advances every unfinished cluster by at least one block step
+            if (total == prev[l]) {
+                err = fail(e, NB_ESTATE, "ensemble lane %d made no progress over %d global steps", l, spl);
+                break;
+            }
+            prev[l] = total;
+            err = launch(l);
+        }
+    }
+    for (int l = 0; l < L; ++l) {  // later work on the context's stream follows every lane
+        (void)hipEventRecord(e->lane_event[l], e->lane_stream[l]);
+        (void)hipStreamWaitEvent(e->stream, e->lane_event[l], 0);
+    }
+    if (err != NB_OK) {
+        for (int l = 0; l < L; ++l) (void)hipStreamSynchronize(e->lane_stream[l]);
+        return err;
+    }
+    return ens_flags(e);
 }
 
 }  // namespace
@@ -1488,6 +1608,12 @@ nb_status nb_ens_destroy(nb_ens *e) {
     (void)hipDeviceSynchronize();
     ens_drop_graph(e);
     if (e->cap_stream) (void)hipStreamDestroy(e->cap_stream);
+    for (int l = 0; l < ENS_MAX_LANES; ++l) {
+        if (e->lane_stream[l]) (void)hipStreamDestroy(e->lane_stream[l]);
+        if (e->lane_event[l]) (void)hipEventDestroy(e->lane_event[l]);
+        if (e->lane_host[l]) (void)hipHostFree(e->lane_host[l]);
+    }
+    if (e->lane_join) (void)hipEventDestroy(e->lane_join);
     delete e;
     return NB_OK;
 }
@@ -1537,6 +1663,47 @@ nb_status nb_ens_set_split(nb_ens *e, int32_t smin) {
     return NB_OK;
 }
 
+nb_status nb_ens_set_lanes(nb_ens *e, int32_t lanes, const int32_t *lane_of) {
+    if (!e) return NB_EINVAL;
+    if (lanes < 1 || lanes > ENS_MAX_LANES)
+        return fail(e, NB_EINVAL, "nb_ens_set_lanes: lanes must lie in [1, %d]", ENS_MAX_LANES);
+    if (lanes > 1 && !lane_of) return fail(e, NB_EINVAL, "nb_ens_set_lanes: lane_of required");
+    std::vector<int32_t> count(lanes, 0);
+    for (int32_t c = 0; c < e->C; ++c) {
+        const int32_t l = lanes > 1 ? lane_of[c] : 0;
+        if (l < 0 || l >= lanes) return fail(e, NB_EINVAL, "nb_ens_set_lanes: cluster %d has lane %d", c, l);
+        ++count[l];
+    }
+    for (int32_t l = 0; l < lanes; ++l)
+        if (count[l] == 0) return fail(e, NB_EINVAL, "nb_ens_set_lanes: lane %d has no cluster", l);
+    EHIP_OK(e, hipSetDevice(e->device));
+    EHIP_OK(e, hipStreamSynchronize(e->stream));
+    for (int32_t l = 0; l < lanes && lanes > 1; ++l) {  // streams at the default priority
+        if (!e->lane_stream[l]) EHIP_OK(e, hipStreamCreateWithFlags(&e->lane_stream[l], hipStreamNonBlocking));
+        if (!e->lane_event[l]) EHIP_OK(e, hipEventCreateWithFlags(&e->lane_event[l], hipEventDisableTiming));
+        if (!e->lane_host[l])
+            EHIP_OK(e, hipHostMalloc((void **)&e->lane_host[l], (size_t)e->C * sizeof(EnsCluster), hipHostMallocDefault));
+    }
+    if (lanes > 1 && !e->lane_join) EHIP_OK(e, hipEventCreateWithFlags(&e->lane_join, hipEventDisableTiming));
+    // lane-major order table, each lane's clusters by decreasing size
+    std::vector<int32_t> order, start(lanes + 1, 0);
+    for (int32_t l = 0; l < lanes; ++l) {
+        start[l] = (int32_t)order.size();
+        for (int32_t c : e->size_order_h)
+            if (lanes == 1 || lane_of[c] == l) order.push_back(c);
+    }
+    start[lanes] = e->C;
+    e->order_h = order;
+    e->lane_start_h = start;
+    e->lanes = lanes;
+    ens_drop_graph(e);
+    if (e->scratch_ok) {
+        EHIP_OK(e, hipMemcpyAsync(e->order, e->order_h.data(), e->C * sizeof(int32_t), hipMemcpyHostToDevice, e->stream));
+        EHIP_OK(e, hipStreamSynchronize(e->stream));
+    }
+    return NB_OK;
+}
+
 nb_status nb_ens_set_local(nb_ens *e, int64_t local_limit, int32_t local_steps,
                            int64_t local_work) {
     if (!e) return NB_EINVAL;
@@ -1573,6 +1740,7 @@ nb_status nb_ens_run(nb_ens *e, double eta, int64_t t_end, int32_t steps_per_lau
     if (!e->initialised) return fail(e, NB_ESTATE, "nb_ens_run before nb_ens_init");
     if (!(eta > 0.0) || steps_per_launch < 1) return fail(e, NB_EINVAL, "bad arguments");
     EHIP_OK(e, hipSetDevice(e->device));
+    if (e->lanes > 1) return ens_run_lanes(e, eta, t_end, steps_per_launch, max_steps, use_graph);
     if (use_graph && (!e->gexec || e->g_eta != eta || e->g_tend != t_end ||
                       e->g_steps != steps_per_launch)) {
         ens_drop_graph(e);

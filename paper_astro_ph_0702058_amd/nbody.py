@@ -58,7 +58,7 @@ EXPORTS = ["nb_create", "nb_destroy", "nb_set_stream", "nb_bind", "nb_init",
            "nb_ens_last_error", "nb_shared_step", "nb_force_vjp", "nb_step_vjp",
            "nb_scratch_bytes", "nb_bind_scratch", "nb_ens_scratch_bytes", "nb_ens_bind_scratch",
            "nb_ens_set_local", "nb_fma_rate", "nb_force_noalloc",
-           "nb_set_resident", "nb_ens_set_split"]
+           "nb_set_resident", "nb_ens_set_split", "nb_ens_set_lanes"]
 
 _lib = None
 
@@ -113,6 +113,7 @@ def load_library(path: str = LIB_PATH):
         "nb_ens_bind_scratch": [P, P, ctypes.c_size_t],
         "nb_ens_set_local": [P, I64, I32, I64],
         "nb_ens_set_split": [P, I32],
+        "nb_ens_set_lanes": [P, I32, P],
         "nb_fma_rate": [P, ctypes.POINTER(D)],
         "nb_force_noalloc": [P, P, P, I32, P, P, P],
         "nb_set_resident": [P, I32],
@@ -556,6 +557,17 @@ class Ensemble:
     def nb_ens_set_split(self, smin):
         """Every block particle of a force item shared by at least smin lanes (power of 2)."""
         self._check(self.lib.nb_ens_set_split(self.h, int(smin)))
+
+    def nb_ens_set_lanes(self, lane_of=None):
+        """Independent lanes: lane_of[c] in [0, lanes) for every cluster (None: one lane)."""
+        if lane_of is None:
+            self._check(self.lib.nb_ens_set_lanes(self.h, 1, None))
+            return
+        lane_of = np.ascontiguousarray(lane_of, dtype=np.int32)
+        if lane_of.shape != (self.C,):
+            raise ValueError(f"lane_of: one lane per cluster ({self.C}) expected")
+        lanes = int(lane_of.max()) + 1 if lane_of.size else 1
+        self._check(self.lib.nb_ens_set_lanes(self.h, lanes, lane_of.ctypes.data_as(ctypes.c_void_p)))
 
     def nb_ens_init(self, eta):
         self._check(self.lib.nb_ens_init(self.h, float(eta)))

@@ -21,7 +21,7 @@ def build(sizes, seed0=100):
 
 
 def run_ensemble(sizes, eps, eta, t_end, prec, lmin=3, layout=None, graph=True, spl=8,
-                 local=None, split=None):
+                 local=None, split=None, lanes=None):
     xs, vs, ms = build(sizes)
     st = nbody.DeviceState(np.concatenate(xs), np.concatenate(vs), np.concatenate(ms))
     ens = nbody.Ensemble(sizes, eps, lmin=lmin, lmax=LMAX, precision=prec)
@@ -32,6 +32,8 @@ def run_ensemble(sizes, eps, eta, t_end, prec, lmin=3, layout=None, graph=True, 
         ens.nb_ens_set_local(**local)
     if split:
         ens.nb_ens_set_split(split)
+    if lanes is not None:
+        ens.nb_ens_set_lanes(lanes)
     ens.nb_ens_init(eta)
     e0 = ens.nb_ens_energy()
     ens.nb_ens_run(eta, t_end, steps_per_launch=spl, max_steps=200000, use_graph=graph)
@@ -108,6 +110,49 @@ def test_ensemble_layouts_agree():
     for g, steps in outs[1:]:
         assert steps == outs[0][1]
         assert np.max(np.abs(g["x"] - outs[0][0]["x"])) < 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("graph", [True, False])
+def test_ensemble_lanes_give_the_same_runs(prec, graph):
+    """Clusters split into independent lanes (each its own global steps, graph and stream) give
+    bitwise the same states, block steps and energies as one lane: the clusters are
+    independent.  Lanes of one, two and three groups of uneven size, replays of 8 global steps
+    (several per lane, the lanes finishing at different replays)."""
+    sizes = [70, 600, 1300, 90, 2100, 300, 64]
+    eps = [1.0 / n for n in sizes]
+    ref = run_ensemble(sizes, eps, 0.02, 1 / 16, prec, graph=graph)
+    for lane_of in ([1, 0, 0, 1, 0, 1, 1], [2, 0, 1, 2, 0, 2, 1]):
+        out = run_ensemble(sizes, eps, 0.02, 1 / 16, prec, graph=graph, lanes=lane_of)
+        g, ctl, e1 = out[3], out[4], out[6]
+        for key in ("x", "v", "a", "k", "tick", "level"):
+            assert np.array_equal(g[key], ref[3][key]), (lane_of, key)
+        assert [(c.n_steps, c.n_active_sum, c.t_cur) for c in ctl] == \
+               [(c.n_steps, c.n_active_sum, c.t_cur) for c in ref[4]]
+        assert np.array_equal(e1[0], ref[6][0]) and np.array_equal(e1[1], ref[6][1])
+
+
+def test_ensemble_lanes_are_checked():
+    """nb_ens_set_lanes refuses a lane outside [0, lanes), an empty lane and more than three."""
+    sizes = [70, 300, 90]
+    xs, vs, ms = build(sizes)
+    st = nbody.DeviceState(np.concatenate(xs), np.concatenate(vs), np.concatenate(ms))
+    ens = nbody.Ensemble(sizes, [1 / 70, 1 / 300, 1 / 90], lmin=3, lmax=LMAX, precision="fp32")
+    ens.nb_ens_bind(st)
+    ens.nb_ens_set_lanes([0, 1, 2])
+    ens.nb_ens_set_lanes(None)
+    for bad in ([0, 2, 2], [0, -1, 1], [0, 1, 3]):
+        with pytest.raises(RuntimeError, match="lane"):
+            ens.nb_ens_set_lanes(bad)
+    ens.close()
+    sizes = [64] * 5
+    xs, vs, ms = build(sizes)
+    st = nbody.DeviceState(np.concatenate(xs), np.concatenate(vs), np.concatenate(ms))
+    ens = nbody.Ensemble(sizes, 1 / 64, lmin=3, lmax=LMAX, precision="fp32")
+    ens.nb_ens_bind(st)
+    with pytest.raises(RuntimeError, match="lanes"):
+        ens.nb_ens_set_lanes([0, 1, 2, 3, 0])
+    ens.close()
 
 
 def test_ensemble_split_is_a_power_of_two():
