@@ -98,13 +98,13 @@ def bench_ensemble(args, emit=True):
         log(f"[bench] ensemble layout {layout}")
     lanes = None
     if args.ens_lanes == "probe":
-        # untimed, like the tuner: a run to t = 1/4 picks the 8 clusters with the most block
+        # untimed, like the tuner: a run to t = 1/4 picks the 4 clusters with the most block
         # steps for a lane of their own
         from paper_astro_ph_0702058_amd.tuning import ensemble_lanes
         t_p = time.perf_counter()
         lane = ensemble_lanes(ens, st, x0, v0, eta)
         lanes = {"lanes": int(lane.max()) + 1, "lane0_clusters": np.flatnonzero(lane == 0).tolist(),
-                 "assignment": "the 8 clusters with the most block steps in a probe run to "
+                 "assignment": "the 4 clusters with the most block steps in a probe run to "
                                "t = 1/4 (untimed) in lane 0, the rest in lane 1",
                  "probe_s": time.perf_counter() - t_p}
         log(f"[bench] ensemble lanes: {lanes}")

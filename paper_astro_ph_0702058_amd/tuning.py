@@ -120,13 +120,14 @@ def ensemble_autotune(ens, state, x0, v0, eta, t_probe=0.25, steps_per_launch=12
             "probe_seconds_default": t_default, "beats_default": bool(beats)}
 
 
-def ensemble_lanes(ens, state, x0, v0, eta, t_probe=0.25, top=8, steps_per_launch=128):
+def ensemble_lanes(ens, state, x0, v0, eta, t_probe=0.25, top=4, steps_per_launch=128):
     """Two independent lanes for an ensemble (nb_ens_set_lanes): a probe run to t_probe from the
     initial state (x0, v0) counts every cluster's block steps, and the `top` clusters with the
     most steps get a lane of their own, so the global step count of the rest no longer follows
     the cluster with the tightest encounters.  On MI355X, 512 Plummer clusters of 64-4096
-    particles to t = 1: 0.689 s against 0.763 s in one lane (the same split by the whole run's
-    counts: 0.685 s; three lanes, 8 / 56 / the rest: 0.85-0.88 s, one lane by size: 1.01 s).
+    particles to t = 1 (alternated on one machine): 0.657-0.658 s against 0.757-0.758 s in one
+    lane; 2 / 8 / 16 / 32 / 64 clusters apart 0.661 / 0.683 / 0.709 / 0.710 / 0.710 s; three
+    lanes (8 / 56 / the rest) 0.85-0.88 s; 8 apart by size 1.01 s.
     The probe leaves the ensemble re-initialised at (x0, v0).  Returns the lane of each cluster
     (numpy int32) after setting it."""
     import numpy as np
