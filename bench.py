@@ -557,7 +557,8 @@ def bench_adjoint(args, emit=True):
     xp_, vp_ = perturb(x0, v0, 1e-3, 6)
     soa = lambda a: torch.tensor(np.ascontiguousarray(np.asarray(a).T), dtype=torch.float64,
                                  device="cuda")
-    runner = SharedRunner(n, eps, dt, nsteps, checkpoint_every=ce, precision=prec)
+    runner = SharedRunner(n, eps, dt, nsteps, checkpoint_every=ce, precision=prec,
+                          overlap=args.adj_overlap == "on")
     with torch.no_grad():  # target: the perturbed run, on the same engine
         tx, _ = HermiteRun.apply(soa(xp_), soa(vp_), torch.tensor(m, device="cuda"), runner)
         target = tx.clone()
@@ -652,6 +653,9 @@ def main():
                     help="nb_set_resident for the run and timed workloads (default: the "
                          "library's; 0: always the launch chain)")
     ap.add_argument("--clusters", type=int, default=512)
+    ap.add_argument("--adj-overlap", default="on", choices=["on", "off"],
+                    help="adjoint: recompute the next checkpoint segment on a second stream "
+                         "while the current segment's step VJPs run (default on)")
     ap.add_argument("--ens-lanes", default="probe", choices=["probe", "one"],
                     help="ensemble: two independent lanes chosen by an untimed probe run "
                          "(default), or one lane")
