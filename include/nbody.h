@@ -18,7 +18,8 @@
  *     scheduler record, j-split partial sums, energy and adjoint scratch), bound with
  *     nb_bind_scratch(); an ensemble likewise (nb_ens_scratch_bytes(), nb_ens_bind_scratch()).
  *     The library owns only its host-side context, captured HIP graphs and one private
- *     capture stream per context.
+ *     capture stream per context (an ensemble split into lanes also the lanes' streams and
+ *     events and a pinned host copy of its cluster records per lane).
  *   - Per-particle vectors are structure-of-arrays: component c (0 = x, 1 = y, 2 = z) of
  *     particle i lives at [c * ld + i], where ld is the array's leading dimension (n for the
  *     particle state, the caller's n_i_max for force outputs).
@@ -222,7 +223,8 @@ nb_status nb_set_resident(nb_ctx *ctx, int32_t max_n);
 nb_status nb_energy(nb_ctx *ctx, double *ekin, double *epot);
 
 /* Copy the device scheduler record to the HOST struct *out (synchronising), and return the
- * latched device error, if any. */
+ * latched device error, if any (NB_ENONFINITE, NB_ESTATE, NB_EDTMIN; *out is filled in those
+ * cases too, its flags saying which). */
 nb_status nb_read_control(nb_ctx *ctx, nb_control *out);
 
 /* Force-kernel timing for measurement: with enable != 0, every force-kernel launch of this
