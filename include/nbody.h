@@ -223,8 +223,9 @@ nb_status nb_set_resident(nb_ctx *ctx, int32_t max_n);
 nb_status nb_energy(nb_ctx *ctx, double *ekin, double *epot);
 
 /* Copy the device scheduler record to the HOST struct *out (synchronising), and return the
- * latched device error, if any (NB_ENONFINITE, NB_ESTATE, NB_EDTMIN; *out is filled in those
- * cases too, its flags saying which). */
+ * latched device error, if any: NB_ENONFINITE, NB_ESTATE from the block selection or
+ * NB_EDTMIN, with *out filled in those cases too (its flags say which).  NB_ESTATE without a
+ * bound workspace leaves *out untouched. */
 nb_status nb_read_control(nb_ctx *ctx, nb_control *out);
 
 /* Force-kernel timing for measurement: with enable != 0, every force-kernel launch of this
