@@ -581,11 +581,12 @@ void ctx_plan(nb_ctx *c) {
     // work-item at a large target, whose plan would need more)
     int64_t rows = 0;
     for (int ipl = 1; ipl <= 2; ++ipl) {
-        // two i per work-item: sized for half the full target (the same partial rows)
+        // two i per work-item: sized for half the full target (the same partial rows); the
+        // scalar-load threshold does not change the plan
         rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->num_cu * FULL_ITEMS_PER_CU / ipl,
-                                                          FULL_KMAX}, smax_of(precision)));
+                                                          FULL_KMAX, 1}, smax_of(precision)));
         rows = std::max(rows, partial_rows_for(n, Variant{ipl, 1, c->num_cu * BLOCK_ITEMS_PER_CU,
-                                                          1 << 16}, smax_of(precision)));
+                                                          1 << 16, 1}, smax_of(precision)));
     }
     // the force VJP writes K * P rows of its plan even when K = 1
     {
