@@ -132,6 +132,31 @@ def test_ensemble_lanes_give_the_same_runs(prec, graph):
         assert np.array_equal(e1[0], ref[6][0]) and np.array_equal(e1[1], ref[6][1])
 
 
+def test_ensemble_lanes_stop_at_max_steps():
+    """A global step advances every unfinished cluster by one block step, in one lane or in
+    several, so a run stopped after the same number of global steps (max_steps 16 at 8 per
+    replay) leaves bitwise the same state in one lane and in two."""
+    sizes = [600, 90, 1300, 64]
+    eps = [1.0 / n for n in sizes]
+    outs = []
+    for lanes in (None, [0, 1, 1, 0]):
+        xs, vs, ms = build(sizes)
+        st = nbody.DeviceState(np.concatenate(xs), np.concatenate(vs), np.concatenate(ms))
+        ens = nbody.Ensemble(sizes, eps, lmin=3, lmax=LMAX, precision="fp64")
+        ens.nb_ens_bind(st)
+        if lanes is not None:
+            ens.nb_ens_set_lanes(lanes)
+        ens.nb_ens_init(0.02)
+        ens.nb_ens_run(0.02, 1.0, steps_per_launch=8, max_steps=16)
+        ctl = ens.nb_ens_control()
+        outs.append((st.numpy(), [(c.n_steps, c.t_cur) for c in ctl]))
+        ens.close()
+    assert all(n == 16 for n, _ in outs[0][1]), outs[0][1]
+    assert outs[1][1] == outs[0][1]
+    for key in ("x", "v", "a", "k", "tick", "level"):
+        assert np.array_equal(outs[1][0][key], outs[0][0][key]), key
+
+
 def test_ensemble_lanes_are_checked():
     """nb_ens_set_lanes refuses a lane outside [0, lanes), an empty lane and more than three."""
     sizes = [70, 300, 90]
